@@ -1,0 +1,136 @@
+"""Discrete Fourier calculus on the periodic voxel grid (oracle).
+
+Paper Sec. 3.1: fields are trigonometric polynomials on an nx*ny*nz grid; the
+equilibrium residual uses the compatibility projection G (eq. `GFourier`)
+built with Willot's rotated finite-difference frequencies, while the
+Helmholtz/Laplacian terms use the standard frequencies (eq.
+`LinearOpe_Helm`).
+
+Readings taken here (the paper leaves them open):
+* The projection is the orthogonal projection of a symmetric tensor onto the
+  symmetric compatible fields sym(n (x) u):
+      P(A) = (A n) (x) n + n (x) (A n) - (n . A n) n (x) n,
+  which has the same kernel as the paper's G on symmetric stresses
+  (both vanish iff A n = 0) and therefore gives the same Newton roots.
+* Rotated frequencies: the rotated difference at voxel corners has symbol
+  proportional to r_j = sin(q_j/2) prod_{m != j} cos(q_m/2); the common
+  complex factor cancels in P, so n = r/|r|, and P = 0 where r = 0
+  (q = 0 and modes with two or more Nyquist axes).  At an even axis' Nyquist
+  index cos(q/2) is taken as exactly 0.
+* Laplacian symbol -|q|^2 with q_j = 2 pi m_j / N_j and the Nyquist mode kept.
+Arrays are [z, y, x]; tensor index 0 <-> x, 1 <-> y, 2 <-> z.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+# Mandel ordering of symmetric tensors (inner product = Frobenius product).
+MANDEL3D = ((0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1))
+MANDEL2D = ((0, 0), (1, 1), (0, 1))
+
+
+def mandel_pairs(ncomp):
+    return MANDEL2D if ncomp == 3 else MANDEL3D
+
+
+def to_tensor(m):
+    """Mandel vector field (c, ...) -> symmetric tensor field (3, 3, ...)."""
+    c = m.shape[0]
+    t = np.zeros((3, 3) + m.shape[1:], dtype=m.dtype)
+    for k, (i, j) in enumerate(mandel_pairs(c)):
+        if i == j:
+            t[i, i] = m[k]
+        else:
+            t[i, j] = m[k] / np.sqrt(2.0)
+            t[j, i] = m[k] / np.sqrt(2.0)
+    return t
+
+
+def to_mandel(t, ncomp):
+    """Symmetric tensor field (3, 3, ...) -> Mandel vector field (c, ...)."""
+    out = np.zeros((ncomp,) + t.shape[2:], dtype=t.dtype)
+    for k, (i, j) in enumerate(mandel_pairs(ncomp)):
+        out[k] = t[i, i] if i == j else np.sqrt(2.0) * 0.5 * (t[i, j] + t[j, i])
+    return out
+
+
+def standard_frequencies(shape):
+    """q = (qx, qy, qz) broadcast to `shape`, q_j = 2 pi m_j / N_j, m_j in the
+    usual FFT order (Nyquist index of an even axis reads m = -N/2)."""
+    nz, ny, nx = shape
+    qz = 2.0 * np.pi * np.fft.fftfreq(nz)[:, None, None]
+    qy = 2.0 * np.pi * np.fft.fftfreq(ny)[None, :, None]
+    qx = 2.0 * np.pi * np.fft.fftfreq(nx)[None, None, :]
+    return [np.broadcast_to(q, shape) for q in (qx, qy, qz)]
+
+
+def laplacian_symbol(shape):
+    qx, qy, qz = standard_frequencies(shape)
+    return -(qx * qx + qy * qy + qz * qz)
+
+
+def _half_angle(n):
+    m = np.fft.fftfreq(n) * n            # signed integer frequencies
+    half = np.pi * m / n                 # q/2
+    s = np.sin(half)
+    c = np.cos(half)
+    if n % 2 == 0:
+        c[n // 2] = 0.0                  # Nyquist: cos(-pi/2) is exactly zero
+    return s, c
+
+
+def rotated_direction(shape):
+    """Unit vectors n = r/|r| of the rotated scheme and the mask of r == 0."""
+    nz, ny, nx = shape
+    sx, cx = _half_angle(nx)
+    sy, cy = _half_angle(ny)
+    sz, cz = _half_angle(nz)
+    sx, cx = sx[None, None, :], cx[None, None, :]
+    sy, cy = sy[None, :, None], cy[None, :, None]
+    sz, cz = sz[:, None, None], cz[:, None, None]
+    rx = np.broadcast_to(sx * cy * cz, shape)
+    ry = np.broadcast_to(cx * sy * cz, shape)
+    rz = np.broadcast_to(cx * cy * sz, shape)
+    r2 = rx * rx + ry * ry + rz * rz
+    zero = r2 == 0.0
+    inv = np.where(zero, 0.0, 1.0 / np.sqrt(np.where(zero, 1.0, r2)))
+    n = np.stack([rx * inv, ry * inv, rz * inv])
+    return n, zero
+
+
+def project_hat(A_hat, n, zero):
+    """P(A) = (A n) (x) n + n (x) (A n) - (n . A n) n (x) n, zero where r = 0."""
+    An = np.einsum("ij...,j...->i...", A_hat, n)
+    nAn = np.einsum("i...,i...->...", n, An)
+    out = (np.einsum("i...,j...->ij...", An, n)
+           + np.einsum("i...,j...->ij...", n, An)
+           - nAn * np.einsum("i...,j...->ij...", n, n))
+    out[:, :, zero] = 0.0
+    return out
+
+
+def fftn(a):
+    return np.fft.fftn(a, axes=(-3, -2, -1))
+
+
+def ifftn(a):
+    return np.fft.ifftn(a, axes=(-3, -2, -1))
+
+
+def G_tensor(A):
+    """Projection of a real symmetric tensor field A (3, 3, nz, ny, nx)."""
+    shape = A.shape[2:]
+    n, zero = rotated_direction(shape)
+    out = project_hat(fftn(A), n, zero)
+    return ifftn(out).real
+
+
+def G_mandel(m):
+    """Projection acting on a Mandel field (c, nz, ny, nx)."""
+    return to_mandel(G_tensor(to_tensor(m)), m.shape[0])
+
+
+def laplacian(phi):
+    """Spectral Laplacian with standard frequencies, Nyquist kept."""
+    return ifftn(laplacian_symbol(phi.shape) * fftn(phi)).real

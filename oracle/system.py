@@ -1,0 +1,114 @@
+"""Residual and tangent action of the crack-length-controlled system (oracle).
+
+Paper Sec. 3.2: unknowns q = (eps_tilde, phi, E) with macroscopic strain
+E_M = f E (Sec. 2.3, eq. `SystemDis`); residual eq. `System_CrackLength`,
+crack functional eq. `CrackLenght` evaluated spectrally (eq.
+`newGammaFourier`), tangent action eq. `CrackLength_linearization` with the
+history derivative of eq. `Delta_history`.
+
+Readings (the paper is silent, garbled or inconsistent):
+* Signs: the Fourier symbol xi stands for the derivative i q, so the
+  Helmholtz operator is (Gc/l + 2H) phi - Gc l Lap(phi) (SPD), consistent
+  with the derivative of the crack density (eq. `gamFunct`).
+* Gc(x) multiplies the Laplacian pointwise, as printed.
+* Length control: F3 = Gamma - a (the paper's dissipation form with one
+  homogeneous Gc only rescales it); its exact derivative is
+  r = phi/l - l Lap(phi).
+* Gamma = sum_x [phi^2/(2l) - (l/2) phi Lap(phi)] (discrete Parseval form of
+  eq. `CrackLenght`, Nyquist energy kept), so that r is its exact gradient.
+* An initial crack is a Dirichlet mask m (phi = 1 there): the phase-field
+  rows of masked voxels become the identity and their increments are
+  excluded from all couplings.
+* H = max(psi0(+)(eps), Hn) with Hn the last converged history.
+Fields: Mandel strain (c, nz, ny, nx), c = 3 in 2D plane strain, 6 in 3D.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from . import fourier as fo
+from . import pointlaw as pl
+
+
+class System:
+    """Fixed data of one RVE problem (grid, phases, mask, l, k, f)."""
+
+    def __init__(self, prob):
+        self.prob = prob
+        self.shape = tuple(prob.shape)
+        self.ncomp = 3 if self.shape[0] == 1 else 6
+        self.N = int(np.prod(self.shape))
+        pid = np.asarray(prob.phase_id, dtype=np.int64).reshape(self.shape)
+        E = np.array([p[0] for p in prob.phases], dtype=np.float64)[pid]
+        nu = np.array([p[1] for p in prob.phases], dtype=np.float64)[pid]
+        self.Gc = np.array([p[2] for p in prob.phases], dtype=np.float64)[pid]
+        self.lam, self.mu = pl.lame(E, nu)
+        self.m = (np.zeros(self.shape) if prob.mask is None
+                  else np.asarray(prob.mask, dtype=np.float64).reshape(self.shape))
+        self.l = float(prob.l)
+        self.k = float(prob.k)
+        self.f = fo.to_mandel(np.asarray(prob.f, dtype=np.float64)[:, :, None, None, None],
+                              self.ncomp)[:, 0, 0, 0]
+
+    # -- helpers -----------------------------------------------------------
+    def fE(self, E):
+        return self.f.reshape((self.ncomp, 1, 1, 1)) * E
+
+    def point(self, eps, phi, Hn):
+        return pl.evaluate(fo.to_tensor(eps), phi, Hn, self.lam, self.mu, self.k)
+
+    def gamma(self, phi):
+        """Crack length/area Gamma(phi) (eq. `CrackLenght`, spectral form)."""
+        l = self.l
+        return float(np.sum(phi * phi / (2.0 * l) - 0.5 * l * phi * fo.laplacian(phi)))
+
+    # -- residual (eq. System_CrackLength) ---------------------------------
+    def residual(self, eps_t, phi, E, Hn, a):
+        eps = eps_t + self.fE(E)
+        st = self.point(eps, phi, Hn)
+        F1 = fo.to_mandel(fo.G_tensor(st["sigma"]), self.ncomp)
+        lap = fo.laplacian(phi)
+        l, Gc, H = self.l, self.Gc, st["H"]
+        F2 = (1.0 - self.m) * ((Gc / l + 2.0 * H) * phi - Gc * l * lap - 2.0 * H)
+        gam = float(np.sum(phi * phi / (2.0 * l) - 0.5 * l * phi * lap))
+        F3 = gam - a
+        sig_mean = st["sigma"].reshape(3, 3, -1).mean(axis=-1)
+        return dict(F1=F1, F2=F2, F3=F3, Gamma=gam, sigma_M=sig_mean, state=st,
+                    r=phi / l - l * lap)
+
+    # -- tangent action (eq. CrackLength_linearization) --------------------
+    def tangent(self, eps_t, phi, E, Hn):
+        """Return a function v -> J v on flat vectors [d_eps_t, d_phi, dE]."""
+        eps = eps_t + self.fE(E)
+        st = self.point(eps, phi, Hn)
+        l, Gc, m = self.l, self.Gc, self.m
+        b = -2.0 * (1.0 - phi) * st["sigma0p"]          # d sigma / d phi
+        A = Gc / l + 2.0 * st["H"]
+        r = phi / l - l * fo.laplacian(phi)
+        c, shp = self.ncomp, self.shape
+
+        def apply(v):
+            d_eps = v[: c * self.N].reshape((c,) + shp)
+            d_phi = v[c * self.N: (c + 1) * self.N].reshape(shp)
+            dE = v[-1]
+            w = fo.to_tensor(d_eps + self.fE(dE))
+            dphi_f = (1.0 - m) * d_phi
+            tau = pl.tangent_apply(st, w) + b * dphi_f
+            J1 = fo.to_mandel(fo.G_tensor(tau), c)
+            bw = np.einsum("ij...,ij...->...", b, w)
+            J2 = (1.0 - m) * (st["chi"] * bw + A * dphi_f
+                              - Gc * l * fo.laplacian(dphi_f)) + m * d_phi
+            J3 = np.sum(r * dphi_f)
+            return np.concatenate([J1.ravel(), J2.ravel(), [J3]])
+
+        return apply
+
+    # -- flat-vector packing ----------------------------------------------
+    def pack(self, F1, F2, F3):
+        return np.concatenate([np.ravel(F1), np.ravel(F2), [F3]])
+
+    def unpack(self, x):
+        c, N = self.ncomp, self.N
+        return (x[: c * N].reshape((c,) + self.shape),
+                x[c * N: (c + 1) * N].reshape(self.shape), float(x[-1]))

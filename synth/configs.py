@@ -1,0 +1,136 @@
+"""Problem definitions of the benchmark workloads and of small parity cases.
+
+A problem is the paper's statement of the RVE problem (Sec. 2.3 and Sec. 3.2):
+a periodic voxel grid with a phase per voxel, per-phase Young modulus,
+Poisson ratio and toughness Gc (as in Table 2), the length scale l, the
+loading-direction tensor f (Table 1), the crack-length increment per step and
+the solver controls.  The values themselves are synthetic stand-ins for the
+paper's figure-only geometries (the fibre composite, porous and 3D cases of
+Sec. 5); voxel units throughout (h = 1).
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+from .microstructure import (
+    disks_rsa,
+    line_crack_mask,
+    penny_crack_mask,
+    spheres_random,
+)
+
+
+def _dyad(a, b):
+    t = np.zeros((3, 3))
+    t[a, b] += 0.5
+    t[b, a] += 0.5
+    return t
+
+
+@dataclass
+class Problem:
+    name: str
+    shape: Tuple[int, int, int]          # (nz, ny, nx); nz == 1 means 2D plane strain
+    phases: List[Tuple[float, float, float]]  # (E, nu, Gc) per phase id
+    phase_id: np.ndarray                 # uint8, shape `shape`
+    mask: Optional[np.ndarray]           # uint8 crack mask (phi == 1 there) or None
+    f: np.ndarray                        # 3x3 symmetric loading direction
+    l: float = 2.0
+    k: float = 1e-6
+    delta_a: float = 1.0
+    n_increments: int = 10
+    alpha: float = 1.0
+    newton_tol: float = 1e-8
+    newton_maxit: int = 50
+    krylov_rtol: float = 1e-10
+    krylov_maxit: int = 5000
+    precision: str = "fp64"              # "fp64" or "mixed"
+    notes: str = ""
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def dim(self) -> int:
+        return 2 if self.shape[0] == 1 else 3
+
+    @property
+    def nvox(self) -> int:
+        return int(np.prod(self.shape))
+
+
+CONFIG_NAMES = ("cfg0_64sq", "cfg1_256sq_fibres", "cfg2_64cube_pores",
+                "cfg3_128cube_particles")
+
+
+def problem_config(name: str) -> Problem:
+    """Return the seeded problem called `name` (benchmark or parity case)."""
+    if name == "cfg0_64sq":
+        n = 64
+        return Problem(
+            name=name, shape=(1, n, n), phases=[(1.0, 0.3, 1e-3)],
+            phase_id=np.zeros((1, n, n), np.uint8),
+            mask=line_crack_mask(n, n, 32, 24, 40), f=_dyad(1, 1), l=2.0,
+            delta_a=1.0, n_increments=30, alpha=1.0, newton_tol=1e-8,
+            notes="homogeneous 64^2, centred 16-voxel crack, uniaxial yy")
+    if name == "cfg1_256sq_fibres":
+        n = 256
+        pid, _ = disks_rsa(n, n, radius=8, min_gap=2, target_fraction=0.30, seed=2)
+        return Problem(
+            name=name, shape=(1, n, n),
+            phases=[(1.0, 0.35, 1e-3), (10.0, 0.2, 1e-2)], phase_id=pid, mask=None,
+            f=_dyad(1, 1), l=2.0, delta_a=2.0, n_increments=100, alpha=1.0,
+            notes="256^2 fibre composite, 30% RSA disks r=8 gap 2, transverse tension")
+    if name == "cfg2_64cube_pores":
+        n = 64
+        pid, _ = spheres_random(n, 3.0, 6.0, 0.15, seed=3, gap=1.0)
+        return Problem(
+            name=name, shape=(n, n, n),
+            phases=[(1.0, 0.3, 1e-3), (1e-6, 0.3, 1e-3)], phase_id=pid, mask=None,
+            f=_dyad(2, 2), l=1.5, delta_a=4.0, n_increments=60, alpha=0.9,
+            precision="mixed", notes="64^3 porous, 15% spherical pores r~U[3,6]")
+    if name == "cfg3_128cube_particles":
+        n = 128
+        pid, _ = spheres_random(n, 6.0, 6.0, 0.25, seed=4, gap=1.0, fixed_radius=6.0)
+        f = _dyad(2, 2) + 0.3 * (2.0 * _dyad(0, 2))
+        return Problem(
+            name=name, shape=(n, n, n),
+            phases=[(1.0, 0.3, 1e-3), (8.0, 0.2, 5e-3)], phase_id=pid,
+            mask=penny_crack_mask(n, 64, 64, 64, 10), f=f, l=2.0, delta_a=8.0,
+            n_increments=80, alpha=0.9, precision="mixed",
+            notes="128^3 particle composite 25%, penny crack R=10, eps_zz:eps_xz=1:0.3")
+    # ---- small parity cases ------------------------------------------------
+    if name == "tiny16":
+        n = 16
+        return Problem(
+            name=name, shape=(1, n, n), phases=[(1.0, 0.3, 1e-3)],
+            phase_id=np.zeros((1, n, n), np.uint8),
+            mask=line_crack_mask(n, n, 8, 6, 10), f=_dyad(1, 1), l=1.5,
+            delta_a=0.5, n_increments=4)
+    if name == "fib64":
+        n = 64
+        pid, _ = disks_rsa(n, n, radius=5, min_gap=2, target_fraction=0.25, seed=11)
+        return Problem(
+            name=name, shape=(1, n, n),
+            phases=[(1.0, 0.35, 1e-3), (10.0, 0.2, 1e-2)], phase_id=pid,
+            mask=line_crack_mask(n, n, 32, 28, 36), f=_dyad(1, 1), l=2.0,
+            delta_a=1.0, n_increments=5)
+    if name == "pore24":
+        n = 24
+        pid, _ = spheres_random(n, 2.5, 4.0, 0.12, seed=12, gap=1.0)
+        return Problem(
+            name=name, shape=(n, n, n),
+            phases=[(1.0, 0.3, 1e-3), (1e-6, 0.3, 1e-3)], phase_id=pid, mask=None,
+            f=_dyad(2, 2), l=1.5, delta_a=2.0, n_increments=3, alpha=0.9)
+    if name == "part24":
+        n = 24
+        pid, _ = spheres_random(n, 3.0, 3.0, 0.15, seed=13, gap=1.0, fixed_radius=3.0)
+        f = _dyad(2, 2) + 0.3 * (2.0 * _dyad(0, 2))
+        return Problem(
+            name=name, shape=(n, n, n),
+            phases=[(1.0, 0.3, 1e-3), (8.0, 0.2, 5e-3)], phase_id=pid,
+            mask=penny_crack_mask(n, 12, 12, 12, 3), f=f, l=2.0, delta_a=2.0,
+            n_increments=3, alpha=0.9)
+    raise KeyError(name)
