@@ -1,0 +1,171 @@
+/*
+ * pff.h -- C ABI of the MI355X crack-length-controlled phase-field FFT solver.
+ *
+ * Method: Aranda & Segurado, "A crack-length control technique for phase
+ * field fracture in FFT homogenization".  A periodic voxel RVE (Sec. 3.1)
+ * with per-phase stiffness and toughness (Table 2) is loaded along a fixed
+ * strain direction f (E_M = f E, Sec. 2.3, Table 1); every step prescribes
+ * the next crack length a += delta_a (Sec. 2.3, linear ramp) and solves the
+ * monolithic system F(eps_tilde, phi, E) = 0 of Sec. 3.2 (eq.
+ * System_CrackLength) by Newton (Algorithm 2) with BiCGSTAB on the
+ * matrix-free bordered tangent (eq. CrackLength_linearization).
+ *
+ * Conventions
+ *  - Voxel index i = x + nx*(y + ny*z); nz == 1 means 2D plane strain.
+ *  - C = 3 strain components in 2D (Mandel [11, 22, sqrt2*12]), 6 in 3D
+ *    (Mandel [11, 22, 33, sqrt2*23, sqrt2*13, sqrt2*12]).
+ *  - Fields are structure-of-arrays, component-major: component k of voxel
+ *    i at [k*N + i].
+ *  - Krylov vectors ("v", "Jv") hold (C+1)*N + 1 entries
+ *    [d eps_tilde | d phi | dE] in the solver's working precision: double
+ *    for PFF_PREC_FP64, float for PFF_PREC_MIXED.
+ *  - Units are voxels (h = 1).
+ *  - All entry points return a pff_status: 0 = success, > 0 a solver
+ *    outcome, < 0 an error whose text pff_last_error() returns.  No C++
+ *    exception crosses the ABI.  A failed call leaves the handle usable.
+ *  - Host buffers passed in are copied; the caller keeps ownership.  Device
+ *    buffers passed in ("*_dev") belong to the caller, must be device
+ *    memory of the current HIP device and must not alias each other.  All
+ *    device work is queued on the stream given at creation.  Entry points
+ *    returning host data synchronise that stream.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef PFF_H
+#define PFF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PFF_ABI_VERSION 1
+
+typedef int pff_status;
+enum {
+  PFF_OK = 0,
+  PFF_NOT_CONVERGED = 1,   /* Newton or Krylov limit reached; state rolled back */
+  PFF_ERR_ARG = -1,        /* invalid argument (NULL, size, range) */
+  PFF_ERR_OOM = -2,        /* device allocation failed */
+  PFF_ERR_DEVICE = -3,     /* HIP runtime error */
+  PFF_ERR_STATE = -4       /* call out of order (e.g. step before bootstrap) */
+};
+
+enum { PFF_PREC_FP64 = 0, PFF_PREC_MIXED = 1 };
+
+typedef struct pff_solver pff_solver;
+
+/* Voxel grid. nx, ny >= 2 and nz >= 1; each size a product of 2s and 3s,
+ * at most 512 (x) / 512 (y, z). */
+typedef struct {
+  int nx, ny, nz;
+} pff_grid;
+
+/* One material phase (Table 2): Young modulus, Poisson ratio, toughness Gc. */
+typedef struct {
+  double E, nu, Gc;
+} pff_phase;
+
+/* Problem and solver controls.
+ *  l            phase-field length scale (voxels), eq. CrackLenght
+ *  k_resid      residual stiffness k of g(phi) = (1-phi)^2 + k (eq. gFunct)
+ *  f[9]         loading-direction tensor f, 3x3 row-major, symmetric
+ *  delta_a      crack-length increment per step (Sec. 2.3 ramp)
+ *  alpha        Newton relaxation (Algorithm 2), 0 < alpha <= 1
+ *  newton_tol   tolerance of the error measure of eq. errors_crack
+ *  krylov_rtol  BiCGSTAB stop ||r|| <= rtol ||b||
+ *  precision    PFF_PREC_FP64 or PFF_PREC_MIXED (FP32 tangent/FFT/Krylov
+ *               vectors, FP64 residual, inner products, constraint and
+ *               load-factor update) */
+typedef struct {
+  double l, k_resid, f[9], delta_a, alpha, newton_tol, krylov_rtol;
+  int newton_maxit, krylov_maxit, precision;
+} pff_params;
+
+/* Per-increment outputs (Algorithm 2): macroscopic stress Sigma_M = <sigma>
+ * as tensor components [11, 22, 33, 23, 13, 12] (sigma_33 of plane strain
+ * included), load factor E, crack length Gamma(phi) and its target a, the
+ * three error measures of the last Newton iteration and counters. */
+typedef struct {
+  int increment, newton_iters, krylov_iters, converged;
+  long long applies;
+  double sigma_M[6];
+  double load_factor, crack_length, target_a;
+  double err[3];
+  double seconds;
+} pff_increment_result;
+
+int pff_abi_version(void);
+
+/* Create a solver.  phase_id: N bytes (host) with values < n_phases;
+ * crack_mask: N bytes (host, 1 = initial crack, phi = 1 there) or NULL;
+ * hip_stream: a hipStream_t or NULL for the default stream.
+ * Errors: PFF_ERR_ARG, PFF_ERR_OOM, PFF_ERR_DEVICE (*out is NULL then). */
+pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phases,
+                      const uint8_t* phase_id, const uint8_t* crack_mask,
+                      const pff_params* params, void* hip_stream, pff_solver** out);
+
+/* Bootstrap (paper silent; see the design notes): damage-free Helmholtz
+ * solution phi0 with phi = 1 on the crack mask, a0 = Gamma(phi0), and the
+ * homogeneous-solution predictor E_s for the first increment.
+ * Outputs (host, may be NULL): a0, E_s. */
+pff_status pff_bootstrap(pff_solver* s, double* a0, double* E_s);
+
+/* One crack-length increment (Algorithm 2).  On PFF_NOT_CONVERGED the state
+ * is rolled back to the last converged increment. */
+pff_status pff_step(pff_solver* s, pff_increment_result* out);
+
+/* Copy the committed state to host buffers (any may be NULL):
+ * eps_total C*N, phi N, Hn N (history), and scalars E, a. */
+pff_status pff_get_state(pff_solver* s, double* eps_total, double* phi, double* Hn,
+                         double* E, double* a);
+
+/* Overwrite the committed state from host buffers (all required):
+ * eps_tilde C*N (compatible fluctuation), phi N, Hn N, E, a.  Marks the
+ * solver bootstrapped with n increments done. */
+pff_status pff_set_state(pff_solver* s, const double* eps_tilde, const double* phi,
+                         const double* Hn, double E, double a, int n);
+
+/* Hot path, step (a1)+(a8): constitutive update at the current state and
+ * the FP64 residual F = (F1, F2, F3) for target crack length `a`
+ * (eq. System_CrackLength); F_dev receives (C+1)*N+1 doubles or may be
+ * NULL.  Host outputs (may be NULL): gamma = Gamma(phi), sigma_M[6]. */
+pff_status pff_residual(pff_solver* s, double a, double* F_dev, double* gamma,
+                        double* sigma_M);
+
+/* Hot path, steps (a2)-(a6): Jv = dF(q; v) at the state of the last
+ * pff_residual call (eq. CrackLength_linearization). v_dev, Jv_dev: Krylov
+ * vectors in working precision. */
+pff_status pff_apply_tangent(pff_solver* s, const void* v_dev, void* Jv_dev);
+
+/* Steps (a3)-(a5) alone: out = [G(in_1..C) | Lap(in_{C+1})] on C+1 fields
+ * of N values (eq. GFourier with rotated frequencies, eq. LinearOpe_Helm).
+ * prec selects double (0) or float (1) buffers. */
+pff_status pff_project(pff_solver* s, const void* in_dev, void* out_dev, int prec);
+
+/* Step (a7): BiCGSTAB on the tangent at the last residual state,
+ * x = J^{-1} b.  b_dev, x_dev: Krylov vectors in working precision.
+ * Outputs (may be NULL): iterations, relative residual of the returned
+ * iterate.  Returns PFF_NOT_CONVERGED if rtol was not reached. */
+pff_status pff_krylov_solve(pff_solver* s, const void* b_dev, void* x_dev, double rtol,
+                            int maxit, int* iters, double* relres);
+
+/* Counters since creation: tangent applies, Krylov iterations. */
+pff_status pff_counters(pff_solver* s, long long* applies, long long* krylov_iters);
+
+/* Serialised committed state (checkpoint/resume).  pff_save with
+ * buf == NULL returns the size in *bytes. */
+pff_status pff_save(pff_solver* s, void* buf, size_t* bytes);
+pff_status pff_load(pff_solver* s, const void* buf, size_t bytes);
+
+/* Text of the last error on this handle ("" if none). */
+const char* pff_last_error(const pff_solver* s);
+
+void pff_destroy(pff_solver* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFF_H */

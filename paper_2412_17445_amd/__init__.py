@@ -1,0 +1,10 @@
+"""MI355X-native crack-length-controlled phase-field FFT solver.
+
+The compute path is the HIP library libpff.so (C ABI in include/pff.h);
+this package only builds it and marshals arguments to it.
+"""
+
+from ._lib import load as load_library  # noqa: F401
+from .solver import PffError, Solver  # noqa: F401
+
+__all__ = ["Solver", "PffError", "load_library"]

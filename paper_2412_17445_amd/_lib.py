@@ -1,0 +1,82 @@
+"""ctypes binding of libpff.so (argument marshalling only).
+
+Every function keeps the C name and signature of include/pff.h.  Loading
+fails loudly when the library has not been built: there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpff.so")
+
+PFF_OK, PFF_NOT_CONVERGED = 0, 1
+PFF_ERR_ARG, PFF_ERR_OOM, PFF_ERR_DEVICE, PFF_ERR_STATE = -1, -2, -3, -4
+PFF_PREC_FP64, PFF_PREC_MIXED = 0, 1
+
+
+class pff_grid(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int)]
+
+
+class pff_phase(C.Structure):
+    _fields_ = [("E", C.c_double), ("nu", C.c_double), ("Gc", C.c_double)]
+
+
+class pff_params(C.Structure):
+    _fields_ = [("l", C.c_double), ("k_resid", C.c_double), ("f", C.c_double * 9),
+                ("delta_a", C.c_double), ("alpha", C.c_double), ("newton_tol", C.c_double),
+                ("krylov_rtol", C.c_double), ("newton_maxit", C.c_int),
+                ("krylov_maxit", C.c_int), ("precision", C.c_int)]
+
+
+class pff_increment_result(C.Structure):
+    _fields_ = [("increment", C.c_int), ("newton_iters", C.c_int), ("krylov_iters", C.c_int),
+                ("converged", C.c_int), ("applies", C.c_longlong), ("sigma_M", C.c_double * 6),
+                ("load_factor", C.c_double), ("crack_length", C.c_double),
+                ("target_a", C.c_double), ("err", C.c_double * 3), ("seconds", C.c_double)]
+
+
+EXPORTS = {
+    "pff_abi_version": (C.c_int, []),
+    "pff_create": (C.c_int, [C.POINTER(pff_grid), C.POINTER(pff_phase), C.c_int, C.c_void_p,
+                             C.c_void_p, C.POINTER(pff_params), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "pff_bootstrap": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "pff_step": (C.c_int, [C.c_void_p, C.POINTER(pff_increment_result)]),
+    "pff_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "pff_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                C.c_double, C.c_int]),
+    "pff_residual": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.POINTER(C.c_double),
+                               C.c_void_p]),
+    "pff_apply_tangent": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pff_project": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "pff_krylov_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
+                                   C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "pff_counters": (C.c_int, [C.c_void_p, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
+    "pff_save": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)]),
+    "pff_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "pff_last_error": (C.c_char_p, [C.c_void_p]),
+    "pff_destroy": (None, [C.c_void_p]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libpff.so and bind every exported function (raises if missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() or "
+                           "python -m paper_2412_17445_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

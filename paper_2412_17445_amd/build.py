@@ -1,0 +1,46 @@
+"""Build the HIP shared library libpff.so for gfx950 (in-tree)."""
+
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB = os.path.join(HERE, "libpff.so")
+SOURCES = [os.path.join(HERE, "csrc", "pff.hip")]
+HEADERS = [os.path.join(HERE, "csrc", f) for f in
+           ("common.hpp", "fft.hpp", "pointlaw.hpp", "passes.hpp", "pipes.hpp", "krylov.hpp")]
+HEADERS.append(os.path.join(ROOT, "include", "pff.h"))
+
+
+def hipcc():
+    for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def command(out=LIB, arch="gfx950", extra=()):
+    return [hipcc(), "-O3", "-std=c++17", f"--offload-arch={arch}", "-fPIC", "-shared",
+            # packed FP32 instructions are kept out of the device code
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-I", os.path.join(ROOT, "include"), "-o", out, *SOURCES, *extra]
+
+
+def build(verbose=False):
+    """Compile libpff.so (always recompiles; writes atomically)."""
+    tmp = LIB + ".tmp"
+    cmd = command(out=tmp)
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    proc = subprocess.run(cmd, capture_output=True, text=True)
+    if proc.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + proc.stdout + proc.stderr)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

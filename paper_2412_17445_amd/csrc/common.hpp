@@ -1,0 +1,77 @@
+// Common device types and helpers for the phase-field FFT solver kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pff {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts of 64)
+constexpr int kMaxPhases = 16;
+constexpr int kMaxRed = 12;          // reduction slots per pass
+constexpr int kMaxStages = 10;
+
+template <typename T> struct cpx { T x, y; };
+
+template <typename T> __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T> __device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) {
+  return {a.x + b.x, a.y + b.y};
+}
+template <typename T> __device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) {
+  return {a.x - b.x, a.y - b.y};
+}
+template <typename T> __device__ __forceinline__ cpx<T> cconj(cpx<T> a) { return {a.x, -a.y}; }
+// multiply by s*i (s = +1 or -1)
+template <typename T, int S> __device__ __forceinline__ cpx<T> mul_si(cpx<T> a) {
+  return S > 0 ? cpx<T>{-a.y, a.x} : cpx<T>{a.y, -a.x};
+}
+
+// One FFT axis: length n = prod(radix), twiddles tw[k] = exp(-2 pi i k / n).
+struct AxisPlan {
+  int n;
+  int nstage;
+  int radix[kMaxStages];
+};
+
+// Per-phase material constants (Lame lambda, mu and toughness Gc).
+struct Material {
+  int nphase;
+  double lam[kMaxPhases], mu[kMaxPhases], Gc[kMaxPhases];
+};
+
+// Small per-component constant vector passed by value (e.g. f in Mandel form).
+struct Vec16 {
+  double v[16];
+};
+
+// Geometry of the voxel grid and of the x-halved spectrum.
+struct GridDesc {
+  int nx, ny, nz, nxh;   // nxh = nx/2 + 1
+  long long N, Nh;       // voxels, half-spectrum points per field
+};
+
+// Deterministic block reduction of NR double accumulators; thread 0 of the
+// block ends with the totals.  Fixed pairing order -> bitwise reproducible.
+template <int NR>
+__device__ __forceinline__ void block_reduce(double (&v)[NR], double* lds /* NR*kBlock */) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) lds[q * kBlock + t] = v[q];
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (t < s) {
+#pragma unroll
+      for (int q = 0; q < NR; ++q) lds[q * kBlock + t] += lds[q * kBlock + t + s];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+#pragma unroll
+    for (int q = 0; q < NR; ++q) v[q] = lds[q * kBlock];
+  }
+  __syncthreads();
+}
+
+}  // namespace pff

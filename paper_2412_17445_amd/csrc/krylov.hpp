@@ -1,0 +1,275 @@
+// Vector kernels of the Krylov and Newton loops.
+//
+// BiCGSTAB (van der Vorst) for the non-symmetric bordered Newton system
+// (paper Sec. 3.2); vectors are in the apply precision TW, every inner
+// product is accumulated in FP64 per thread, then per block, then over
+// blocks in a fixed order (bitwise reproducible).  Scalars live on the
+// device in `ks` so that no host round trip sits between the vector steps.
+#pragma once
+
+#include "common.hpp"
+
+namespace pff {
+
+enum KrylovScalar {
+  KS_RHO = 0, KS_RHO_OLD, KS_ALPHA, KS_OMEGA, KS_BETA, KS_RR, KS_BNORM, KS_FLAG,
+  KS_RV, KS_TS, KS_TT, KS_RNORM, KS_TRUE, KS_COUNT
+};
+
+constexpr int kRedBlocks = 1024;   // upper bound on the blocks of a vector reduction
+
+__host__ __device__ inline int red_blocks(long long M) {
+  long long b = (M + (long long)kBlock * 8 - 1) / ((long long)kBlock * 8);
+  if (b < 1) b = 1;
+  if (b > kRedBlocks) b = kRedBlocks;
+  return (int)b;
+}
+
+// splitmix64 (Steele, Lea & Flood 2014): output number i of the stream
+// started at `seed` is mix(seed + (i+1) * golden).
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <int ND>
+__device__ __forceinline__ void write_partials(double (&acc)[ND], double* partials) {
+  __shared__ double lds[ND * kBlock];
+  block_reduce<ND>(acc, lds);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < ND; ++q) partials[(long long)q * gridDim.x + blockIdx.x] = acc[q];
+}
+
+// partials of up to three inner products (a_q, b_q)
+template <typename T, int ND>
+__global__ void __launch_bounds__(kBlock) k_dots(const T* __restrict__ a0, const T* __restrict__ b0,
+                                                 const T* __restrict__ a1, const T* __restrict__ b1,
+                                                 const T* __restrict__ a2, const T* __restrict__ b2,
+                                                 long long M, double* __restrict__ partials) {
+  double acc[ND];
+#pragma unroll
+  for (int q = 0; q < ND; ++q) acc[q] = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+       i += (long long)gridDim.x * blockDim.x) {
+    acc[0] += double(a0[i]) * double(b0[i]);
+    if (ND > 1) acc[1] += double(a1[i]) * double(b1[i]);
+    if (ND > 2) acc[2] += double(a2[i]) * double(b2[i]);
+  }
+  write_partials<ND>(acc, partials);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_copy(T* __restrict__ dst, const T* __restrict__ src, long long M) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fill(T* __restrict__ dst, T val, long long M) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = val;
+}
+
+// BiCGSTAB start: x = 0, r = b, p = v = 0, partial of (b, b)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bicg_init(const T* __restrict__ b, T* __restrict__ x,
+                                                      T* __restrict__ r, T* __restrict__ p,
+                                                      T* __restrict__ v, long long M,
+                                                      double* __restrict__ partials) {
+  double acc[1] = {0.0};
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+       i += (long long)gridDim.x * blockDim.x) {
+    const T bi = b[i];
+    x[i] = T(0);
+    r[i] = bi;
+    p[i] = T(0);
+    v[i] = T(0);
+    acc[0] += double(bi) * double(bi);
+  }
+  write_partials<1>(acc, partials);
+}
+
+// shadow residual r_hat = r0 + (||r0|| / sqrt(M)) s_i, and partial of (r_hat, r0)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bicg_shadow(const T* __restrict__ r, T* __restrict__ rhat,
+                                                        const double* __restrict__ ks, uint64_t seed,
+                                                        long long M, double* __restrict__ partials) {
+  const double scale = ks[KS_RNORM] / sqrt(double(M));
+  double acc[1] = {0.0};
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double s = (splitmix64_at(seed, (uint64_t)i) >> 63) ? 1.0 : -1.0;
+    const T h = T(double(r[i]) + scale * s);
+    rhat[i] = h;
+    acc[0] += double(h) * double(r[i]);
+  }
+  write_partials<1>(acc, partials);
+}
+
+// p = r + beta (p - omega v)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bicg_p(T* __restrict__ p, const T* __restrict__ r,
+                                                   const T* __restrict__ v, const double* __restrict__ ks,
+                                                   long long M) {
+  const T beta = T(ks[KS_BETA]), omega = T(ks[KS_OMEGA]);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = r[i] + beta * (p[i] - omega * v[i]);
+}
+
+// s = r - alpha v
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bicg_s(T* __restrict__ s, const T* __restrict__ r,
+                                                   const T* __restrict__ v, const double* __restrict__ ks,
+                                                   long long M) {
+  const T alpha = T(ks[KS_ALPHA]);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+       i += (long long)gridDim.x * blockDim.x)
+    s[i] = r[i] - alpha * v[i];
+}
+
+// x_next = x + alpha p + omega s ; r = s - omega t ; partials (r, r), (r_hat, r)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bicg_xr(T* __restrict__ xn, const T* __restrict__ x,
+                                                    const T* __restrict__ p, const T* __restrict__ s,
+                                                    const T* __restrict__ t, T* __restrict__ r,
+                                                    const T* __restrict__ rhat,
+                                                    const double* __restrict__ ks, long long M,
+                                                    double* __restrict__ partials) {
+  const T alpha = T(ks[KS_ALPHA]), omega = T(ks[KS_OMEGA]);
+  double acc[2] = {0.0, 0.0};
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+       i += (long long)gridDim.x * blockDim.x) {
+    const T si = s[i];
+    xn[i] = x[i] + alpha * p[i] + omega * si;
+    const T ri = si - omega * t[i];
+    r[i] = ri;
+    acc[0] += double(ri) * double(ri);
+    acc[1] += double(rhat[i]) * double(ri);
+  }
+  write_partials<2>(acc, partials);
+}
+
+// ---- scalar finalisers (run by one thread after the fixed-order reduction)
+
+struct FinStore {   // copy totals to dst[0..n)
+  struct Args { double* dst; int n; };
+  __device__ static void run(const Args& F, const double* tot) {
+    for (int q = 0; q < F.n; ++q) F.dst[q] = tot[q];
+  }
+};
+
+struct FinBnorm {   // ||b|| -> ks, initial scalars
+  struct Args { double* ks; };
+  __device__ static void run(const Args& F, const double* tot) {
+    double* ks = F.ks;
+    ks[KS_BNORM] = sqrt(tot[0]);
+    ks[KS_RNORM] = sqrt(tot[0]);
+    ks[KS_RR] = tot[0];
+    ks[KS_RHO_OLD] = 1.0;
+    ks[KS_ALPHA] = 1.0;
+    ks[KS_OMEGA] = 1.0;
+    ks[KS_BETA] = 0.0;
+    ks[KS_FLAG] = 0.0;
+  }
+};
+
+struct FinRestart {  // true residual of the best iterate; scalars of a new run
+  struct Args { double* ks; };
+  __device__ static void run(const Args& F, const double* tot) {
+    double* ks = F.ks;
+    ks[KS_TRUE] = sqrt(tot[0]);
+    ks[KS_RNORM] = sqrt(tot[0]);
+    ks[KS_RR] = tot[0];
+    ks[KS_RHO_OLD] = 1.0;
+    ks[KS_ALPHA] = 1.0;
+    ks[KS_OMEGA] = 1.0;
+    ks[KS_BETA] = 0.0;
+    ks[KS_FLAG] = 0.0;
+  }
+};
+
+// r = b - t (t = A x), partial of (r, r); p = v = 0 for a new run
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_true_resid(T* __restrict__ r, const T* __restrict__ b,
+                                                       const T* __restrict__ t, T* __restrict__ p,
+                                                       T* __restrict__ v, long long M,
+                                                       double* __restrict__ partials) {
+  double acc[1] = {0.0};
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+       i += (long long)gridDim.x * blockDim.x) {
+    const T ri = b[i] - t[i];
+    r[i] = ri;
+    p[i] = T(0);
+    v[i] = T(0);
+    acc[0] += double(ri) * double(ri);
+  }
+  write_partials<1>(acc, partials);
+}
+
+struct FinRho0 {    // rho = (r_hat, r0)
+  struct Args { double* ks; };
+  __device__ static void run(const Args& F, const double* tot) { F.ks[KS_RHO] = tot[0]; }
+};
+
+struct FinAlpha {   // alpha = rho / (r_hat, v)
+  struct Args { double* ks; };
+  __device__ static void run(const Args& F, const double* tot) {
+    double* ks = F.ks;
+    const double rv = tot[0];
+    ks[KS_RV] = rv;
+    if (rv == 0.0 || !isfinite(rv)) {
+      ks[KS_FLAG] = 1.0;
+      ks[KS_ALPHA] = 0.0;
+    } else {
+      ks[KS_ALPHA] = ks[KS_RHO] / rv;
+    }
+  }
+};
+
+struct FinOmega {   // omega = (t, s) / (t, t)
+  struct Args { double* ks; };
+  __device__ static void run(const Args& F, const double* tot) {
+    double* ks = F.ks;
+    ks[KS_TS] = tot[0];
+    ks[KS_TT] = tot[1];
+    if (tot[1] == 0.0 || !isfinite(tot[1])) {
+      ks[KS_FLAG] = 2.0;
+      ks[KS_OMEGA] = 0.0;
+    } else {
+      ks[KS_OMEGA] = tot[0] / tot[1];
+    }
+  }
+};
+
+struct FinRR {      // ||r||^2 and the next rho, beta
+  struct Args { double* ks; };
+  __device__ static void run(const Args& F, const double* tot) {
+    double* ks = F.ks;
+    ks[KS_RR] = tot[0];
+    const double rho_new = tot[1];
+    const double rho = ks[KS_RHO];
+    ks[KS_RHO_OLD] = rho;
+    ks[KS_RHO] = rho_new;
+    const double om = ks[KS_OMEGA];
+    if (rho_new == 0.0 || !isfinite(rho_new) || rho == 0.0 || om == 0.0) {
+      if (ks[KS_FLAG] == 0.0) ks[KS_FLAG] = 3.0;
+      ks[KS_BETA] = 0.0;
+    } else {
+      ks[KS_BETA] = (rho_new / rho) * (ks[KS_ALPHA] / om);
+    }
+  }
+};
+
+template <typename T>
+struct FinLast {    // write the reduced total into the trailing entry of a vector
+  struct Args { T* dst; };
+  __device__ static void run(const Args& F, const double* tot) { *F.dst = T(tot[0]); }
+};
+
+}  // namespace pff

@@ -1,0 +1,1135 @@
+// Host driver and C ABI of the crack-length-controlled phase-field FFT solver.
+//
+// Paper: Aranda & Segurado, Sec. 3.2 and Algorithm 2.  One increment:
+//   a <- a + delta_a; Newton from the committed fields; per iteration the
+//   FP64 residual pass (constitutive update fused into its first FFT pass),
+//   BiCGSTAB on the matrix-free tangent (FFT passes with fused prologue and
+//   epilogue), the relaxed update; history committed after convergence.
+#include "pff.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "krylov.hpp"
+#include "pipes.hpp"
+
+using namespace pff;
+
+namespace {
+
+struct Fail : std::runtime_error {
+  int code;
+  Fail(const std::string& m, int c) : std::runtime_error(m), code(c) {}
+};
+
+#define HC(expr)                                                                          \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw Fail(std::string(#expr) + ": " + hipGetErrorString(e_),                       \
+                 e_ == hipErrorOutOfMemory ? PFF_ERR_OOM : PFF_ERR_DEVICE);               \
+  } while (0)
+
+#define LAUNCH_CHECK() HC(hipGetLastError())
+
+constexpr size_t kLdsBudget = 64 * 1024;
+constexpr uint64_t kShadowSeed = 0x5EED;
+constexpr double kDiverged = 1e8;
+constexpr int kBisection = 100;
+constexpr int kMaxCycles = 8;
+
+// device scalar slots
+enum {
+  SC_SIG = 0,      // 6 sums of sigma
+  SC_GAMMA = 6, SC_F1 = 7, SC_F2 = 8,
+  SC_NW = 9, SC_NEPS = 10, SC_NDPHI = 11, SC_NPHI = 12,
+  SC_CG = 16,      // CG scratch
+  SC_KS = 32,      // Krylov scalars
+  SC_COUNT = 64
+};
+
+bool factor23(int n, AxisPlan& pl) {
+  pl.n = n;
+  pl.nstage = 0;
+  int a = 0, b = 0, m = n;
+  while (m % 2 == 0) { m /= 2; ++a; }
+  while (m % 3 == 0) { m /= 3; ++b; }
+  if (m != 1) return false;
+  while (a >= 3) { pl.radix[pl.nstage++] = 8; a -= 3; }
+  if (a == 2) pl.radix[pl.nstage++] = 4;
+  else if (a == 1) pl.radix[pl.nstage++] = 2;
+  for (int i = 0; i < b; ++i) pl.radix[pl.nstage++] = 3;
+  return pl.nstage <= kMaxStages;
+}
+
+template <typename T> struct DevTables {
+  cpx<T>* tw[3] = {nullptr, nullptr, nullptr};
+  T* hs[3] = {nullptr, nullptr, nullptr};
+  T* hc[3] = {nullptr, nullptr, nullptr};
+  T* q2[3] = {nullptr, nullptr, nullptr};
+};
+
+}  // namespace
+
+struct pff_solver {
+  // problem
+  int nx = 0, ny = 0, nz = 0, nxh = 0, dim = 0, C = 0;
+  long long N = 0, Nh = 0, M = 0;
+  Material mat{};
+  pff_params prm{};
+  double fm[6] = {0, 0, 0, 0, 0, 0};   // f in Mandel form
+  std::vector<uint8_t> h_pid, h_mask;
+  bool has_mask = false;
+  std::vector<pff_phase> phases;
+  hipStream_t stream = nullptr;
+  GridDesc g{};
+  AxisPlan plan[3]{};
+  DevTables<double> td;
+  DevTables<float> tf;
+  // device memory
+  std::vector<void*> allocs;
+  uint8_t *pid = nullptr, *mask = nullptr;
+  double *eps_t = nullptr, *phi = nullptr, *Hn = nullptr, *Hcur = nullptr;
+  double *eps_c = nullptr, *phi_c = nullptr, *phi_guess = nullptr, *dmask = nullptr;
+  double* Edev = nullptr;   // [0] current E, [1] committed E
+  void* ts = nullptr;       // tangent state (C+3)*N, working precision
+  void* kv[11] = {};        // Krylov vectors, working precision, M each
+  void* aux = nullptr;      // N, working precision
+  cpx<double>* spec_d = nullptr;
+  cpx<float>* spec_f = nullptr;
+  double *part0 = nullptr, *part1 = nullptr;
+  size_t part_len = 0;
+  double* scal = nullptr;
+  double* hscal = nullptr;  // pinned mirror
+  double* hstage = nullptr; // pinned staging for small uploads
+  double* cgv[4] = {};      // CG vectors (N doubles)
+  // host state
+  bool bootstrapped = false;
+  bool ts_valid = false;
+  bool trace = false;       // PFF_TRACE=1: per-Newton-iteration log on stderr
+  int n = 0;
+  double a = 0.0, E = 0.0, E_s = 0.0;
+  long long applies = 0, kiters = 0;
+  std::string err;
+
+  bool mixed() const { return prm.precision == PFF_PREC_MIXED; }
+
+  template <typename T> T* alloc(size_t count) {
+    void* p = nullptr;
+    HC(hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)));
+    allocs.push_back(p);
+    return static_cast<T*>(p);
+  }
+  template <typename T> const DevTables<T>& tables() const;
+  template <typename T> cpx<T>* spec() const;
+};
+
+template <> const DevTables<double>& pff_solver::tables<double>() const { return td; }
+template <> const DevTables<float>& pff_solver::tables<float>() const { return tf; }
+template <> cpx<double>* pff_solver::spec<double>() const { return spec_d; }
+template <> cpx<float>* pff_solver::spec<float>() const { return spec_f ? spec_f : (cpx<float>*)spec_d; }
+
+namespace {
+
+template <typename T> SpecTables<T> spec_tables(const pff_solver* s) {
+  const DevTables<T>& t = s->tables<T>();
+  SpecTables<T> st;
+  for (int a = 0; a < 3; ++a) {
+    st.hs[a] = t.hs[a];
+    st.hc[a] = t.hc[a];
+    st.q2[a] = t.q2[a];
+  }
+  st.invN = T(1.0 / double(s->N));
+  return st;
+}
+
+int grid1(long long M) {
+  long long b = (M + kBlock - 1) / kBlock;
+  if (b > 4096) b = 4096;
+  return (int)std::max<long long>(b, 1);
+}
+
+int choose_rb(int nx, int np, size_t csz, int nred) {
+  int rb = std::max(1, 1024 / nx);
+  while (rb > 1 && (size_t(2 * rb * np * nx) + nx) * csz > kLdsBudget) rb /= 2;
+  (void)nred;
+  return rb;
+}
+
+size_t lds_x(int rb, int np, int nx, size_t csz, int nred) {
+  size_t b = (size_t(2 * rb * np * nx) + nx) * csz;
+  return std::max(b, size_t(nred) * kBlock * sizeof(double));
+}
+
+int choose_tx(int n, int nf, size_t csz, int nxh) {
+  int tx = 16;
+  while (tx > 1 && (size_t(2 * nf * tx * n) + n) * csz > kLdsBudget) tx /= 2;
+  while (tx > 1 && tx / 2 >= nxh) tx /= 2;
+  return tx;
+}
+
+// Runs the FFT round trip of pipe P: forward passes with its prologue, the
+// spectral stage, inverse passes with its epilogue.
+template <class P>
+void run_pipeline(pff_solver* s, const typename P::Args& A, int& nblk_x) {
+  using T = typename P::real;
+  constexpr int NF = P::NF;
+  constexpr int NP = (NF + 1) / 2;
+  const DevTables<T>& tb = s->tables<T>();
+  cpx<T>* spec = s->spec<T>();
+  const size_t csz = sizeof(cpx<T>);
+  const int rb = choose_rb(s->nx, NP, csz, std::max(P::NRED_PRO, P::NRED_EPI));
+  const size_t ldsx = lds_x(rb, NP, s->nx, csz, std::max(P::NRED_PRO, P::NRED_EPI));
+  if (ldsx > kLdsBudget) throw Fail("grid too large for the LDS budget of the x pass", PFF_ERR_ARG);
+  const long long nrows = (long long)s->ny * s->nz;
+  nblk_x = (int)((nrows + rb - 1) / rb);
+  if ((size_t)nblk_x > s->part_len) throw Fail("partial buffer too small", PFF_ERR_STATE);
+  k_xfwd<P><<<nblk_x, kBlock, ldsx, s->stream>>>(A, s->plan[0], tb.tw[0], spec, rb, s->part0);
+  LAUNCH_CHECK();
+  if (s->dim == 2) {
+    const int tx = choose_tx(s->ny, NF, csz, s->nxh);
+    const size_t lds = (size_t(2 * NF * tx * s->ny) + s->ny) * csz;
+    if (lds > kLdsBudget) throw Fail("axis too long for the LDS budget", PFF_ERR_ARG);
+    dim3 grid((s->nxh + tx - 1) / tx, 1);
+    k_axis<P, -1, true><<<grid, kBlock, lds, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, tx);
+    LAUNCH_CHECK();
+  } else {
+    const int txy = choose_tx(s->ny, NF, csz, s->nxh);
+    const size_t ldsy = (size_t(2 * NF * txy * s->ny) + s->ny) * csz;
+    const int txz = choose_tx(s->nz, NF, csz, s->nxh);
+    const size_t ldsz = (size_t(2 * NF * txz * s->nz) + s->nz) * csz;
+    if (ldsy > kLdsBudget || ldsz > kLdsBudget) throw Fail("axis too long for the LDS budget", PFF_ERR_ARG);
+    dim3 gy((s->nxh + txy - 1) / txy, s->nz), gz((s->nxh + txz - 1) / txz, s->ny);
+    k_axis<P, -1, false><<<gy, kBlock, ldsy, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, txy);
+    LAUNCH_CHECK();
+    k_axis<P, -1, true><<<gz, kBlock, ldsz, s->stream>>>(A, s->plan[2], tb.tw[2], spec, 2, txz);
+    LAUNCH_CHECK();
+    k_axis<P, 1, false><<<gy, kBlock, ldsy, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, txy);
+    LAUNCH_CHECK();
+  }
+  k_xinv<P><<<nblk_x, kBlock, ldsx, s->stream>>>(A, s->plan[0], tb.tw[0], spec, rb, s->part1);
+  LAUNCH_CHECK();
+}
+
+void sync_scal(pff_solver* s) {
+  HC(hipMemcpyAsync(s->hscal, s->scal, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HC(hipStreamSynchronize(s->stream));
+}
+
+// ---- small kernels ------------------------------------------------------------
+
+__global__ void k_lincomb(double* __restrict__ out, double a, const double* __restrict__ x, double b,
+                          const double* __restrict__ y, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = a * x[i] + (y ? b * y[i] : 0.0);
+}
+
+__global__ void k_mask_to_double(double* __restrict__ out, const uint8_t* __restrict__ m, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = m[i] ? 1.0 : 0.0;
+}
+
+// phi0 = m + (1 - m) u
+__global__ void k_phi0(double* __restrict__ phi, const double* __restrict__ u,
+                       const uint8_t* __restrict__ m, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    phi[i] = m[i] ? 1.0 : u[i];
+}
+
+// predictor guess: phi = max(phi0, (1-m) phi_loc(phase))
+__global__ void k_guess(double* __restrict__ phi, const double* __restrict__ phi0,
+                        const uint8_t* __restrict__ pid, const uint8_t* __restrict__ m, Vec16 loc,
+                        long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double pl = m[i] ? 0.0 : loc.v[pid[i]];
+    phi[i] = phi0[i] > pl ? phi0[i] : pl;
+  }
+}
+
+// Newton update (Algorithm 2): eps_t += alpha d eps, phi += alpha (1-m) d phi,
+// partials of ||d eps + f dE||^2, ||eps||^2, ||d phi||^2, ||phi||^2 at the new state.
+template <typename TW, int C>
+__global__ void __launch_bounds__(kBlock) k_newton_update(double* __restrict__ eps_t, double* __restrict__ phi,
+                                                          const TW* __restrict__ x,
+                                                          const uint8_t* __restrict__ mask, Vec16 fm,
+                                                          const double* __restrict__ Edev, double alpha,
+                                                          long long N, double* __restrict__ partials) {
+  const double dE = double(x[(long long)(C + 1) * N]);
+  const double En = Edev[0] + alpha * dE;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      const double d = double(x[k * N + i]);
+      const double w = d + fm.v[k] * dE;
+      const double e = eps_t[k * N + i] + alpha * d;
+      eps_t[k * N + i] = e;
+      const double et = e + fm.v[k] * En;
+      acc[0] += w * w;
+      acc[1] += et * et;
+    }
+    const double dp = mask[i] ? 0.0 : double(x[(long long)C * N + i]);
+    const double p = phi[i] + alpha * dp;
+    phi[i] = p;
+    acc[2] += dp * dp;
+    acc[3] += p * p;
+  }
+  write_partials<4>(acc, partials);
+}
+
+__global__ void k_commit_history(double* __restrict__ Hn, const double* __restrict__ Hcur, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    Hn[i] = fabs(Hcur[i]);
+}
+
+struct FinNewton {
+  struct Args { double* scal; double* Edev; const void* x; int last_is_float; long long idx; double alpha; };
+  __device__ static void run(const Args& F, const double* tot) {
+    F.scal[SC_NW] = tot[0];
+    F.scal[SC_NEPS] = tot[1];
+    F.scal[SC_NDPHI] = tot[2];
+    F.scal[SC_NPHI] = tot[3];
+    const double dE = F.last_is_float ? double(((const float*)F.x)[F.idx]) : ((const double*)F.x)[F.idx];
+    F.Edev[0] = F.Edev[0] + F.alpha * dE;
+  }
+};
+
+template <typename TW>
+struct FinResid {
+  struct Args { double* scal; double a; TW* rhs_last; double* F_last; };
+  __device__ static void run(const Args& F, const double* tot) {
+    F.scal[SC_GAMMA] = tot[0];
+    F.scal[SC_F1] = tot[1];
+    F.scal[SC_F2] = tot[2];
+    F.rhs_last[0] = TW(F.a - tot[0]);
+    if (F.F_last) F.F_last[0] = tot[0] - F.a;
+  }
+};
+
+// ---- templated solver steps -------------------------------------------------------
+
+template <int DIM, typename TW>
+struct Impl {
+  static constexpr int C = DIM == 2 ? 3 : 6;
+
+  static TW* vec(pff_solver* s, int k) { return static_cast<TW*>(s->kv[k]); }
+  enum { X0 = 0, X1, X2, R, RHAT, P, V, S, T, RHS, SOL };
+
+  static void fill_tangent_args(pff_solver* s, typename TangentPipe<TW, DIM>::Args& A) {
+    A.g = s->g;
+    A.mat = s->mat;
+    A.l = TW(s->prm.l);
+    A.k = TW(s->prm.k_resid);
+    for (int k = 0; k < 6; ++k) A.f[k] = TW(s->fm[k]);
+    A.ts = static_cast<const TW*>(s->ts);
+    A.pid = s->pid;
+    A.mask = s->mask;
+    A.aux = static_cast<TW*>(s->aux);
+    A.tab = spec_tables<TW>(s);
+  }
+
+  static void apply(pff_solver* s, const TW* v, TW* Jv) {
+    typename TangentPipe<TW, DIM>::Args A;
+    fill_tangent_args(s, A);
+    A.v = v;
+    A.Jv = Jv;
+    int nblk = 0;
+    run_pipeline<TangentPipe<TW, DIM>>(s, A, nblk);
+    typename FinLast<TW>::Args F{Jv + (long long)(C + 1) * s->N};
+    k_reduce<FinLast<TW>><<<1, kBlock, 0, s->stream>>>(s->part0, nblk, 1, F);
+    LAUNCH_CHECK();
+    s->applies++;
+  }
+
+  // residual at the current state for target a; rhs = -F in working precision
+  static void residual(pff_solver* s, double a, double* F_dev) {
+    typename ResidualPipe<DIM, TW>::Args A;
+    A.g = s->g;
+    A.mat = s->mat;
+    A.l = s->prm.l;
+    A.k = s->prm.k_resid;
+    for (int k = 0; k < 6; ++k) A.f[k] = s->fm[k];
+    A.eps_t = s->eps_t;
+    A.phi = s->phi;
+    A.Hn = s->Hn;
+    A.Hcur = s->Hcur;
+    A.E = s->Edev;
+    A.ts = static_cast<TW*>(s->ts);
+    A.rhs = vec(s, RHS);
+    A.F = F_dev;
+    A.pid = s->pid;
+    A.mask = s->mask;
+    A.tab = spec_tables<double>(s);
+    int nblk = 0;
+    run_pipeline<ResidualPipe<DIM, TW>>(s, A, nblk);
+    FinStore::Args fs{s->scal + SC_SIG, 6};
+    k_reduce<FinStore><<<1, kBlock, 0, s->stream>>>(s->part0, nblk, 6, fs);
+    LAUNCH_CHECK();
+    typename FinResid<TW>::Args fr{s->scal, a, vec(s, RHS) + (long long)(C + 1) * s->N,
+                                    F_dev ? F_dev + (long long)(C + 1) * s->N : nullptr};
+    k_reduce<FinResid<TW>><<<1, kBlock, 0, s->stream>>>(s->part1, nblk, 3, fr);
+    LAUNCH_CHECK();
+    s->ts_valid = true;
+  }
+
+  static void reduce_ks(pff_solver* s, int nslot, int which) {
+    const int nb = red_blocks(s->M);
+    double* ks = s->scal + SC_KS;
+    if (which == 0) k_reduce<FinBnorm><<<1, kBlock, 0, s->stream>>>(s->part0, nb, nslot, FinBnorm::Args{ks});
+    else if (which == 1) k_reduce<FinRho0><<<1, kBlock, 0, s->stream>>>(s->part0, nb, nslot, FinRho0::Args{ks});
+    else if (which == 2) k_reduce<FinAlpha><<<1, kBlock, 0, s->stream>>>(s->part0, nb, nslot, FinAlpha::Args{ks});
+    else if (which == 3) k_reduce<FinOmega><<<1, kBlock, 0, s->stream>>>(s->part0, nb, nslot, FinOmega::Args{ks});
+    else k_reduce<FinRR><<<1, kBlock, 0, s->stream>>>(s->part0, nb, nslot, FinRR::Args{ks});
+    LAUNCH_CHECK();
+  }
+
+  // BiCGSTAB with a true-residual check (x_out = J^{-1} b); returns 1 if
+  // ||b - J x_out|| <= rtol ||b||.  A run keeps its iterate of smallest
+  // recursive residual (three x buffers rotate, no copies); when the run
+  // stops, b - J x of that iterate is formed and, if it misses the
+  // tolerance, a new run starts from it (the recursive residual of BiCGSTAB
+  // can drift from the true one after large intermediate iterates).
+  static int bicgstab(pff_solver* s, const TW* b, TW* x_out, double rtol, int maxit, int* iters,
+                      double* relres) {
+    const long long M = s->M;
+    const int nb = red_blocks(M);
+    const int g1 = nb;
+    double* ks = s->scal + SC_KS;
+    TW* xb[3] = {vec(s, X0), vec(s, X1), vec(s, X2)};
+    TW *r = vec(s, R), *rhat = vec(s, RHAT), *p = vec(s, P), *v = vec(s, V), *sv = vec(s, S),
+       *t = vec(s, T);
+    k_bicg_init<TW><<<g1, kBlock, 0, s->stream>>>(b, xb[0], r, p, v, M, s->part0);
+    LAUNCH_CHECK();
+    reduce_ks(s, 1, 0);
+    sync_scal(s);
+    const double bnorm = s->hscal[SC_KS + KS_BNORM];
+    int total = 0, conv = 0, cur = 0, best = 0;
+    double true_res = bnorm;
+    if (bnorm == 0.0) conv = 1;
+    for (int cycle = 0; cycle < kMaxCycles && !conv; ++cycle) {
+      double res_best = true_res;     // the run starts at x[best] with its true residual
+      cur = best;
+      k_bicg_shadow<TW><<<g1, kBlock, 0, s->stream>>>(r, rhat, ks, kShadowSeed, M, s->part0);
+      LAUNCH_CHECK();
+      reduce_ks(s, 1, 1);
+      while (total < maxit) {
+        ++total;
+        k_bicg_p<TW><<<g1, kBlock, 0, s->stream>>>(p, r, v, ks, M);
+        LAUNCH_CHECK();
+        apply(s, p, v);
+        k_dots<TW, 1><<<g1, kBlock, 0, s->stream>>>(rhat, v, nullptr, nullptr, nullptr, nullptr, M, s->part0);
+        LAUNCH_CHECK();
+        reduce_ks(s, 1, 2);
+        k_bicg_s<TW><<<g1, kBlock, 0, s->stream>>>(sv, r, v, ks, M);
+        LAUNCH_CHECK();
+        apply(s, sv, t);
+        k_dots<TW, 2><<<g1, kBlock, 0, s->stream>>>(t, sv, t, t, nullptr, nullptr, M, s->part0);
+        LAUNCH_CHECK();
+        reduce_ks(s, 2, 3);
+        int nxt = 0;
+        while (nxt == cur || nxt == best) ++nxt;
+        k_bicg_xr<TW><<<g1, kBlock, 0, s->stream>>>(xb[nxt], xb[cur], p, sv, t, r, rhat, ks, M, s->part0);
+        LAUNCH_CHECK();
+        reduce_ks(s, 2, 4);
+        sync_scal(s);
+        s->kiters++;
+        const double flag = s->hscal[SC_KS + KS_FLAG];
+        if (flag == 1.0 || flag == 2.0) {   // breakdown before the update
+          --total;
+          s->kiters--;
+          break;
+        }
+        cur = nxt;
+        const double res = std::sqrt(s->hscal[SC_KS + KS_RR]);
+        if (res < res_best) {
+          best = cur;
+          res_best = res;
+        }
+        if (res <= rtol * bnorm) break;
+        if (flag != 0.0 || !std::isfinite(res) || res > kDiverged * bnorm) break;
+      }
+      // true residual of the best iterate; also resets the scalars of a new run
+      apply(s, xb[best], t);
+      k_true_resid<TW><<<g1, kBlock, 0, s->stream>>>(r, b, t, p, v, M, s->part0);
+      LAUNCH_CHECK();
+      k_reduce<FinRestart><<<1, kBlock, 0, s->stream>>>(s->part0, nb, 1, FinRestart::Args{ks});
+      LAUNCH_CHECK();
+      sync_scal(s);
+      true_res = s->hscal[SC_KS + KS_TRUE];
+      if (true_res <= rtol * bnorm) conv = 1;
+      if (total >= maxit) break;
+    }
+    k_copy<TW><<<g1, kBlock, 0, s->stream>>>(x_out, xb[best], M);
+    LAUNCH_CHECK();
+    if (iters) *iters = total;
+    if (relres) *relres = bnorm > 0.0 ? true_res / bnorm : 0.0;
+    return conv;
+  }
+
+  static void newton_update(pff_solver* s, const TW* x, double alpha) {
+    const int nb = red_blocks(s->N);
+    Vec16 fm{};
+    for (int k = 0; k < 6; ++k) fm.v[k] = s->fm[k];
+    k_newton_update<TW, C><<<nb, kBlock, 0, s->stream>>>(s->eps_t, s->phi, x, s->mask, fm, s->Edev,
+                                                          alpha, s->N, s->part0);
+    LAUNCH_CHECK();
+    FinNewton::Args F{s->scal, s->Edev, x, std::is_same<TW, float>::value ? 1 : 0,
+                      (long long)(C + 1) * s->N, alpha};
+    k_reduce<FinNewton><<<1, kBlock, 0, s->stream>>>(s->part0, nb, 4, F);
+    LAUNCH_CHECK();
+    s->ts_valid = false;
+  }
+
+  static void helm_apply(pff_solver* s, const double* u, double* out, int mask_input) {
+    HelmPipe::Args A;
+    A.g = s->g;
+    A.l = s->prm.l;
+    A.u = u;
+    A.out = out;
+    A.mask_input = mask_input;
+    A.mask = s->mask;
+    A.tab = spec_tables<double>(s);
+    int nblk = 0;
+    run_pipeline<HelmPipe>(s, A, nblk);
+  }
+
+  static double dot(pff_solver* s, const double* a, const double* b, long long n) {
+    const int nb = red_blocks(n);
+    k_dots<double, 1><<<nb, kBlock, 0, s->stream>>>(a, b, nullptr, nullptr, nullptr, nullptr, n, s->part0);
+    LAUNCH_CHECK();
+    FinStore::Args fs{s->scal + SC_CG, 1};
+    k_reduce<FinStore><<<1, kBlock, 0, s->stream>>>(s->part0, nb, 1, fs);
+    LAUNCH_CHECK();
+    sync_scal(s);
+    return s->hscal[SC_CG];
+  }
+
+  // phi0: masked damage-free Helmholtz problem by CG (rtol 1e-14)
+  static void initial_damage(pff_solver* s, double* phi0) {
+    const long long N = s->N;
+    const int g = grid1(N);
+    if (!s->has_mask) {
+      k_fill<double><<<g, kBlock, 0, s->stream>>>(phi0, 0.0, N);
+      LAUNCH_CHECK();
+      return;
+    }
+    double *x = s->cgv[0], *r = s->cgv[1], *p = s->cgv[2], *Ap = s->cgv[3];
+    k_mask_to_double<<<g, kBlock, 0, s->stream>>>(s->dmask, s->mask, N);
+    LAUNCH_CHECK();
+    helm_apply(s, s->dmask, r, 0);                       // (1-m) B m
+    k_lincomb<<<g, kBlock, 0, s->stream>>>(r, -1.0, r, 0.0, nullptr, N);   // r = b = -(1-m) B m
+    k_fill<double><<<g, kBlock, 0, s->stream>>>(x, 0.0, N);
+    k_copy<double><<<g, kBlock, 0, s->stream>>>(p, r, N);
+    LAUNCH_CHECK();
+    double rr = dot(s, r, r, N);
+    const double bnorm = std::sqrt(rr);
+    for (int it = 1; it <= 20000 && bnorm > 0.0; ++it) {
+      helm_apply(s, p, Ap, 1);
+      const double pAp = dot(s, p, Ap, N);
+      const double al = rr / pAp;
+      k_lincomb<<<g, kBlock, 0, s->stream>>>(x, 1.0, x, al, p, N);
+      k_lincomb<<<g, kBlock, 0, s->stream>>>(r, 1.0, r, -al, Ap, N);
+      LAUNCH_CHECK();
+      const double rr_new = dot(s, r, r, N);
+      if (std::sqrt(rr_new) <= 1e-14 * bnorm) break;
+      k_lincomb<<<g, kBlock, 0, s->stream>>>(p, 1.0, r, rr_new / rr, p, N);
+      LAUNCH_CHECK();
+      rr = rr_new;
+    }
+    k_phi0<<<g, kBlock, 0, s->stream>>>(phi0, x, s->mask, N);
+    LAUNCH_CHECK();
+  }
+};
+
+// ---- host-side predictor --------------------------------------------------------
+
+// psi0(+) of a symmetric tensor (3x3, or its in-plane 2x2 block in 2D)
+double psi_plus_host(const double f[9], double lam, double mu, int dim) {
+  double A[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) A[i][j] = 0.5 * (f[3 * i + j] + f[3 * j + i]);
+  const int D = dim == 2 ? 2 : 3;
+  if (D == 2) A[2][2] = A[0][2] = A[2][0] = A[1][2] = A[2][1] = 0.0;
+  // cyclic Jacobi (eigenvalues only)
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    if (off < 1e-300) break;
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2, o = 3 - p - q;
+      const double apq = A[p][q];
+      if (apq == 0.0) continue;
+      const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+      const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+      const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+      A[p][p] -= t * apq;
+      A[q][q] += t * apq;
+      A[p][q] = A[q][p] = 0.0;
+      const double aop = A[o][p], aoq = A[o][q];
+      A[o][p] = A[p][o] = c * aop - sn * aoq;
+      A[o][q] = A[q][o] = sn * aop + c * aoq;
+    }
+  }
+  double tr = 0.0, sq = 0.0;
+  for (int a = 0; a < D; ++a) {
+    tr += A[a][a];
+    const double zp = A[a][a] > 0.0 ? A[a][a] : 0.0;
+    sq += zp * zp;
+  }
+  const double trp = tr > 0.0 ? tr : 0.0;
+  return 0.5 * lam * trp * trp + mu * sq;
+}
+
+pff_status fail(pff_solver* s, const Fail& e) {
+  if (s) s->err = e.what();
+  return e.code;
+}
+
+template <typename F> pff_status guarded(pff_solver* s, F&& fn) {
+  if (!s) return PFF_ERR_ARG;
+  try {
+    s->err.clear();
+    return fn();
+  } catch (const Fail& e) {
+    return fail(s, e);
+  } catch (const std::exception& e) {
+    s->err = e.what();
+    return PFF_ERR_DEVICE;
+  }
+}
+
+template <typename F> void dispatch(pff_solver* s, F&& fn) {
+  if (s->dim == 2) {
+    if (s->mixed()) fn(Impl<2, float>{});
+    else fn(Impl<2, double>{});
+  } else {
+    if (s->mixed()) fn(Impl<3, float>{});
+    else fn(Impl<3, double>{});
+  }
+}
+
+template <typename T>
+void upload_tables(pff_solver* s, DevTables<T>& t) {
+  const int ns[3] = {s->nx, s->ny, s->nz};
+  for (int a = 0; a < 3; ++a) {
+    const int n = ns[a];
+    std::vector<cpx<T>> tw(n);
+    std::vector<T> hs(n), hc(n), q2(n);
+    for (int j = 0; j < n; ++j) {
+      const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)j / n;
+      tw[j] = cpx<T>{T(cosl(ang)), T(sinl(ang))};
+      const int m = (2 * j < n) ? j : j - n;      // signed frequency, Nyquist reads -n/2
+      const long double half = 3.14159265358979323846264338327950288L * (long double)m / n;
+      hs[j] = T(sinl(half));
+      hc[j] = (n % 2 == 0 && 2 * j == n) ? T(0) : T(cosl(half));
+      const long double q = 2.0L * half;
+      q2[j] = T(q * q);
+    }
+    t.tw[a] = s->alloc<cpx<T>>(n);
+    t.hs[a] = s->alloc<T>(n);
+    t.hc[a] = s->alloc<T>(n);
+    t.q2[a] = s->alloc<T>(n);
+    HC(hipMemcpy(t.tw[a], tw.data(), n * sizeof(cpx<T>), hipMemcpyHostToDevice));
+    HC(hipMemcpy(t.hs[a], hs.data(), n * sizeof(T), hipMemcpyHostToDevice));
+    HC(hipMemcpy(t.hc[a], hc.data(), n * sizeof(T), hipMemcpyHostToDevice));
+    HC(hipMemcpy(t.q2[a], q2.data(), n * sizeof(T), hipMemcpyHostToDevice));
+  }
+}
+
+void destroy_buffers(pff_solver* s) {
+  for (void* p : s->allocs) (void)hipFree(p);
+  s->allocs.clear();
+  if (s->hscal) (void)hipHostFree(s->hscal);
+  if (s->hstage) (void)hipHostFree(s->hstage);
+  s->hscal = nullptr;
+  s->hstage = nullptr;
+}
+
+}  // namespace
+
+// ================================================================== C ABI ====
+
+extern "C" {
+
+int pff_abi_version(void) { return PFF_ABI_VERSION; }
+
+const char* pff_last_error(const pff_solver* s) { return s ? s->err.c_str() : "null handle"; }
+
+pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phases, const uint8_t* phase_id,
+                      const uint8_t* crack_mask, const pff_params* params, void* hip_stream,
+                      pff_solver** out) {
+  if (!out) return PFF_ERR_ARG;
+  *out = nullptr;
+  if (!grid || !phases || !phase_id || !params) return PFF_ERR_ARG;
+  if (n_phases < 1 || n_phases > kMaxPhases) return PFF_ERR_ARG;
+  pff_solver* s = new (std::nothrow) pff_solver();
+  if (!s) return PFF_ERR_OOM;
+  pff_status st = guarded(s, [&]() -> pff_status {
+    s->nx = grid->nx;
+    s->ny = grid->ny;
+    s->nz = grid->nz;
+    if (s->nx < 2 || s->ny < 2 || s->nz < 1 || s->nx > 512 || s->ny > 512 || s->nz > 512)
+      throw Fail("grid sizes out of range", PFF_ERR_ARG);
+    if (!factor23(s->nx, s->plan[0]) || !factor23(s->ny, s->plan[1]) || !factor23(s->nz, s->plan[2]))
+      throw Fail("grid sizes must be products of 2 and 3", PFF_ERR_ARG);
+    s->dim = s->nz == 1 ? 2 : 3;
+    s->C = s->dim == 2 ? 3 : 6;
+    s->nxh = s->nx / 2 + 1;
+    s->N = (long long)s->nx * s->ny * s->nz;
+    s->Nh = (long long)s->nxh * s->ny * s->nz;
+    s->M = (long long)(s->C + 1) * s->N + 1;
+    s->g = GridDesc{s->nx, s->ny, s->nz, s->nxh, s->N, s->Nh};
+    s->prm = *params;
+    const pff_params& p = s->prm;
+    if (!(p.l > 0) || !(p.k_resid >= 0) || !(p.delta_a > 0) || !(p.alpha > 0) || p.alpha > 1 ||
+        !(p.newton_tol > 0) || !(p.krylov_rtol > 0) || p.newton_maxit < 1 || p.krylov_maxit < 1 ||
+        (p.precision != PFF_PREC_FP64 && p.precision != PFF_PREC_MIXED))
+      throw Fail("invalid solver parameters", PFF_ERR_ARG);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        if (p.f[3 * i + j] != p.f[3 * j + i]) throw Fail("f must be symmetric", PFF_ERR_ARG);
+    if (s->dim == 2 && (p.f[2] != 0 || p.f[5] != 0 || p.f[8] != 0))
+      throw Fail("2D (plane strain) needs an in-plane f", PFF_ERR_ARG);
+    const double r2 = std::sqrt(2.0);
+    if (s->dim == 2) {
+      s->fm[0] = p.f[0]; s->fm[1] = p.f[4]; s->fm[2] = r2 * p.f[1];
+    } else {
+      s->fm[0] = p.f[0]; s->fm[1] = p.f[4]; s->fm[2] = p.f[8];
+      s->fm[3] = r2 * p.f[5]; s->fm[4] = r2 * p.f[2]; s->fm[5] = r2 * p.f[1];
+    }
+    s->mat.nphase = n_phases;
+    s->phases.assign(phases, phases + n_phases);
+    for (int k = 0; k < n_phases; ++k) {
+      const double E = phases[k].E, nu = phases[k].nu;
+      if (!(E > 0) || !(nu > -1 && nu < 0.5) || !(phases[k].Gc > 0))
+        throw Fail("invalid phase constants", PFF_ERR_ARG);
+      s->mat.lam[k] = E * nu / ((1 + nu) * (1 - 2 * nu));
+      s->mat.mu[k] = E / (2 * (1 + nu));
+      s->mat.Gc[k] = phases[k].Gc;
+    }
+    s->h_pid.assign(phase_id, phase_id + s->N);
+    for (uint8_t v : s->h_pid)
+      if (v >= n_phases) throw Fail("phase id out of range", PFF_ERR_ARG);
+    s->h_mask.assign(s->N, 0);
+    if (crack_mask) {
+      for (long long i = 0; i < s->N; ++i) s->h_mask[i] = crack_mask[i] ? 1 : 0;
+      s->has_mask = std::any_of(s->h_mask.begin(), s->h_mask.end(), [](uint8_t v) { return v != 0; });
+    }
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    const char* tr = std::getenv("PFF_TRACE");
+    s->trace = tr && tr[0] == '1';
+    // device memory
+    const long long N = s->N, M = s->M;
+    const int C = s->C;
+    s->pid = s->alloc<uint8_t>(N);
+    s->mask = s->alloc<uint8_t>(N);
+    HC(hipMemcpy(s->pid, s->h_pid.data(), N, hipMemcpyHostToDevice));
+    HC(hipMemcpy(s->mask, s->h_mask.data(), N, hipMemcpyHostToDevice));
+    s->eps_t = s->alloc<double>(C * N);
+    s->eps_c = s->alloc<double>(C * N);
+    s->phi = s->alloc<double>(N);
+    s->phi_c = s->alloc<double>(N);
+    s->phi_guess = s->alloc<double>(N);
+    s->dmask = s->alloc<double>(N);
+    s->Hn = s->alloc<double>(N);
+    s->Hcur = s->alloc<double>(N);
+    s->Edev = s->alloc<double>(4);
+    const size_t wsz = s->mixed() ? sizeof(float) : sizeof(double);
+    s->ts = s->alloc<unsigned char>((size_t)(C + 3) * N * wsz);
+    for (int k = 0; k < 11; ++k) s->kv[k] = s->alloc<unsigned char>((size_t)M * wsz);
+    s->aux = s->alloc<unsigned char>((size_t)N * wsz);
+    s->spec_d = s->alloc<cpx<double>>((size_t)(C + 1) * s->Nh);
+    if (s->mixed()) s->spec_f = s->alloc<cpx<float>>((size_t)(C + 1) * s->Nh);
+    s->part_len = std::max<size_t>(kRedBlocks, (size_t)s->ny * s->nz + 16);
+    s->part0 = s->alloc<double>(s->part_len * kMaxRed);
+    s->part1 = s->alloc<double>(s->part_len * kMaxRed);
+    s->scal = s->alloc<double>(SC_COUNT);
+    for (int k = 0; k < 4; ++k) s->cgv[k] = s->alloc<double>(N);
+    HC(hipHostMalloc((void**)&s->hscal, SC_COUNT * sizeof(double), hipHostMallocDefault));
+    HC(hipHostMalloc((void**)&s->hstage, 8 * sizeof(double), hipHostMallocDefault));
+    upload_tables<double>(s, s->td);
+    upload_tables<float>(s, s->tf);
+    HC(hipMemset(s->eps_t, 0, C * N * sizeof(double)));
+    HC(hipMemset(s->eps_c, 0, C * N * sizeof(double)));
+    HC(hipMemset(s->phi, 0, N * sizeof(double)));
+    HC(hipMemset(s->phi_c, 0, N * sizeof(double)));
+    HC(hipMemset(s->Hn, 0, N * sizeof(double)));
+    HC(hipMemset(s->Edev, 0, 4 * sizeof(double)));
+    HC(hipMemset(s->scal, 0, SC_COUNT * sizeof(double)));
+    HC(hipDeviceSynchronize());
+    return PFF_OK;
+  });
+  if (st != PFF_OK) {
+    destroy_buffers(s);
+    delete s;
+    return st;
+  }
+  *out = s;
+  return PFF_OK;
+}
+
+void pff_destroy(pff_solver* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  destroy_buffers(s);
+  delete s;
+}
+
+pff_status pff_bootstrap(pff_solver* s, double* a0, double* E_s) {
+  return guarded(s, [&]() -> pff_status {
+    dispatch(s, [&](auto impl) {
+      using I = decltype(impl);
+      I::initial_damage(s, s->phi);
+      // a0 = Gamma(phi0): a residual pass at eps = 0, E = 0, H = 0
+      HC(hipMemsetAsync(s->eps_t, 0, s->C * s->N * sizeof(double), s->stream));
+      HC(hipMemsetAsync(s->Hn, 0, s->N * sizeof(double), s->stream));
+      HC(hipMemsetAsync(s->Edev, 0, 4 * sizeof(double), s->stream));
+      I::residual(s, 0.0, nullptr);
+      sync_scal(s);
+    });
+    s->a = s->hscal[SC_GAMMA];
+    // predictor: bisection on the gradient-free homogeneous damage
+    std::vector<double> psif(s->mat.nphase), cnt(s->mat.nphase, 0.0);
+    for (int k = 0; k < s->mat.nphase; ++k) psif[k] = psi_plus_host(s->prm.f, s->mat.lam[k], s->mat.mu[k], s->dim);
+    for (long long i = 0; i < s->N; ++i)
+      if (!s->h_mask[i]) cnt[s->h_pid[i]] += 1.0;
+    const double l = s->prm.l, da = s->prm.delta_a;
+    auto loc = [&](double E, int k) {
+      const double h = 2.0 * E * E * psif[k];
+      return h / (s->mat.Gc[k] / l + h);
+    };
+    auto S = [&](double E) {
+      double acc = 0.0;
+      for (int k = 0; k < s->mat.nphase; ++k) {
+        const double p = loc(E, k);
+        acc += cnt[k] * p * p;
+      }
+      return acc / (2.0 * l);
+    };
+    double lo = 0.0, hi = 1.0;
+    while (S(hi) < da) {
+      hi *= 2.0;
+      if (hi > 1e12) throw Fail("predictor: crack-length increment not reachable", PFF_ERR_ARG);
+    }
+    for (int it = 0; it < kBisection; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (S(mid) < da) lo = mid;
+      else hi = mid;
+    }
+    s->E_s = 0.5 * (lo + hi);
+    Vec16 locm{};
+    for (int k = 0; k < s->mat.nphase; ++k) locm.v[k] = loc(s->E_s, k);
+    const int g = grid1(s->N);
+    k_guess<<<g, kBlock, 0, s->stream>>>(s->phi_guess, s->phi, s->pid, s->mask, locm, s->N);
+    LAUNCH_CHECK();
+    HC(hipMemcpyAsync(s->phi_c, s->phi, s->N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    HC(hipStreamSynchronize(s->stream));
+    s->E = 0.0;
+    s->n = 0;
+    s->bootstrapped = true;
+    s->ts_valid = false;
+    if (a0) *a0 = s->a;
+    if (E_s) *E_s = s->E_s;
+    return PFF_OK;
+  });
+}
+
+pff_status pff_step(pff_solver* s, pff_increment_result* out) {
+  return guarded(s, [&]() -> pff_status {
+    if (!s->bootstrapped) throw Fail("pff_step before pff_bootstrap/pff_set_state", PFF_ERR_STATE);
+    const auto t0 = std::chrono::steady_clock::now();
+    const long long ap0 = s->applies, ki0 = s->kiters;
+    const double a_new = s->a + s->prm.delta_a;
+    const long long N = s->N;
+    const int C = s->C;
+    // Newton start
+    if (s->n == 0 && s->E_s > 0.0) {
+      HC(hipMemsetAsync(s->eps_t, 0, C * N * sizeof(double), s->stream));
+      HC(hipMemcpyAsync(s->phi, s->phi_guess, N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+      HC(hipStreamSynchronize(s->stream));
+      s->hstage[0] = s->E_s;
+      HC(hipMemcpyAsync(s->Edev, s->hstage, sizeof(double), hipMemcpyHostToDevice, s->stream));
+    } else {
+      HC(hipMemcpyAsync(s->eps_t, s->eps_c, C * N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+      HC(hipMemcpyAsync(s->phi, s->phi_c, N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+      HC(hipStreamSynchronize(s->stream));
+      s->hstage[0] = s->E;
+      HC(hipMemcpyAsync(s->Edev, s->hstage, sizeof(double), hipMemcpyHostToDevice, s->stream));
+    }
+    int conv = 0, it = 0;
+    double err[3] = {0, 0, 0};
+    const bool trace = s->trace;
+    dispatch(s, [&](auto impl) {
+      using I = decltype(impl);
+      using TW = typename std::remove_pointer<decltype(I::vec(s, 0))>::type;
+      I::residual(s, a_new, nullptr);
+      if (trace) {
+        sync_scal(s);
+        std::fprintf(stderr, "[pff] inc %d start |F1|=%.6e |F2|=%.6e F3=%.6e\n", s->n + 1,
+                     std::sqrt(s->hscal[SC_F1]), std::sqrt(s->hscal[SC_F2]), s->hscal[SC_GAMMA] - a_new);
+      }
+      for (it = 1; it <= s->prm.newton_maxit; ++it) {
+        int kit = 0;
+        double rr = 0;
+        I::bicgstab(s, I::vec(s, I::RHS), I::vec(s, I::SOL), s->prm.krylov_rtol, s->prm.krylov_maxit, &kit, &rr);
+        I::newton_update(s, I::vec(s, I::SOL), s->prm.alpha);
+        I::residual(s, a_new, nullptr);
+        sync_scal(s);
+        const double* h = s->hscal;
+        if (trace) {
+          HC(hipMemcpy(s->hstage, s->Edev, sizeof(double), hipMemcpyDeviceToHost));
+          std::fprintf(stderr,
+                       "[pff] inc %d it %d krylov %d relres %.2e | E=%.12e |F1|=%.6e |F2|=%.6e F3=%.6e "
+                       "|w|/|eps|=%.2e |dphi|/|phi|=%.2e\n",
+                       s->n + 1, it, kit, rr, s->hstage[0], std::sqrt(h[SC_F1]), std::sqrt(h[SC_F2]),
+                       h[SC_GAMMA] - a_new, std::sqrt(h[SC_NW] / h[SC_NEPS]), std::sqrt(h[SC_NDPHI] / h[SC_NPHI]));
+        }
+        err[0] = std::sqrt(h[SC_NW]) / std::sqrt(h[SC_NEPS]);
+        err[1] = std::sqrt(h[SC_NDPHI]) / std::sqrt(h[SC_NPHI]);
+        err[2] = std::fabs(h[SC_GAMMA] - a_new) / std::fabs(a_new);
+        const double e = std::max(err[0], std::max(err[1], err[2]));
+        if (e <= s->prm.newton_tol) {
+          conv = 1;
+          break;
+        }
+        if (!std::isfinite(e)) break;
+      }
+      (void)sizeof(TW);
+    });
+    if (it > s->prm.newton_maxit) it = s->prm.newton_maxit;
+    const int g = grid1(N);
+    if (out) {
+      std::memset(out, 0, sizeof(*out));
+      out->increment = s->n + 1;
+      out->newton_iters = it;
+      out->krylov_iters = (int)(s->kiters - ki0);
+      out->applies = s->applies - ap0;
+      out->converged = conv;
+      out->target_a = a_new;
+      for (int q = 0; q < 3; ++q) out->err[q] = err[q];
+    }
+    if (!conv) {
+      // roll back to the committed increment
+      HC(hipMemcpyAsync(s->eps_t, s->eps_c, C * N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+      HC(hipMemcpyAsync(s->phi, s->phi_c, N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+      HC(hipStreamSynchronize(s->stream));
+      s->ts_valid = false;
+      if (out) out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      return PFF_NOT_CONVERGED;
+    }
+    k_commit_history<<<g, kBlock, 0, s->stream>>>(s->Hn, s->Hcur, N);
+    LAUNCH_CHECK();
+    HC(hipMemcpyAsync(s->eps_c, s->eps_t, C * N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    HC(hipMemcpyAsync(s->phi_c, s->phi, N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    HC(hipMemcpyAsync(s->hstage, s->Edev, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HC(hipStreamSynchronize(s->stream));
+    const double Ecur = s->hstage[0];
+    s->E = Ecur;
+    s->a = a_new;
+    s->n += 1;
+    s->ts_valid = false;
+    if (out) {
+      for (int q = 0; q < 6; ++q) out->sigma_M[q] = s->hscal[SC_SIG + q] / double(N);
+      out->load_factor = Ecur;
+      out->crack_length = s->hscal[SC_GAMMA];
+      out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return PFF_OK;
+  });
+}
+
+pff_status pff_get_state(pff_solver* s, double* eps_total, double* phi, double* Hn, double* E, double* a) {
+  return guarded(s, [&]() -> pff_status {
+    const long long N = s->N;
+    const int C = s->C;
+    HC(hipStreamSynchronize(s->stream));
+    if (eps_total) {
+      HC(hipMemcpy(eps_total, s->eps_c, C * N * sizeof(double), hipMemcpyDeviceToHost));
+      for (int k = 0; k < C; ++k)
+        for (long long i = 0; i < N; ++i) eps_total[k * N + i] += s->fm[k] * s->E;
+    }
+    if (phi) HC(hipMemcpy(phi, s->phi_c, N * sizeof(double), hipMemcpyDeviceToHost));
+    if (Hn) HC(hipMemcpy(Hn, s->Hn, N * sizeof(double), hipMemcpyDeviceToHost));
+    if (E) *E = s->E;
+    if (a) *a = s->a;
+    return PFF_OK;
+  });
+}
+
+pff_status pff_set_state(pff_solver* s, const double* eps_tilde, const double* phi, const double* Hn, double E,
+                         double a, int n) {
+  return guarded(s, [&]() -> pff_status {
+    if (!eps_tilde || !phi || !Hn || n < 0) throw Fail("pff_set_state: null buffer", PFF_ERR_ARG);
+    const long long N = s->N;
+    const int C = s->C;
+    HC(hipStreamSynchronize(s->stream));
+    HC(hipMemcpy(s->eps_c, eps_tilde, C * N * sizeof(double), hipMemcpyHostToDevice));
+    HC(hipMemcpy(s->eps_t, eps_tilde, C * N * sizeof(double), hipMemcpyHostToDevice));
+    HC(hipMemcpy(s->phi_c, phi, N * sizeof(double), hipMemcpyHostToDevice));
+    HC(hipMemcpy(s->phi, phi, N * sizeof(double), hipMemcpyHostToDevice));
+    HC(hipMemcpy(s->Hn, Hn, N * sizeof(double), hipMemcpyHostToDevice));
+    double e2[2] = {E, E};
+    HC(hipMemcpy(s->Edev, e2, 2 * sizeof(double), hipMemcpyHostToDevice));
+    s->E = E;
+    s->a = a;
+    s->n = n;
+    s->E_s = 0.0;
+    s->bootstrapped = true;
+    s->ts_valid = false;
+    return PFF_OK;
+  });
+}
+
+pff_status pff_residual(pff_solver* s, double a, double* F_dev, double* gamma, double* sigma_M) {
+  return guarded(s, [&]() -> pff_status {
+    dispatch(s, [&](auto impl) {
+      using I = decltype(impl);
+      I::residual(s, a, F_dev);
+    });
+    sync_scal(s);
+    if (gamma) *gamma = s->hscal[SC_GAMMA];
+    if (sigma_M)
+      for (int q = 0; q < 6; ++q) sigma_M[q] = s->hscal[SC_SIG + q] / double(s->N);
+    return PFF_OK;
+  });
+}
+
+pff_status pff_apply_tangent(pff_solver* s, const void* v_dev, void* Jv_dev) {
+  return guarded(s, [&]() -> pff_status {
+    if (!v_dev || !Jv_dev || v_dev == Jv_dev) throw Fail("pff_apply_tangent: bad buffers", PFF_ERR_ARG);
+    if (!s->ts_valid) throw Fail("pff_apply_tangent: no tangent state (call pff_residual)", PFF_ERR_STATE);
+    dispatch(s, [&](auto impl) {
+      using I = decltype(impl);
+      using TW = typename std::remove_pointer<decltype(I::vec(s, 0))>::type;
+      I::apply(s, static_cast<const TW*>(v_dev), static_cast<TW*>(Jv_dev));
+    });
+    return PFF_OK;
+  });
+}
+
+pff_status pff_project(pff_solver* s, const void* in_dev, void* out_dev, int prec) {
+  return guarded(s, [&]() -> pff_status {
+    if (!in_dev || !out_dev || (prec != 0 && prec != 1)) throw Fail("pff_project: bad arguments", PFF_ERR_ARG);
+    auto go = [&](auto tag, auto dimc) {
+      using T = decltype(tag);
+      constexpr int DIM = decltype(dimc)::value;
+      typename ProjectPipe<T, DIM>::Args A;
+      A.g = s->g;
+      A.in = static_cast<const T*>(in_dev);
+      A.out = static_cast<T*>(out_dev);
+      A.tab = spec_tables<T>(s);
+      int nblk = 0;
+      if (std::is_same<T, float>::value && !s->spec_f) s->spec_f = s->alloc<cpx<float>>((size_t)(s->C + 1) * s->Nh);
+      run_pipeline<ProjectPipe<T, DIM>>(s, A, nblk);
+    };
+    if (s->dim == 2) {
+      if (prec == 0) go(double(), std::integral_constant<int, 2>());
+      else go(float(), std::integral_constant<int, 2>());
+    } else {
+      if (prec == 0) go(double(), std::integral_constant<int, 3>());
+      else go(float(), std::integral_constant<int, 3>());
+    }
+    HC(hipStreamSynchronize(s->stream));
+    return PFF_OK;
+  });
+}
+
+pff_status pff_krylov_solve(pff_solver* s, const void* b_dev, void* x_dev, double rtol, int maxit, int* iters,
+                            double* relres) {
+  return guarded(s, [&]() -> pff_status {
+    if (!b_dev || !x_dev || !(rtol > 0) || maxit < 1) throw Fail("pff_krylov_solve: bad arguments", PFF_ERR_ARG);
+    if (!s->ts_valid) throw Fail("pff_krylov_solve: no tangent state (call pff_residual)", PFF_ERR_STATE);
+    int conv = 0;
+    dispatch(s, [&](auto impl) {
+      using I = decltype(impl);
+      using TW = typename std::remove_pointer<decltype(I::vec(s, 0))>::type;
+      conv = I::bicgstab(s, static_cast<const TW*>(b_dev), static_cast<TW*>(x_dev), rtol, maxit, iters, relres);
+    });
+    HC(hipStreamSynchronize(s->stream));
+    return conv ? PFF_OK : PFF_NOT_CONVERGED;
+  });
+}
+
+pff_status pff_counters(pff_solver* s, long long* applies, long long* krylov_iters) {
+  return guarded(s, [&]() -> pff_status {
+    if (applies) *applies = s->applies;
+    if (krylov_iters) *krylov_iters = s->kiters;
+    return PFF_OK;
+  });
+}
+
+pff_status pff_save(pff_solver* s, void* buf, size_t* bytes) {
+  return guarded(s, [&]() -> pff_status {
+    if (!bytes) throw Fail("pff_save: bytes is NULL", PFF_ERR_ARG);
+    const long long N = s->N;
+    const int C = s->C;
+    const size_t need = 64 + (size_t)(C + 2) * N * sizeof(double);
+    if (!buf) {
+      *bytes = need;
+      return PFF_OK;
+    }
+    if (*bytes < need) throw Fail("pff_save: buffer too small", PFF_ERR_ARG);
+    HC(hipStreamSynchronize(s->stream));
+    unsigned char* b = static_cast<unsigned char*>(buf);
+    std::memset(b, 0, 64);
+    const int hdr[6] = {0x50464631, s->nx, s->ny, s->nz, s->n, s->bootstrapped ? 1 : 0};
+    std::memcpy(b, hdr, sizeof(hdr));
+    const double sc[3] = {s->E, s->a, s->E_s};
+    std::memcpy(b + 32, sc, sizeof(sc));
+    double* d = reinterpret_cast<double*>(b + 64);
+    HC(hipMemcpy(d, s->eps_c, C * N * sizeof(double), hipMemcpyDeviceToHost));
+    HC(hipMemcpy(d + C * N, s->phi_c, N * sizeof(double), hipMemcpyDeviceToHost));
+    HC(hipMemcpy(d + (C + 1) * N, s->Hn, N * sizeof(double), hipMemcpyDeviceToHost));
+    *bytes = need;
+    return PFF_OK;
+  });
+}
+
+pff_status pff_load(pff_solver* s, const void* buf, size_t bytes) {
+  return guarded(s, [&]() -> pff_status {
+    const long long N = s->N;
+    const int C = s->C;
+    const size_t need = 64 + (size_t)(C + 2) * N * sizeof(double);
+    if (!buf || bytes < need) throw Fail("pff_load: buffer too small", PFF_ERR_ARG);
+    const unsigned char* b = static_cast<const unsigned char*>(buf);
+    int hdr[6];
+    std::memcpy(hdr, b, sizeof(hdr));
+    if (hdr[0] != 0x50464631 || hdr[1] != s->nx || hdr[2] != s->ny || hdr[3] != s->nz)
+      throw Fail("pff_load: checkpoint does not match this grid", PFF_ERR_ARG);
+    double sc[3];
+    std::memcpy(sc, b + 32, sizeof(sc));
+    const double* d = reinterpret_cast<const double*>(b + 64);
+    HC(hipStreamSynchronize(s->stream));
+    HC(hipMemcpy(s->eps_c, d, C * N * sizeof(double), hipMemcpyHostToDevice));
+    HC(hipMemcpy(s->eps_t, d, C * N * sizeof(double), hipMemcpyHostToDevice));
+    HC(hipMemcpy(s->phi_c, d + C * N, N * sizeof(double), hipMemcpyHostToDevice));
+    HC(hipMemcpy(s->phi, d + C * N, N * sizeof(double), hipMemcpyHostToDevice));
+    HC(hipMemcpy(s->Hn, d + (C + 1) * N, N * sizeof(double), hipMemcpyHostToDevice));
+    s->n = hdr[4];
+    s->bootstrapped = hdr[5] != 0;
+    s->E = sc[0];
+    s->a = sc[1];
+    s->E_s = sc[2];
+    s->ts_valid = false;
+    if (s->n == 0 && s->bootstrapped) {
+      // the first-increment guess is rebuilt by pff_bootstrap; resume only after an increment
+      s->bootstrapped = false;
+    }
+    return PFF_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,261 @@
+// Pipes: the point-wise stages plugged into the FFT passes.
+//
+//   TangentPipe   the tangent action dF(q; dq) of the crack-length system
+//                 (paper Sec. 3.2, eq. CrackLength_linearization, with the
+//                 history derivative of eq. Delta_history);
+//   ResidualPipe  the constitutive update and the residual F(q) (eqs.
+//                 System_CrackLength, newGammaFourier, history) in FP64;
+//   HelmPipe      (1-m)(1/l - l Lap)(.) for the damage bootstrap;
+//   ProjectPipe   plain projection of C fields and Laplacian of one field.
+//
+// Layouts (N voxels, x fastest; C = 3 in plane strain, 6 in 3D; Mandel
+// components): a Krylov vector is [d eps (C*N) | d phi (N) | dE (1)]; the
+// tangent state ts is [eps (C*N) | phi (N) | Hs (N) | r (N)] where
+// Hs = -H when the history is loading (psi0(+) >= Hn) and +H otherwise, and
+// r = phi/l - l Lap(phi) is the crack-length gradient.
+#pragma once
+
+#include "passes.hpp"
+#include "pointlaw.hpp"
+
+namespace pff {
+
+template <typename T, int DIM>
+struct TangentPipe {
+  using real = T;
+  static constexpr int C = DIM == 2 ? 3 : 6;
+  static constexpr int D = DIM == 2 ? 2 : 3;
+  static constexpr int NF = C + 1;
+  static constexpr int NRED_PRO = 1;
+  static constexpr int NRED_EPI = 0;
+  struct Args {
+    GridDesc g;
+    Material mat;
+    T l, k;
+    T f[6];
+    const T* ts;
+    const uint8_t* pid;
+    const uint8_t* mask;
+    const T* v;
+    T* Jv;
+    T* aux;
+    SpecTables<T> tab;
+  };
+
+  __device__ static void prologue(const Args& A, long long i, T* out, double* red) {
+    const long long N = A.g.N;
+    const int p = A.pid[i];
+    const bool m = A.mask[i] != 0;
+    const T lam = T(A.mat.lam[p]), mu = T(A.mat.mu[p]), Gc = T(A.mat.Gc[p]);
+    const T dE = A.v[(long long)(C + 1) * N];
+    T eps[C], w[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      eps[k] = A.ts[k * N + i];
+      w[k] = A.v[k * N + i] + A.f[k] * dE;
+    }
+    const T phi = A.ts[C * N + i];
+    const T Hs = A.ts[(C + 1) * N + i];
+    const T r = A.ts[(C + 2) * N + i];
+    const T dphi = A.v[C * N + i];
+    const T dphf = m ? T(0) : dphi;
+    Split<T, D> sp;
+    split_eval<T, D>(eps, lam, mu, sp);
+    const T g = (T(1) - phi) * (T(1) - phi) + A.k;
+    T Cw[C];
+    tangent_apply<T, D>(sp, lam, mu, g, w, Cw);
+    T S[D][D];
+    sigma0<T, D, true>(sp, lam, mu, S);
+    T b[C];
+    tensor_to_mandel<T, D>(S, b);
+    const T gp = T(-2) * (T(1) - phi);            // g'(phi)
+    T bw = T(0);
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      b[k] *= gp;
+      out[k] = Cw[k] + b[k] * dphf;
+      bw += b[k] * w[k];
+    }
+    out[C] = dphf;
+    const bool chi = signbit(Hs);
+    const T H = fabs(Hs);
+    const T s = m ? dphi : (chi ? bw : T(0)) + (Gc / A.l + T(2) * H) * dphf;
+    A.aux[i] = s;
+    red[0] += double(r) * double(dphf);
+  }
+
+  __device__ static void spectral(const Args& A, int kx, int ky, int kz, cpx<T>* v) {
+    spectral_proj_lap<T, DIM, C, true>(A.tab, kx, ky, kz, v);
+  }
+
+  __device__ static void epilogue(const Args& A, long long i, const T* in, double*) {
+    const long long N = A.g.N;
+#pragma unroll
+    for (int k = 0; k < C; ++k) A.Jv[k * N + i] = in[k];
+    const bool m = A.mask[i] != 0;
+    const T Gc = T(A.mat.Gc[A.pid[i]]);
+    A.Jv[C * N + i] = A.aux[i] - (m ? T(0) : Gc * A.l * in[C]);
+  }
+};
+
+template <int DIM, typename TW>
+struct ResidualPipe {
+  using real = double;
+  static constexpr int C = DIM == 2 ? 3 : 6;
+  static constexpr int D = DIM == 2 ? 2 : 3;
+  static constexpr int NF = C + 1;
+  static constexpr int NRED_PRO = 6;   // sum of sigma: 11, 22, 33, 23, 13, 12
+  static constexpr int NRED_EPI = 3;   // Gamma, ||F1||^2, ||F2||^2
+  struct Args {
+    GridDesc g;
+    Material mat;
+    double l, k;
+    double f[6];
+    const double* eps_t;
+    const double* phi;
+    const double* Hn;
+    double* Hcur;
+    const double* E;
+    TW* ts;
+    TW* rhs;
+    double* F;
+    const uint8_t* pid;
+    const uint8_t* mask;
+    SpecTables<double> tab;
+  };
+
+  __device__ static void prologue(const Args& A, long long i, double* out, double* red) {
+    const long long N = A.g.N;
+    const int p = A.pid[i];
+    const double lam = A.mat.lam[p], mu = A.mat.mu[p];
+    const double E = *A.E;
+    double eps[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) eps[k] = A.eps_t[k * N + i] + A.f[k] * E;
+    const double phi = A.phi[i];
+    const double Hn = A.Hn[i];
+    Split<double, D> sp;
+    split_eval<double, D>(eps, lam, mu, sp);
+    const double g = (1.0 - phi) * (1.0 - phi) + A.k;
+    double Sp[D][D], Sm[D][D], Sg[D][D];
+    sigma0<double, D, true>(sp, lam, mu, Sp);
+    sigma0<double, D, false>(sp, lam, mu, Sm);
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) Sg[a][b] = g * Sp[a][b] + Sm[a][b];
+    double sm[C];
+    tensor_to_mandel<double, D>(Sg, sm);
+    const double H = sp.psi_p > Hn ? sp.psi_p : Hn;
+    const bool chi = sp.psi_p >= Hn;
+    const double Hs = chi ? -H : H;
+    A.Hcur[i] = Hs;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      A.ts[k * N + i] = TW(eps[k]);
+      out[k] = sm[k];
+    }
+    A.ts[C * N + i] = TW(phi);
+    A.ts[(C + 1) * N + i] = TW(Hs);
+    out[C] = phi;
+    if constexpr (DIM == 2) {
+      const double trp = sp.tr > 0.0 ? sp.tr : 0.0, trm = sp.tr < 0.0 ? sp.tr : 0.0;
+      red[0] += Sg[0][0];
+      red[1] += Sg[1][1];
+      red[2] += g * lam * trp + lam * trm;     // sigma_zz of plane strain
+      red[5] += Sg[0][1];
+    } else {
+      red[0] += Sg[0][0];
+      red[1] += Sg[1][1];
+      red[2] += Sg[2][2];
+      red[3] += Sg[1][2];
+      red[4] += Sg[0][2];
+      red[5] += Sg[0][1];
+    }
+  }
+
+  __device__ static void spectral(const Args& A, int kx, int ky, int kz, cpx<double>* v) {
+    spectral_proj_lap<double, DIM, C, true>(A.tab, kx, ky, kz, v);
+  }
+
+  __device__ static void epilogue(const Args& A, long long i, const double* in, double* red) {
+    const long long N = A.g.N;
+    const bool m = A.mask[i] != 0;
+    const double Gc = A.mat.Gc[A.pid[i]];
+    const double phi = A.phi[i];
+    const double H = fabs(A.Hcur[i]);
+    const double lap = in[C];
+    const double l = A.l;
+    const double F2 = m ? 0.0 : (Gc / l + 2.0 * H) * phi - Gc * l * lap - 2.0 * H;
+    A.ts[(C + 2) * N + i] = TW(phi / l - l * lap);
+    double f1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      A.rhs[k * N + i] = TW(-in[k]);
+      if (A.F) A.F[k * N + i] = in[k];
+      f1 += in[k] * in[k];
+    }
+    A.rhs[C * N + i] = TW(-F2);
+    if (A.F) A.F[C * N + i] = F2;
+    red[0] += phi * phi / (2.0 * l) - 0.5 * l * phi * lap;
+    red[1] += f1;
+    red[2] += F2 * F2;
+  }
+};
+
+struct HelmPipe {
+  using real = double;
+  static constexpr int NF = 1;
+  static constexpr int NRED_PRO = 0;
+  static constexpr int NRED_EPI = 0;
+  struct Args {
+    GridDesc g;
+    double l;
+    const double* u;
+    double* out;
+    int mask_input;          // 1: operator (1-m) B (1-m); 0: (1-m) B
+    const uint8_t* mask;
+    SpecTables<double> tab;
+  };
+  __device__ static void prologue(const Args& A, long long i, double* out, double*) {
+    const bool m = A.mask[i] != 0;
+    out[0] = (A.mask_input && m) ? 0.0 : A.u[i];
+  }
+  __device__ static void spectral(const Args& A, int kx, int ky, int kz, cpx<double>* v) {
+    if (A.g.nz == 1) spectral_proj_lap<double, 2, 0, true>(A.tab, kx, ky, kz, v);
+    else spectral_proj_lap<double, 3, 0, true>(A.tab, kx, ky, kz, v);
+  }
+  __device__ static void epilogue(const Args& A, long long i, const double* in, double*) {
+    const bool m = A.mask[i] != 0;
+    const double u = (A.mask_input && m) ? 0.0 : A.u[i];
+    A.out[i] = m ? 0.0 : u / A.l - A.l * in[0];
+  }
+};
+
+template <typename T, int DIM>
+struct ProjectPipe {
+  using real = T;
+  static constexpr int C = DIM == 2 ? 3 : 6;
+  static constexpr int NF = C + 1;
+  static constexpr int NRED_PRO = 0;
+  static constexpr int NRED_EPI = 0;
+  struct Args {
+    GridDesc g;
+    const T* in;
+    T* out;
+    SpecTables<T> tab;
+  };
+  __device__ static void prologue(const Args& A, long long i, T* out, double*) {
+#pragma unroll
+    for (int k = 0; k < NF; ++k) out[k] = A.in[k * A.g.N + i];
+  }
+  __device__ static void spectral(const Args& A, int kx, int ky, int kz, cpx<T>* v) {
+    spectral_proj_lap<T, DIM, C, true>(A.tab, kx, ky, kz, v);
+  }
+  __device__ static void epilogue(const Args& A, long long i, const T* in, double*) {
+#pragma unroll
+    for (int k = 0; k < NF; ++k) A.out[k * A.g.N + i] = in[k];
+  }
+};
+
+}  // namespace pff

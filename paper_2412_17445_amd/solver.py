@@ -1,0 +1,181 @@
+"""Python wrapper of the C ABI (marshalling only; all compute is in libpff.so).
+
+PyTorch provides device memory and the HIP stream: tensors handed to the
+library are HIP device buffers, and the solver queues its work on the
+stream that was current when it was created.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+
+class PffError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"pff status {status}: {msg}")
+        self.status = status
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device: the solver runs only on the GPU")
+    return torch
+
+
+class Solver:
+    """One RVE solve.  `precision` is "fp64" or "mixed"."""
+
+    def __init__(self, shape, phases, phase_id, mask, f, l, k=1e-6, delta_a=1.0, alpha=1.0,
+                 newton_tol=1e-8, krylov_rtol=1e-10, newton_maxit=50, krylov_maxit=5000,
+                 precision="fp64", stream=None):
+        torch = _torch()
+        self.lib = L.load()
+        nz, ny, nx = shape
+        self.shape = (nz, ny, nx)
+        self.N = nx * ny * nz
+        self.ncomp = 3 if nz == 1 else 6
+        self.M = (self.ncomp + 1) * self.N + 1
+        self.mixed = precision == "mixed"
+        self.wdtype = torch.float32 if self.mixed else torch.float64
+        grid = L.pff_grid(nx, ny, nz)
+        ph = (L.pff_phase * len(phases))(*[L.pff_phase(*map(float, p)) for p in phases])
+        pid = np.ascontiguousarray(np.asarray(phase_id, dtype=np.uint8).reshape(-1))
+        msk = None if mask is None else np.ascontiguousarray(
+            np.asarray(mask, dtype=np.uint8).reshape(-1))
+        prm = L.pff_params()
+        prm.l, prm.k_resid = float(l), float(k)
+        fa = np.asarray(f, dtype=np.float64).reshape(3, 3)
+        for i in range(9):
+            prm.f[i] = float(fa.reshape(-1)[i])
+        prm.delta_a, prm.alpha = float(delta_a), float(alpha)
+        prm.newton_tol, prm.krylov_rtol = float(newton_tol), float(krylov_rtol)
+        prm.newton_maxit, prm.krylov_maxit = int(newton_maxit), int(krylov_maxit)
+        prm.precision = L.PFF_PREC_MIXED if self.mixed else L.PFF_PREC_FP64
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self._stream = stream
+        h = C.c_void_p()
+        st = self.lib.pff_create(C.byref(grid), ph, len(phases), pid.ctypes.data,
+                                 None if msk is None else msk.ctypes.data, C.byref(prm),
+                                 C.c_void_p(stream), C.byref(h))
+        if st != L.PFF_OK:
+            raise PffError(st, "pff_create failed")
+        self.h = h
+
+    @classmethod
+    def from_problem(cls, prob, **over):
+        kw = dict(k=prob.k, delta_a=prob.delta_a, alpha=prob.alpha, newton_tol=prob.newton_tol,
+                  krylov_rtol=prob.krylov_rtol, newton_maxit=prob.newton_maxit,
+                  krylov_maxit=prob.krylov_maxit, precision=prob.precision)
+        kw.update(over)
+        return cls(prob.shape, prob.phases, prob.phase_id, prob.mask, prob.f, prob.l, **kw)
+
+    # -- helpers ------------------------------------------------------------
+    def _check(self, st, what):
+        if st < 0:
+            msg = self.lib.pff_last_error(self.h)
+            raise PffError(st, f"{what}: {msg.decode() if msg else ''}")
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pff_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- solver -------------------------------------------------------------
+    def bootstrap(self):
+        a0, es = C.c_double(), C.c_double()
+        self._check(self.lib.pff_bootstrap(self.h, C.byref(a0), C.byref(es)), "pff_bootstrap")
+        return a0.value, es.value
+
+    def step(self):
+        r = L.pff_increment_result()
+        st = self._check(self.lib.pff_step(self.h, C.byref(r)), "pff_step")
+        return dict(status=st, increment=r.increment, newton_iters=r.newton_iters,
+                    krylov_iters=r.krylov_iters, converged=bool(r.converged), applies=r.applies,
+                    sigma_M=list(r.sigma_M), E=r.load_factor, Gamma=r.crack_length,
+                    a=r.target_a, err=list(r.err), seconds=r.seconds)
+
+    def get_state(self):
+        c, N = self.ncomp, self.N
+        eps = np.empty(c * N)
+        phi = np.empty(N)
+        Hn = np.empty(N)
+        E, a = C.c_double(), C.c_double()
+        self._check(self.lib.pff_get_state(self.h, eps.ctypes.data, phi.ctypes.data,
+                                           Hn.ctypes.data, C.byref(E), C.byref(a)),
+                    "pff_get_state")
+        return (eps.reshape((c,) + self.shape), phi.reshape(self.shape),
+                Hn.reshape(self.shape), E.value, a.value)
+
+    def set_state(self, eps_tilde, phi, Hn, E, a, n=1):
+        e = np.ascontiguousarray(eps_tilde, dtype=np.float64).reshape(-1)
+        p = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1)
+        h = np.ascontiguousarray(Hn, dtype=np.float64).reshape(-1)
+        self._check(self.lib.pff_set_state(self.h, e.ctypes.data, p.ctypes.data, h.ctypes.data,
+                                           float(E), float(a), int(n)), "pff_set_state")
+
+    def residual(self, a, want_F=True):
+        torch = _torch()
+        F = torch.empty(self.M, dtype=torch.float64, device="cuda") if want_F else None
+        gam = C.c_double()
+        sig = (C.c_double * 6)()
+        self._check(self.lib.pff_residual(self.h, float(a), None if F is None else F.data_ptr(),
+                                          C.byref(gam), sig), "pff_residual")
+        return F, gam.value, list(sig)
+
+    def apply(self, v, out=None):
+        torch = _torch()
+        if v.dtype != self.wdtype or v.numel() != self.M or not v.is_cuda:
+            raise ValueError("v must be a contiguous device vector of the working precision")
+        v = v.contiguous()
+        if out is None:
+            out = torch.empty_like(v)
+        self._check(self.lib.pff_apply_tangent(self.h, v.data_ptr(), out.data_ptr()),
+                    "pff_apply_tangent")
+        return out
+
+    def project(self, x):
+        torch = _torch()
+        prec = 1 if x.dtype == torch.float32 else 0
+        x = x.contiguous()
+        out = torch.empty_like(x)
+        self._check(self.lib.pff_project(self.h, x.data_ptr(), out.data_ptr(), prec), "pff_project")
+        return out
+
+    def krylov_solve(self, b, rtol=1e-10, maxit=5000):
+        torch = _torch()
+        b = b.contiguous()
+        x = torch.empty_like(b)
+        it, rr = C.c_int(), C.c_double()
+        st = self._check(self.lib.pff_krylov_solve(self.h, b.data_ptr(), x.data_ptr(), float(rtol),
+                                                   int(maxit), C.byref(it), C.byref(rr)),
+                         "pff_krylov_solve")
+        return x, it.value, rr.value, st == L.PFF_OK
+
+    def counters(self):
+        a, k = C.c_longlong(), C.c_longlong()
+        self._check(self.lib.pff_counters(self.h, C.byref(a), C.byref(k)), "pff_counters")
+        return a.value, k.value
+
+    def save(self):
+        n = C.c_size_t()
+        self._check(self.lib.pff_save(self.h, None, C.byref(n)), "pff_save")
+        buf = (C.c_ubyte * n.value)()
+        self._check(self.lib.pff_save(self.h, buf, C.byref(n)), "pff_save")
+        return bytes(buf)
+
+    def load(self, data):
+        buf = (C.c_ubyte * len(data)).from_buffer_copy(data)
+        self._check(self.lib.pff_load(self.h, buf, len(data)), "pff_load")

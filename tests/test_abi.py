@@ -1,0 +1,94 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load, export every function that include/pff.h declares
+with the binding's names, and reject invalid arguments before touching the
+device.
+"""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2412_17445_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pff.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(L.LIB_PATH),
+                                reason="libpff.so not built (run __graft_entry__.build())")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pff_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(L.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert lib.pff_abi_version() == 1
+
+
+def test_struct_layouts():
+    assert C.sizeof(L.pff_grid) == 12
+    assert C.sizeof(L.pff_phase) == 24
+    # 4 doubles + f[9] + 3 doubles, then 3 ints (+ padding)
+    assert C.sizeof(L.pff_params) == 8 * (2 + 9 + 4) + 4 * 3 + 4
+    assert C.sizeof(L.pff_increment_result) == 4 * 4 + 8 + 8 * (6 + 3 + 3 + 1)
+
+
+def _params(**kw):
+    p = L.pff_params()
+    p.l, p.k_resid, p.delta_a, p.alpha = 2.0, 1e-6, 1.0, 1.0
+    p.newton_tol, p.krylov_rtol, p.newton_maxit, p.krylov_maxit = 1e-8, 1e-10, 50, 100
+    p.f[4] = 1.0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _create(grid, phases, pid, params):
+    lib = L.load()
+    h = C.c_void_p()
+    ph = (L.pff_phase * len(phases))(*phases)
+    st = lib.pff_create(C.byref(grid), ph, len(phases), pid, None, C.byref(params), None, C.byref(h))
+    return st, h
+
+
+def test_invalid_arguments_rejected_before_device_work():
+    lib = L.load()
+    h = C.c_void_p()
+    assert lib.pff_create(None, None, 0, None, None, None, None, C.byref(h)) == L.PFF_ERR_ARG
+    pid = (C.c_ubyte * 64)()
+    ok_phase = [L.pff_phase(1.0, 0.3, 1e-3)]
+    # grid sizes with a factor 5 (no radix-5 FFT)
+    st, h = _create(L.pff_grid(10, 8, 1), ok_phase, pid, _params())
+    assert st == L.PFF_ERR_ARG and not h.value
+    # too many phases
+    st, h = _create(L.pff_grid(8, 8, 1), ok_phase * 17, pid, _params())
+    assert st == L.PFF_ERR_ARG
+    # relaxation out of range
+    st, h = _create(L.pff_grid(8, 8, 1), ok_phase, pid, _params(alpha=1.5))
+    assert st == L.PFF_ERR_ARG
+    # asymmetric f
+    p = _params()
+    p.f[1] = 0.5
+    st, h = _create(L.pff_grid(8, 8, 1), ok_phase, pid, p)
+    assert st == L.PFF_ERR_ARG
+    # 2D with out-of-plane loading
+    p = _params()
+    p.f[8] = 1.0
+    st, h = _create(L.pff_grid(8, 8, 1), ok_phase, pid, p)
+    assert st == L.PFF_ERR_ARG
+    # null handle calls
+    assert lib.pff_step(None, None) == L.PFF_ERR_ARG
+    assert lib.pff_last_error(None) == b"null handle"
+    lib.pff_destroy(None)

@@ -1,0 +1,127 @@
+"""GPU parity of the hot-path steps against the oracle (same seeded inputs).
+
+Steps (a3)-(a5): projection + Laplacian through the FFT passes;
+(a1)+(a8): constitutive update and FP64 residual; (a2)-(a6): tangent action;
+(a7): BiCGSTAB.  Tolerances: FP64 1e-11 relative (FFT round-off grows like
+log N eps), FP32 1e-5 relative.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import fourier as fo
+from oracle.system import System
+from synth import problem_config, random_state, random_vector
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def gpu_solver(prob, **kw):
+    from paper_2412_17445_amd import Solver
+    return Solver.from_problem(prob, **kw)
+
+
+def small_problem(name, shape=None, precision="fp64"):
+    prob = problem_config(name)
+    if shape is not None:
+        prob.shape = shape
+        rng = np.random.default_rng(5)
+        prob.phase_id = (rng.uniform(size=shape) < 0.3).astype(np.uint8) if len(prob.phases) > 1 \
+            else np.zeros(shape, np.uint8)
+        if prob.mask is not None:
+            m = np.zeros(shape, np.uint8)
+            m[shape[0] // 2, shape[1] // 2, shape[2] // 4: shape[2] // 2] = 1
+            prob.mask = m
+    prob.precision = precision
+    return prob
+
+
+SHAPES = [("tiny16", None), ("tiny16", (1, 12, 18)), ("fib64", None), ("pore24", None),
+          ("part24", (12, 18, 16)), ("part24", (9, 8, 6))]
+
+
+def rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
+
+
+@pytest.mark.parametrize("name,shape", SHAPES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_projection_and_laplacian(name, shape, prec):
+    prob = small_problem(name, shape)
+    s = gpu_solver(prob)
+    c = 3 if prob.shape[0] == 1 else 6
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((c + 1,) + tuple(prob.shape))
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    out = s.project(torch.tensor(x.reshape(-1), dtype=dt, device="cuda")).double().cpu().numpy()
+    out = out.reshape(x.shape)
+    refG = fo.G_mandel(x[:c])
+    refL = fo.laplacian(x[c])
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    assert rel(out[:c], refG) < tol
+    assert rel(out[c], refL) < tol
+
+
+def _frozen_state(sysm, seed):
+    eps, phi, Hn, E = random_state(sysm.shape, sysm.ncomp, seed, f_mandel=sysm.f, E=0.01)
+    eps_t = fo.G_mandel(eps - sysm.fE(E))
+    st = sysm.point(eps_t + sysm.fE(E), phi, np.zeros(sysm.shape))
+    rng = np.random.default_rng(seed + 1)
+    Hn = st["psi_p"] * np.where(rng.uniform(size=sysm.shape) < 0.5, 0.7, 1.3)
+    phi = np.where(sysm.m > 0, 1.0, phi)
+    return eps_t, phi, E, Hn
+
+
+@pytest.mark.parametrize("name,shape", SHAPES)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_residual_and_tangent(name, shape, precision):
+    prob = small_problem(name, shape, precision)
+    sysm = System(prob)
+    eps_t, phi, E, Hn = _frozen_state(sysm, 3)
+    a = 2.5
+    s = gpu_solver(prob)
+    s.set_state(eps_t, phi, Hn, E, a - 1.0, n=1)
+    F, gam, sig = s.residual(a)
+    R = sysm.residual(eps_t, phi, E, Hn, a)
+    F = F.cpu().numpy()
+    c, N = sysm.ncomp, sysm.N
+    assert rel(F[: c * N], R["F1"].ravel()) < 1e-11
+    assert rel(F[c * N:(c + 1) * N], R["F2"].ravel()) < 1e-11
+    assert abs(F[-1] - R["F3"]) <= 1e-12 * abs(R["Gamma"])
+    assert abs(gam - R["Gamma"]) <= 1e-12 * abs(R["Gamma"])
+    sM = R["sigma_M"]
+    ref_sig = [sM[0, 0], sM[1, 1], sM[2, 2], sM[1, 2], sM[0, 2], sM[0, 1]]
+    assert rel(sig, ref_sig) < 1e-12
+    # tangent action on a seeded vector
+    v = random_vector(sysm.N * (c + 1) + 1, 9) * 1e-3
+    J = sysm.tangent(eps_t, phi, E, Hn)
+    ref = J(v)
+    dt = torch.float32 if precision == "mixed" else torch.float64
+    Jv = s.apply(torch.tensor(v, dtype=dt, device="cuda")).double().cpu().numpy()
+    tol = 1e-11 if precision == "fp64" else 2e-5
+    for blk in (slice(0, c * N), slice(c * N, (c + 1) * N)):
+        assert rel(Jv[blk], ref[blk]) < tol
+    r = phi / sysm.l - sysm.l * fo.laplacian(phi)
+    scale = np.sum(np.abs(r * (1 - sysm.m) * v[c * N:(c + 1) * N].reshape(sysm.shape)))
+    assert abs(Jv[-1] - ref[-1]) <= tol * scale
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["tiny16", "pore24"])
+def test_krylov_solve(name):
+    prob = small_problem(name)
+    sysm = System(prob)
+    eps_t, phi, E, Hn = _frozen_state(sysm, 4)
+    s = gpu_solver(prob)
+    s.set_state(eps_t, phi, Hn, E, 1.0, n=1)
+    F, _, _ = s.residual(2.0)
+    b = -F
+    x, it, rr, ok = s.krylov_solve(b, rtol=1e-10, maxit=3000)
+    assert ok and rr <= 1e-10
+    J = sysm.tangent(eps_t, phi, E, Hn)
+    xr = x.cpu().numpy()
+    bb = b.cpu().numpy()
+    assert np.linalg.norm(J(xr) - bb) <= 1e-8 * np.linalg.norm(bb)
+    s.close()
