@@ -151,6 +151,17 @@ pff_status pff_project(pff_solver* s, const void* in_dev, void* out_dev, int pre
 pff_status pff_krylov_solve(pff_solver* s, const void* b_dev, void* x_dev, double rtol,
                             int maxit, int* iters, double* relres);
 
+/* Kernel timing (measurement support).  With every > 0, each every-th
+ * tangent apply brackets its FFT pass kernels with HIP events on the solver
+ * stream; every = 0 disables.  pff_timing_read(kernel k) returns the number
+ * of timed launches and their summed duration in milliseconds for
+ * k = 0 x-forward pass (with the tangent prologue), 1 first strided-axis
+ * pass (y; with the spectral stage in 2D), 2 z pass with the spectral stage
+ * (3D), 3 inverse y pass (3D), 4 x-inverse pass (with the epilogue),
+ * 5 the whole apply.  Reading synchronises the stream and resets nothing. */
+pff_status pff_timing(pff_solver* s, int every);
+pff_status pff_timing_read(pff_solver* s, int kernel, long long* count, double* ms);
+
 /* Counters since creation: tangent applies, Krylov iterations. */
 pff_status pff_counters(pff_solver* s, long long* applies, long long* krylov_iters);
 

@@ -55,6 +55,9 @@ EXPORTS = {
     "pff_project": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "pff_krylov_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
                                    C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "pff_timing": (C.c_int, [C.c_void_p, C.c_int]),
+    "pff_timing_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_longlong),
+                                  C.POINTER(C.c_double)]),
     "pff_counters": (C.c_int, [C.c_void_p, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
     "pff_save": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)]),
     "pff_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),

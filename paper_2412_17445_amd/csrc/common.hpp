@@ -6,7 +6,10 @@
 
 namespace pff {
 
-constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts of 64)
+constexpr int kBlock = 256;          // threads per workgroup of vector kernels (4 wavefronts)
+// threads per workgroup of the FFT pass kernels: 8 LDS elements per thread
+// and 64 KB of LDS per block for either precision
+template <typename T> struct FftThreads { static constexpr int value = sizeof(T) == 4 ? 1024 : 512; };
 constexpr int kMaxPhases = 16;
 constexpr int kMaxRed = 12;          // reduction slots per pass
 constexpr int kMaxStages = 10;
@@ -54,22 +57,22 @@ struct GridDesc {
 
 // Deterministic block reduction of NR double accumulators; thread 0 of the
 // block ends with the totals.  Fixed pairing order -> bitwise reproducible.
-template <int NR>
-__device__ __forceinline__ void block_reduce(double (&v)[NR], double* lds /* NR*kBlock */) {
+template <int NR, int BS = kBlock>
+__device__ __forceinline__ void block_reduce(double (&v)[NR], double* lds /* NR*BS */) {
   const int t = threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < NR; ++q) lds[q * kBlock + t] = v[q];
+  for (int q = 0; q < NR; ++q) lds[q * BS + t] = v[q];
   __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
+  for (int s = BS / 2; s > 0; s >>= 1) {
     if (t < s) {
 #pragma unroll
-      for (int q = 0; q < NR; ++q) lds[q * kBlock + t] += lds[q * kBlock + t + s];
+      for (int q = 0; q < NR; ++q) lds[q * BS + t] += lds[q * BS + t + s];
     }
     __syncthreads();
   }
   if (t == 0) {
 #pragma unroll
-    for (int q = 0; q < NR; ++q) v[q] = lds[q * kBlock];
+    for (int q = 0; q < NR; ++q) v[q] = lds[q * BS];
   }
   __syncthreads();
 }

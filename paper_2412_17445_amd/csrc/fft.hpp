@@ -7,6 +7,15 @@
 // r*Ns.  Radices 2, 3, 4 and 8 cover every length 2^a 3^b.  S = -1 is the
 // forward transform (exp(-2 pi i jk/n), the numpy convention), S = +1 the
 // unnormalised inverse.  The caller scales by 1/N elsewhere.
+//
+// Layout: element j of sequence q, interleaved column t, sits at
+// (q*n + j)*TX + t.  TX = 1 gives contiguous sequences (x passes); TX > 1
+// interleaves TX columns so that a strided-axis tile is loaded and stored
+// with TX contiguous values per row and consecutive threads touch
+// consecutive columns.  Stages run in place: each thread first reads all
+// inputs of its butterflies into registers, then (after a barrier) writes
+// the outputs, so one LDS buffer suffices.  A thread handles at most MAXE/R
+// butterflies per stage: the caller guarantees nseq*TX*n <= MAXE*blockDim.
 #pragma once
 
 #include "common.hpp"
@@ -69,55 +78,71 @@ template <typename T, int S, int R> __device__ __forceinline__ void dftR(cpx<T>*
   else dft8<T, S>(v);
 }
 
-template <typename T, int S, int R>
-__device__ __forceinline__ void stockham_stage(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
-                                               int n, int Ns, int ntr, const cpx<T>* tw) {
+template <typename T, int S, int R, int MAXE>
+__device__ __forceinline__ void stockham_stage(cpx<T>* buf, int n, int Ns, int nseq, int ltx,
+                                               const cpx<T>* tw) {
+  constexpr int MB = (MAXE + R - 1) / R;        // butterflies per thread
+  const int TX = 1 << ltx;
   const int nb = n / R;
-  const int total = nb * ntr;
+  const int total = (nb * nseq) << ltx;
   const int twstep = n / (Ns * R);
-  for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int b = t / nb;
-    const int j = t - b * nb;
-    const cpx<T>* s = src + b * n;
-    cpx<T>* d = dst + b * n;
-    const int k = j % Ns;
-    cpx<T> v[R];
+  cpx<T> v[MB][R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = s[j + r * nb];
-    if (Ns > 1) {
+  for (int q = 0; q < MB; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    if (idx < total) {
+      const int t = idx & (TX - 1);
+      const int rest = idx >> ltx;
+      const int s = rest / nb;
+      const int j = rest - s * nb;
+      const int base_in = (s * n + j) * TX + t;
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        cpx<T> w = tw[r * k * twstep];
-        if (S > 0) w.y = -w.y;
-        v[r] = cmul(v[r], w);
-      }
+      for (int r = 0; r < R; ++r) v[q][r] = buf[base_in + r * nb * TX];
     }
-    dftR<T, S, R>(v);
-    const int base = (j - k) * R + k;
-#pragma unroll
-    for (int r = 0; r < R; ++r) d[base + r * Ns] = v[r];
   }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MB; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    if (idx < total) {
+      const int t = idx & (TX - 1);
+      const int rest = idx >> ltx;
+      const int s = rest / nb;
+      const int j = rest - s * nb;
+      const int kk = j % Ns;
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cpx<T> w = tw[r * kk * twstep];
+          if (S > 0) w.y = -w.y;
+          v[q][r] = cmul(v[q][r], w);
+        }
+      }
+      dftR<T, S, R>(v[q]);
+      // output base (j div Ns) * Ns * R + j mod Ns
+      const int base_out = (s * n + (j - kk) * R + kk) * TX + t;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[base_out + r * Ns * TX] = v[q][r];
+    }
+  }
+  __syncthreads();
 }
 
-// Transforms `ntr` sequences of length pl.n stored at a + b*n; b is scratch
-// of the same size.  Returns the buffer that holds the result.  Must be
-// called by every thread of the block; ends with a barrier.
-template <typename T, int S>
-__device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int ntr, const AxisPlan& pl, const cpx<T>* tw) {
+// In-place transform of nseq sequences (times TX = 2^ltx interleaved
+// columns) of length pl.n held in buf; tw is the LDS twiddle table
+// exp(-2 pi i k/n).
+// Must be called by every thread of the block; ends with a barrier.
+template <typename T, int S, int MAXE>
+__device__ void fft_lds(cpx<T>* buf, int nseq, int ltx, const AxisPlan& pl, const cpx<T>* tw) {
   int Ns = 1;
   for (int st = 0; st < pl.nstage; ++st) {
     const int R = pl.radix[st];
-    if (R == 8) stockham_stage<T, S, 8>(a, b, pl.n, Ns, ntr, tw);
-    else if (R == 4) stockham_stage<T, S, 4>(a, b, pl.n, Ns, ntr, tw);
-    else if (R == 3) stockham_stage<T, S, 3>(a, b, pl.n, Ns, ntr, tw);
-    else stockham_stage<T, S, 2>(a, b, pl.n, Ns, ntr, tw);
-    __syncthreads();
-    cpx<T>* tmp = a;
-    a = b;
-    b = tmp;
+    if (R == 8) stockham_stage<T, S, 8, MAXE>(buf, pl.n, Ns, nseq, ltx, tw);
+    else if (R == 4) stockham_stage<T, S, 4, MAXE>(buf, pl.n, Ns, nseq, ltx, tw);
+    else if (R == 3) stockham_stage<T, S, 3, MAXE>(buf, pl.n, Ns, nseq, ltx, tw);
+    else stockham_stage<T, S, 2, MAXE>(buf, pl.n, Ns, nseq, ltx, tw);
     Ns *= R;
   }
-  return a;
 }
 
 }  // namespace pff

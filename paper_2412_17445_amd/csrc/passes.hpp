@@ -29,8 +29,11 @@ template <typename T> struct SpecTables {
   T invN;
 };
 
+// Max LDS elements per thread of the in-place FFT (64 KB per block).
+template <typename T> struct FftCap { static constexpr int MAXE = 8; };
+
 template <class P>
-__global__ void __launch_bounds__(kBlock) k_xfwd(const typename P::Args A, const AxisPlan pl,
+__global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xfwd(const typename P::Args A, const AxisPlan pl,
                                                  const cpx<typename P::real>* __restrict__ tw_g,
                                                  cpx<typename P::real>* __restrict__ spec,
                                                  int rows_per_block, double* __restrict__ partials) {
@@ -44,8 +47,7 @@ __global__ void __launch_bounds__(kBlock) k_xfwd(const typename P::Args A, const
   const int RB = rows_per_block;
   const int seq = RB * NP * nx;
   cpx<T>* bufa = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* bufb = bufa + seq;
-  cpx<T>* tw = bufb + seq;
+  cpx<T>* tw = bufa + seq;
   for (int t = threadIdx.x; t < nx; t += blockDim.x) tw[t] = tw_g[t];
   const long long row0 = (long long)blockIdx.x * RB;
   double red[NR > 0 ? NR : 1];
@@ -62,7 +64,8 @@ __global__ void __launch_bounds__(kBlock) k_xfwd(const typename P::Args A, const
     for (int p = 0; p < NP; ++p) bufa[(r * NP + p) * nx + x] = cpx<T>{vals[2 * p], vals[2 * p + 1]};
   }
   __syncthreads();
-  cpx<T>* res = fft_lds<T, -1>(bufa, bufb, RB * NP, pl, tw);
+  fft_lds<T, -1, FftCap<T>::MAXE>(bufa, RB * NP, 0, pl, tw);
+  const cpx<T>* res = bufa;
   const long long Nh = A.g.Nh;
   for (int idx = threadIdx.x; idx < RB * NP * nxh; idx += blockDim.x) {
     const int k = idx % nxh;
@@ -81,74 +84,77 @@ __global__ void __launch_bounds__(kBlock) k_xfwd(const typename P::Args A, const
   }
   if constexpr (NR > 0) {
     __syncthreads();
-    block_reduce<NR>(red, reinterpret_cast<double*>(smem_raw));
+    block_reduce<NR, FftThreads<T>::value>(red, reinterpret_cast<double*>(smem_raw));
     if (threadIdx.x == 0)
       for (int q = 0; q < NR; ++q) partials[(long long)q * gridDim.x + blockIdx.x] = red[q];
   }
 }
 
-// Complex FFT along y (axis 1) or z (axis 2) of every field, for a tile of
-// TX consecutive kx and one index of the remaining axis.  With SPECTRAL the
-// point-wise spectral stage and the inverse transform follow.
+// Complex FFT along y (axis 1) or z (axis 2) for a tile of TX consecutive
+// kx columns, one index of the remaining axis (blockIdx.y) and a group of
+// NFB fields (blockIdx.z).  With SPECTRAL (NFB = NF) the point-wise spectral
+// stage and the inverse transform along the same axis follow.
 template <class P, int S, bool SPECTRAL>
-__global__ void __launch_bounds__(kBlock) k_axis(const typename P::Args A, const AxisPlan pl,
+__global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_axis(const typename P::Args A, const AxisPlan pl,
                                                  const cpx<typename P::real>* __restrict__ tw_g,
                                                  cpx<typename P::real>* __restrict__ spec, int axis,
-                                                 int TX) {
+                                                 int ltx, int NFB) {
   using T = typename P::real;
   constexpr int NF = P::NF;
+  constexpr int MAXE = FftCap<T>::MAXE;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = pl.n;
+  const int TX = 1 << ltx;
   const int nxh = A.g.nxh, ny = A.g.ny;
   const long long Nh = A.g.Nh;
   const int kx0 = blockIdx.x * TX;
   const int o = blockIdx.y;                       // z for the y pass, y for the z pass
+  const int f0 = blockIdx.z * NFB;
+  const int nfb = (f0 + NFB <= NF) ? NFB : NF - f0;
   const long long stride = axis == 1 ? (long long)nxh : (long long)nxh * ny;
   const long long base = axis == 1 ? (long long)nxh * ny * o : (long long)nxh * o;
-  const int seq = NF * TX * n;
-  cpx<T>* bufa = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* bufb = bufa + seq;
-  cpx<T>* tw = bufb + seq;
+  const int seq = nfb * n * TX;
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw = buf + NFB * n * TX;
   for (int t = threadIdx.x; t < n; t += blockDim.x) tw[t] = tw_g[t];
   for (int idx = threadIdx.x; idx < seq; idx += blockDim.x) {
-    const int t = idx % TX;
-    const int rest = idx / TX;
+    const int t = idx & (TX - 1);
+    const int rest = idx >> ltx;                  // = f*n + j
     const int j = rest % n, f = rest / n;
     const int kx = kx0 + t;
     cpx<T> val = {T(0), T(0)};
-    if (kx < nxh) val = spec[f * Nh + base + kx + stride * j];
-    bufa[(f * TX + t) * n + j] = val;
+    if (kx < nxh) val = spec[(f0 + f) * Nh + base + kx + stride * j];
+    buf[idx] = val;
   }
   __syncthreads();
-  cpx<T>* res = fft_lds<T, S>(bufa, bufb, NF * TX, pl, tw);
+  fft_lds<T, S, MAXE>(buf, nfb, ltx, pl, tw);
   if constexpr (SPECTRAL) {
     for (int idx = threadIdx.x; idx < TX * n; idx += blockDim.x) {
-      const int t = idx % TX, j = idx / TX;
+      const int t = idx & (TX - 1), j = idx >> ltx;
       const int kx = kx0 + t;
       if (kx >= nxh) continue;
       cpx<T> v[NF];
 #pragma unroll
-      for (int f = 0; f < NF; ++f) v[f] = res[(f * TX + t) * n + j];
+      for (int f = 0; f < NF; ++f) v[f] = buf[(f * n + j) * TX + t];
       if (axis == 1) P::spectral(A, kx, j, 0, v);
       else P::spectral(A, kx, o, j, v);
 #pragma unroll
-      for (int f = 0; f < NF; ++f) res[(f * TX + t) * n + j] = v[f];
+      for (int f = 0; f < NF; ++f) buf[(f * n + j) * TX + t] = v[f];
     }
     __syncthreads();
-    cpx<T>* other = (res == bufa) ? bufb : bufa;
-    res = fft_lds<T, -S>(res, other, NF * TX, pl, tw);
+    fft_lds<T, -S, MAXE>(buf, nfb, ltx, pl, tw);
   }
   for (int idx = threadIdx.x; idx < seq; idx += blockDim.x) {
-    const int t = idx % TX;
-    const int rest = idx / TX;
+    const int t = idx & (TX - 1);
+    const int rest = idx >> ltx;
     const int j = rest % n, f = rest / n;
     const int kx = kx0 + t;
-    if (kx < nxh) spec[f * Nh + base + kx + stride * j] = res[(f * TX + t) * n + j];
+    if (kx < nxh) spec[(f0 + f) * Nh + base + kx + stride * j] = buf[idx];
   }
 }
 
 template <class P>
-__global__ void __launch_bounds__(kBlock) k_xinv(const typename P::Args A, const AxisPlan pl,
+__global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xinv(const typename P::Args A, const AxisPlan pl,
                                                  const cpx<typename P::real>* __restrict__ tw_g,
                                                  const cpx<typename P::real>* __restrict__ spec,
                                                  int rows_per_block, double* __restrict__ partials) {
@@ -163,8 +169,7 @@ __global__ void __launch_bounds__(kBlock) k_xinv(const typename P::Args A, const
   const int RB = rows_per_block;
   const int seq = RB * NP * nx;
   cpx<T>* bufa = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* bufb = bufa + seq;
-  cpx<T>* tw = bufb + seq;
+  cpx<T>* tw = bufa + seq;
   for (int t = threadIdx.x; t < nx; t += blockDim.x) tw[t] = tw_g[t];
   const long long row0 = (long long)blockIdx.x * RB;
   for (int idx = threadIdx.x; idx < seq; idx += blockDim.x) {
@@ -188,7 +193,8 @@ __global__ void __launch_bounds__(kBlock) k_xinv(const typename P::Args A, const
     bufa[(r * NP + p) * nx + x] = Z;
   }
   __syncthreads();
-  cpx<T>* res = fft_lds<T, 1>(bufa, bufb, RB * NP, pl, tw);
+  fft_lds<T, 1, FftCap<T>::MAXE>(bufa, RB * NP, 0, pl, tw);
+  const cpx<T>* res = bufa;
   double red[NR > 0 ? NR : 1];
 #pragma unroll
   for (int q = 0; q < (NR > 0 ? NR : 1); ++q) red[q] = 0.0;
@@ -207,7 +213,7 @@ __global__ void __launch_bounds__(kBlock) k_xinv(const typename P::Args A, const
   }
   if constexpr (NR > 0) {
     __syncthreads();
-    block_reduce<NR>(red, reinterpret_cast<double*>(smem_raw));
+    block_reduce<NR, FftThreads<T>::value>(red, reinterpret_cast<double*>(smem_raw));
     if (threadIdx.x == 0)
       for (int q = 0; q < NR; ++q) partials[(long long)q * gridDim.x + blockIdx.x] = red[q];
   }

@@ -8,6 +8,7 @@
 #include "pff.h"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -100,7 +101,7 @@ struct pff_solver {
   double *eps_t = nullptr, *phi = nullptr, *Hn = nullptr, *Hcur = nullptr;
   double *eps_c = nullptr, *phi_c = nullptr, *phi_guess = nullptr, *dmask = nullptr;
   double* Edev = nullptr;   // [0] current E, [1] committed E
-  void* ts = nullptr;       // tangent state (C+3)*N, working precision
+  void* ts = nullptr;       // tangent state (TsLayout fields x N), working precision
   void* kv[11] = {};        // Krylov vectors, working precision, M each
   void* aux = nullptr;      // N, working precision
   cpx<double>* spec_d = nullptr;
@@ -115,6 +116,12 @@ struct pff_solver {
   bool bootstrapped = false;
   bool ts_valid = false;
   bool trace = false;       // PFF_TRACE=1: per-Newton-iteration log on stderr
+  int tim_every = 0;        // sampled kernel timing of the tangent apply
+  // launch tuning (env PFF_AXIS_THREADS, PFF_SPEC_THREADS, PFF_AXIS_TX, PFF_SPEC_TX, PFF_X_ROWS)
+  int axis_threads = 0, spec_threads = 0, axis_tx = 64, spec_tx = 64, x_rows = 64;
+  std::vector<std::array<hipEvent_t, 6>> tim_pending, tim_free;
+  double tim_ms[6] = {0, 0, 0, 0, 0, 0};
+  long long tim_n[6] = {0, 0, 0, 0, 0, 0};
   int n = 0;
   double a = 0.0, E = 0.0, E_s = 0.0;
   long long applies = 0, kiters = 0;
@@ -157,67 +164,115 @@ int grid1(long long M) {
   return (int)std::max<long long>(b, 1);
 }
 
-int choose_rb(int nx, int np, size_t csz, int nred) {
-  int rb = std::max(1, 1024 / nx);
-  while (rb > 1 && (size_t(2 * rb * np * nx) + nx) * csz > kLdsBudget) rb /= 2;
-  (void)nred;
+// Per-pass tiling.  The in-place FFT needs (elements per block) <=
+// MAXE * kBlock and the LDS holds the elements plus one twiddle table.
+size_t g_lds_budget = kLdsBudget;
+
+int maxe_of(size_t) { return 8; }
+int fft_threads(size_t csz) { return csz == 8 ? 1024 : 512; }
+
+int choose_rb(int nx, int np, size_t csz, int rows_max) {
+  const size_t cap = size_t(maxe_of(csz)) * fft_threads(csz);
+  int rb = 1;
+  while (true) {
+    const int nr = rb * 2;
+    const size_t elems = size_t(nr) * np * nx;
+    if (nr > rows_max || elems > cap || (elems + nx) * csz > g_lds_budget || nr * nx > 4096) break;
+    rb = nr;
+  }
   return rb;
 }
 
 size_t lds_x(int rb, int np, int nx, size_t csz, int nred) {
-  size_t b = (size_t(2 * rb * np * nx) + nx) * csz;
-  return std::max(b, size_t(nred) * kBlock * sizeof(double));
+  size_t b = (size_t(rb) * np * nx + nx) * csz;
+  return std::max(b, size_t(nred) * fft_threads(csz) * sizeof(double));
 }
 
-int choose_tx(int n, int nf, size_t csz, int nxh) {
-  int tx = 16;
-  while (tx > 1 && (size_t(2 * nf * tx * n) + n) * csz > kLdsBudget) tx /= 2;
+// columns per tile (a power of two) for a strided-axis pass over nfb fields
+// of length n with `threads` threads per block
+int choose_tx(int n, int nfb, size_t csz, int nxh, int threads, int tx_max) {
+  const size_t cap = size_t(maxe_of(csz)) * threads;
+  int tx = 64;
+  while (tx > 1 && (tx > tx_max || size_t(nfb) * n * tx > cap ||
+                    (size_t(nfb) * n * tx + n) * csz > kLdsBudget))
+    tx /= 2;
   while (tx > 1 && tx / 2 >= nxh) tx /= 2;
   return tx;
 }
 
+int log2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+size_t lds_axis(int n, int nfb, int tx, size_t csz) { return (size_t(nfb) * n * tx + n) * csz; }
+
 // Runs the FFT round trip of pipe P: forward passes with its prologue, the
 // spectral stage, inverse passes with its epilogue.
 template <class P>
-void run_pipeline(pff_solver* s, const typename P::Args& A, int& nblk_x) {
+void run_pipeline(pff_solver* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev = nullptr) {
   using T = typename P::real;
   constexpr int NF = P::NF;
   constexpr int NP = (NF + 1) / 2;
   const DevTables<T>& tb = s->tables<T>();
   cpx<T>* spec = s->spec<T>();
   const size_t csz = sizeof(cpx<T>);
-  const int rb = choose_rb(s->nx, NP, csz, std::max(P::NRED_PRO, P::NRED_EPI));
-  const size_t ldsx = lds_x(rb, NP, s->nx, csz, std::max(P::NRED_PRO, P::NRED_EPI));
-  if (ldsx > kLdsBudget) throw Fail("grid too large for the LDS budget of the x pass", PFF_ERR_ARG);
+  const int nthr = fft_threads(csz);
+  const int nred = std::max(P::NRED_PRO, P::NRED_EPI);
+  const int rb = choose_rb(s->nx, NP, csz, s->x_rows);
+  const size_t ldsx = lds_x(rb, NP, s->nx, csz, nred);
+  if (ldsx > kLdsBudget || size_t(rb) * NP * s->nx > size_t(maxe_of(csz)) * fft_threads(csz))
+    throw Fail("grid too large for the LDS budget of the x pass", PFF_ERR_ARG);
   const long long nrows = (long long)s->ny * s->nz;
   nblk_x = (int)((nrows + rb - 1) / rb);
   if ((size_t)nblk_x > s->part_len) throw Fail("partial buffer too small", PFF_ERR_STATE);
-  k_xfwd<P><<<nblk_x, kBlock, ldsx, s->stream>>>(A, s->plan[0], tb.tw[0], spec, rb, s->part0);
+  if (ev) HC(hipEventRecord(ev[0], s->stream));
+  k_xfwd<P><<<nblk_x, nthr, ldsx, s->stream>>>(A, s->plan[0], tb.tw[0], spec, rb, s->part0);
   LAUNCH_CHECK();
+  if (ev) HC(hipEventRecord(ev[1], s->stream));
+  // the spectral pass holds all NF fields of a tile
+  const int last = s->dim == 2 ? 1 : 2;
+  const int nl = s->dim == 2 ? s->ny : s->nz;
+  const int sthr = s->spec_threads > 0 ? std::min(s->spec_threads, nthr) : nthr;
+  const int txs = choose_tx(nl, NF, csz, s->nxh, sthr, s->spec_tx);
+  const size_t ldss = lds_axis(nl, NF, txs, csz);
+  if (ldss > kLdsBudget || size_t(NF) * nl * txs > size_t(maxe_of(csz)) * sthr)
+    throw Fail("axis too long for the LDS budget", PFF_ERR_ARG);
+  const dim3 gs((s->nxh + txs - 1) / txs, last == 1 ? s->nz : s->ny, 1);
   if (s->dim == 2) {
-    const int tx = choose_tx(s->ny, NF, csz, s->nxh);
-    const size_t lds = (size_t(2 * NF * tx * s->ny) + s->ny) * csz;
-    if (lds > kLdsBudget) throw Fail("axis too long for the LDS budget", PFF_ERR_ARG);
-    dim3 grid((s->nxh + tx - 1) / tx, 1);
-    k_axis<P, -1, true><<<grid, kBlock, lds, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, tx);
+    k_axis<P, -1, true><<<gs, sthr, ldss, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txs), NF);
     LAUNCH_CHECK();
+    if (ev) {
+      HC(hipEventRecord(ev[2], s->stream));
+      HC(hipEventRecord(ev[3], s->stream));
+      HC(hipEventRecord(ev[4], s->stream));
+    }
   } else {
-    const int txy = choose_tx(s->ny, NF, csz, s->nxh);
-    const size_t ldsy = (size_t(2 * NF * txy * s->ny) + s->ny) * csz;
-    const int txz = choose_tx(s->nz, NF, csz, s->nxh);
-    const size_t ldsz = (size_t(2 * NF * txz * s->nz) + s->nz) * csz;
-    if (ldsy > kLdsBudget || ldsz > kLdsBudget) throw Fail("axis too long for the LDS budget", PFF_ERR_ARG);
-    dim3 gy((s->nxh + txy - 1) / txy, s->nz), gz((s->nxh + txz - 1) / txz, s->ny);
-    k_axis<P, -1, false><<<gy, kBlock, ldsy, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, txy);
+    // forward / inverse y passes: one field per block, wide tiles
+    const int athr = s->axis_threads > 0 ? std::min(s->axis_threads, nthr) : nthr;
+    const int txy = choose_tx(s->ny, 1, csz, s->nxh, athr, s->axis_tx);
+    const size_t ldsy = lds_axis(s->ny, 1, txy, csz);
+    const dim3 gy((s->nxh + txy - 1) / txy, s->nz, NF);
+    k_axis<P, -1, false><<<gy, athr, ldsy, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txy), 1);
     LAUNCH_CHECK();
-    k_axis<P, -1, true><<<gz, kBlock, ldsz, s->stream>>>(A, s->plan[2], tb.tw[2], spec, 2, txz);
+    if (ev) HC(hipEventRecord(ev[2], s->stream));
+    k_axis<P, -1, true><<<gs, sthr, ldss, s->stream>>>(A, s->plan[2], tb.tw[2], spec, 2, log2i(txs), NF);
     LAUNCH_CHECK();
-    k_axis<P, 1, false><<<gy, kBlock, ldsy, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, txy);
+    if (ev) HC(hipEventRecord(ev[3], s->stream));
+    k_axis<P, 1, false><<<gy, athr, ldsy, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txy), 1);
     LAUNCH_CHECK();
+    if (ev) HC(hipEventRecord(ev[4], s->stream));
   }
-  k_xinv<P><<<nblk_x, kBlock, ldsx, s->stream>>>(A, s->plan[0], tb.tw[0], spec, rb, s->part1);
+  k_xinv<P><<<nblk_x, nthr, ldsx, s->stream>>>(A, s->plan[0], tb.tw[0], spec, rb, s->part1);
   LAUNCH_CHECK();
+  if (ev) HC(hipEventRecord(ev[5], s->stream));
 }
+
+// ---- live kernel timing (sampled event pairs on the solver stream) -------------
+
+hipEvent_t* timing_acquire(pff_solver* s);
+void timing_harvest(pff_solver* s);
 
 void sync_scal(pff_solver* s) {
   HC(hipMemcpyAsync(s->hscal, s->scal, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s->stream));
@@ -348,7 +403,8 @@ struct Impl {
     A.v = v;
     A.Jv = Jv;
     int nblk = 0;
-    run_pipeline<TangentPipe<TW, DIM>>(s, A, nblk);
+    hipEvent_t* ev = (s->tim_every > 0 && s->applies % s->tim_every == 0) ? timing_acquire(s) : nullptr;
+    run_pipeline<TangentPipe<TW, DIM>>(s, A, nblk, ev);
     typename FinLast<TW>::Args F{Jv + (long long)(C + 1) * s->N};
     k_reduce<FinLast<TW>><<<1, kBlock, 0, s->stream>>>(s->part0, nblk, 1, F);
     LAUNCH_CHECK();
@@ -649,7 +705,45 @@ void upload_tables(pff_solver* s, DevTables<T>& t) {
   }
 }
 
+hipEvent_t* timing_acquire(pff_solver* s) {
+  if (s->tim_pending.size() >= 512) timing_harvest(s);
+  std::array<hipEvent_t, 6> ev;
+  if (!s->tim_free.empty()) {
+    ev = s->tim_free.back();
+    s->tim_free.pop_back();
+  } else {
+    for (auto& e : ev) HC(hipEventCreate(&e));
+  }
+  s->tim_pending.push_back(ev);
+  return s->tim_pending.back().data();
+}
+
+void timing_harvest(pff_solver* s) {
+  if (s->tim_pending.empty()) return;
+  HC(hipEventSynchronize(s->tim_pending.back()[5]));
+  for (auto& ev : s->tim_pending) {
+    float ms[5];
+    for (int k = 0; k < 5; ++k) HC(hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]));
+    float all = 0.f;
+    HC(hipEventElapsedTime(&all, ev[0], ev[5]));
+    for (int k = 0; k < 5; ++k) {
+      s->tim_ms[k] += ms[k];
+      s->tim_n[k] += 1;
+    }
+    s->tim_ms[5] += all;
+    s->tim_n[5] += 1;
+    s->tim_free.push_back(ev);
+  }
+  s->tim_pending.clear();
+}
+
 void destroy_buffers(pff_solver* s) {
+  for (auto& ev : s->tim_pending)
+    for (auto e : ev) (void)hipEventDestroy(e);
+  for (auto& ev : s->tim_free)
+    for (auto e : ev) (void)hipEventDestroy(e);
+  s->tim_pending.clear();
+  s->tim_free.clear();
   for (void* p : s->allocs) (void)hipFree(p);
   s->allocs.clear();
   if (s->hscal) (void)hipHostFree(s->hscal);
@@ -731,6 +825,15 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     s->stream = static_cast<hipStream_t>(hip_stream);
     const char* tr = std::getenv("PFF_TRACE");
     s->trace = tr && tr[0] == '1';
+    auto envi = [](const char* k, int d) {
+      const char* v = std::getenv(k);
+      return v ? std::atoi(v) : d;
+    };
+    s->axis_threads = envi("PFF_AXIS_THREADS", 256);
+    s->spec_threads = envi("PFF_SPEC_THREADS", 512);
+    s->axis_tx = envi("PFF_AXIS_TX", 16);
+    s->spec_tx = envi("PFF_SPEC_TX", 8);
+    s->x_rows = envi("PFF_X_ROWS", 64);
     // device memory
     const long long N = s->N, M = s->M;
     const int C = s->C;
@@ -748,7 +851,7 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     s->Hcur = s->alloc<double>(N);
     s->Edev = s->alloc<double>(4);
     const size_t wsz = s->mixed() ? sizeof(float) : sizeof(double);
-    s->ts = s->alloc<unsigned char>((size_t)(C + 3) * N * wsz);
+    s->ts = s->alloc<unsigned char>((size_t)(s->dim == 2 ? TsLayout<2>::COUNT : TsLayout<3>::COUNT) * N * wsz);
     for (int k = 0; k < 11; ++k) s->kv[k] = s->alloc<unsigned char>((size_t)M * wsz);
     s->aux = s->alloc<unsigned char>((size_t)N * wsz);
     s->spec_d = s->alloc<cpx<double>>((size_t)(C + 1) * s->Nh);
@@ -1060,6 +1163,27 @@ pff_status pff_krylov_solve(pff_solver* s, const void* b_dev, void* x_dev, doubl
     });
     HC(hipStreamSynchronize(s->stream));
     return conv ? PFF_OK : PFF_NOT_CONVERGED;
+  });
+}
+
+pff_status pff_timing(pff_solver* s, int every) {
+  return guarded(s, [&]() -> pff_status {
+    if (every < 0) throw Fail("pff_timing: every must be >= 0", PFF_ERR_ARG);
+    HC(hipStreamSynchronize(s->stream));
+    timing_harvest(s);
+    s->tim_every = every;
+    return PFF_OK;
+  });
+}
+
+pff_status pff_timing_read(pff_solver* s, int kernel, long long* count, double* ms) {
+  return guarded(s, [&]() -> pff_status {
+    if (kernel < 0 || kernel > 5) throw Fail("pff_timing_read: kernel id out of range", PFF_ERR_ARG);
+    HC(hipStreamSynchronize(s->stream));
+    timing_harvest(s);
+    if (count) *count = s->tim_n[kernel];
+    if (ms) *ms = s->tim_ms[kernel];
+    return PFF_OK;
   });
 }
 

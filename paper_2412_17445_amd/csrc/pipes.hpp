@@ -9,10 +9,14 @@
 //   ProjectPipe   plain projection of C fields and Laplacian of one field.
 //
 // Layouts (N voxels, x fastest; C = 3 in plane strain, 6 in 3D; Mandel
-// components): a Krylov vector is [d eps (C*N) | d phi (N) | dE (1)]; the
-// tangent state ts is [eps (C*N) | phi (N) | Hs (N) | r (N)] where
-// Hs = -H when the history is loading (psi0(+) >= Hn) and +H otherwise, and
-// r = phi/l - l Lap(phi) is the crack-length gradient.
+// components): a Krylov vector is [d eps (C*N) | d phi (N) | dE (1)].  The
+// tangent state ts holds the strain split frame, then phi, Hs and r:
+//   2D: [eps (3*N) | phi | Hs | r]                        (TS = 6 fields)
+//   3D: [quaternion of the eigenbasis (4*N) | eigenvalues (3*N) | phi | Hs | r]
+//       (TS = 10 fields: the 3x3 eigen-decomposition is done once per
+//       Newton iteration in the FP64 residual pass, not in every apply)
+// where Hs = -H when the history is loading (psi0(+) >= Hn) and +H
+// otherwise, and r = phi/l - l Lap(phi) is the crack-length gradient.
 #pragma once
 
 #include "passes.hpp"
@@ -20,9 +24,15 @@
 
 namespace pff {
 
+template <int DIM> struct TsLayout {
+  static constexpr int FRAME = DIM == 2 ? 3 : 7;   // fields before phi
+  static constexpr int PHI = FRAME, HS = FRAME + 1, R = FRAME + 2, COUNT = FRAME + 3;
+};
+
 template <typename T, int DIM>
 struct TangentPipe {
   using real = T;
+  using L = TsLayout<DIM>;
   static constexpr int C = DIM == 2 ? 3 : 6;
   static constexpr int D = DIM == 2 ? 2 : 3;
   static constexpr int NF = C + 1;
@@ -48,19 +58,29 @@ struct TangentPipe {
     const bool m = A.mask[i] != 0;
     const T lam = T(A.mat.lam[p]), mu = T(A.mat.mu[p]), Gc = T(A.mat.Gc[p]);
     const T dE = A.v[(long long)(C + 1) * N];
-    T eps[C], w[C];
+    T w[C];
 #pragma unroll
-    for (int k = 0; k < C; ++k) {
-      eps[k] = A.ts[k * N + i];
-      w[k] = A.v[k * N + i] + A.f[k] * dE;
-    }
-    const T phi = A.ts[C * N + i];
-    const T Hs = A.ts[(C + 1) * N + i];
-    const T r = A.ts[(C + 2) * N + i];
+    for (int k = 0; k < C; ++k) w[k] = A.v[k * N + i] + A.f[k] * dE;
+    const T phi = A.ts[L::PHI * N + i];
+    const T Hs = A.ts[L::HS * N + i];
+    const T r = A.ts[L::R * N + i];
     const T dphi = A.v[C * N + i];
     const T dphf = m ? T(0) : dphi;
     Split<T, D> sp;
-    split_eval<T, D>(eps, lam, mu, sp);
+    if constexpr (DIM == 2) {
+      T eps[C];
+#pragma unroll
+      for (int k = 0; k < C; ++k) eps[k] = A.ts[k * N + i];
+      split_eval<T, D>(eps, lam, mu, sp);
+    } else {
+      T q[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) q[k] = A.ts[k * N + i];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) sp.e.z[a] = A.ts[(4 + a) * N + i];
+      quat_to_rot<T>(q, sp.e.V);
+      split_from_eig<T, D>(lam, mu, sp.e.z[0] + sp.e.z[1] + sp.e.z[2], sp);
+    }
     const T g = (T(1) - phi) * (T(1) - phi) + A.k;
     T Cw[C];
     tangent_apply<T, D>(sp, lam, mu, g, w, Cw);
@@ -101,6 +121,7 @@ struct TangentPipe {
 template <int DIM, typename TW>
 struct ResidualPipe {
   using real = double;
+  using L = TsLayout<DIM>;
   static constexpr int C = DIM == 2 ? 3 : 6;
   static constexpr int D = DIM == 2 ? 2 : 3;
   static constexpr int NF = C + 1;
@@ -151,12 +172,20 @@ struct ResidualPipe {
     const double Hs = chi ? -H : H;
     A.Hcur[i] = Hs;
 #pragma unroll
-    for (int k = 0; k < C; ++k) {
-      A.ts[k * N + i] = TW(eps[k]);
-      out[k] = sm[k];
+    for (int k = 0; k < C; ++k) out[k] = sm[k];
+    if constexpr (DIM == 2) {
+#pragma unroll
+      for (int k = 0; k < C; ++k) A.ts[k * N + i] = TW(eps[k]);
+    } else {
+      double q[4];
+      rot_to_quat<double>(sp.e.V, q);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) A.ts[k * N + i] = TW(q[k]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) A.ts[(4 + a) * N + i] = TW(sp.e.z[a]);
     }
-    A.ts[C * N + i] = TW(phi);
-    A.ts[(C + 1) * N + i] = TW(Hs);
+    A.ts[L::PHI * N + i] = TW(phi);
+    A.ts[L::HS * N + i] = TW(Hs);
     out[C] = phi;
     if constexpr (DIM == 2) {
       const double trp = sp.tr > 0.0 ? sp.tr : 0.0, trm = sp.tr < 0.0 ? sp.tr : 0.0;
@@ -187,7 +216,7 @@ struct ResidualPipe {
     const double lap = in[C];
     const double l = A.l;
     const double F2 = m ? 0.0 : (Gc / l + 2.0 * H) * phi - Gc * l * lap - 2.0 * H;
-    A.ts[(C + 2) * N + i] = TW(phi / l - l * lap);
+    A.ts[L::R * N + i] = TW(phi / l - l * lap);
     double f1 = 0.0;
 #pragma unroll
     for (int k = 0; k < C; ++k) {

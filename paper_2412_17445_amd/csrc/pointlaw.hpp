@@ -155,14 +155,9 @@ template <typename T, int D> struct Split {
   T psi_p;         // psi0(+)
 };
 
+// Completes the split state once sp.e holds the eigen-decomposition.
 template <typename T, int D>
-__device__ __forceinline__ void split_eval(const T* eps_m, T lam, T mu, Split<T, D>& sp) {
-  T E[D][D];
-  mandel_to_tensor<T, D>(eps_m, E);
-  eig_sym(E, sp.e);
-  T tr = T(0);
-#pragma unroll
-  for (int i = 0; i < D; ++i) tr += E[i][i];
+__device__ __forceinline__ void split_from_eig(T lam, T mu, T tr, Split<T, D>& sp) {
   sp.tr = tr;
   const T trp = tr > T(0) ? tr : T(0);
   T sq = T(0);
@@ -180,6 +175,65 @@ __device__ __forceinline__ void split_eval(const T* eps_m, T lam, T mu, Split<T,
       sp.theta[a][b] = (ta != tb) ? (sp.zp[a] - sp.zp[b]) / (sp.e.z[a] - sp.e.z[b])
                                   : (ta ? T(1) : T(0));
     }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void split_eval(const T* eps_m, T lam, T mu, Split<T, D>& sp) {
+  T E[D][D];
+  mandel_to_tensor<T, D>(eps_m, E);
+  eig_sym(E, sp.e);
+  T tr = T(0);
+#pragma unroll
+  for (int i = 0; i < D; ++i) tr += E[i][i];
+  split_from_eig<T, D>(lam, mu, tr, sp);
+}
+
+// Unit quaternion (w, x, y, z) of a proper rotation matrix (Shepperd's
+// method: branch on the largest of the trace and the diagonal entries).
+template <typename T>
+__device__ __forceinline__ void rot_to_quat(const T (&V)[3][3], T* q) {
+  const T tr = V[0][0] + V[1][1] + V[2][2];
+  if (tr > T(0)) {
+    const T s = sqrt(tr + T(1)) * T(2);
+    q[0] = T(0.25) * s;
+    q[1] = (V[2][1] - V[1][2]) / s;
+    q[2] = (V[0][2] - V[2][0]) / s;
+    q[3] = (V[1][0] - V[0][1]) / s;
+  } else if (V[0][0] > V[1][1] && V[0][0] > V[2][2]) {
+    const T s = sqrt(T(1) + V[0][0] - V[1][1] - V[2][2]) * T(2);
+    q[0] = (V[2][1] - V[1][2]) / s;
+    q[1] = T(0.25) * s;
+    q[2] = (V[0][1] + V[1][0]) / s;
+    q[3] = (V[0][2] + V[2][0]) / s;
+  } else if (V[1][1] > V[2][2]) {
+    const T s = sqrt(T(1) + V[1][1] - V[0][0] - V[2][2]) * T(2);
+    q[0] = (V[0][2] - V[2][0]) / s;
+    q[1] = (V[0][1] + V[1][0]) / s;
+    q[2] = T(0.25) * s;
+    q[3] = (V[1][2] + V[2][1]) / s;
+  } else {
+    const T s = sqrt(T(1) + V[2][2] - V[0][0] - V[1][1]) * T(2);
+    q[0] = (V[1][0] - V[0][1]) / s;
+    q[1] = (V[0][2] + V[2][0]) / s;
+    q[2] = (V[1][2] + V[2][1]) / s;
+    q[3] = T(0.25) * s;
+  }
+}
+
+// Rotation matrix of a quaternion, renormalised against storage round-off.
+template <typename T>
+__device__ __forceinline__ void quat_to_rot(const T* qin, T (&V)[3][3]) {
+  const T n = T(1) / sqrt(qin[0] * qin[0] + qin[1] * qin[1] + qin[2] * qin[2] + qin[3] * qin[3]);
+  const T w = qin[0] * n, x = qin[1] * n, y = qin[2] * n, z = qin[3] * n;
+  V[0][0] = T(1) - T(2) * (y * y + z * z);
+  V[0][1] = T(2) * (x * y - z * w);
+  V[0][2] = T(2) * (x * z + y * w);
+  V[1][0] = T(2) * (x * y + z * w);
+  V[1][1] = T(1) - T(2) * (x * x + z * z);
+  V[1][2] = T(2) * (y * z - x * w);
+  V[2][0] = T(2) * (x * z - y * w);
+  V[2][1] = T(2) * (y * z + x * w);
+  V[2][2] = T(1) - T(2) * (x * x + y * y);
 }
 
 // sigma0(+) or sigma0(-) as a D x D tensor (the zz entry of plane strain is

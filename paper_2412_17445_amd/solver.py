@@ -164,6 +164,20 @@ class Solver:
                          "pff_krylov_solve")
         return x, it.value, rr.value, st == L.PFF_OK
 
+    def timing(self, every):
+        """Sample every `every`-th tangent apply's pass kernels with HIP events."""
+        self._check(self.lib.pff_timing(self.h, int(every)), "pff_timing")
+
+    def timing_read(self):
+        """{kernel id: (timed launches, summed ms)} for ids 0..5 (see pff.h)."""
+        out = {}
+        for k in range(6):
+            n, ms = C.c_longlong(), C.c_double()
+            self._check(self.lib.pff_timing_read(self.h, k, C.byref(n), C.byref(ms)),
+                        "pff_timing_read")
+            out[k] = (n.value, ms.value)
+        return out
+
     def counters(self):
         a, k = C.c_longlong(), C.c_longlong()
         self._check(self.lib.pff_counters(self.h, C.byref(a), C.byref(k)), "pff_counters")

@@ -90,7 +90,8 @@ def problem_config(name: str) -> Problem:
             name=name, shape=(n, n, n),
             phases=[(1.0, 0.3, 1e-3), (1e-6, 0.3, 1e-3)], phase_id=pid, mask=None,
             f=_dyad(2, 2), l=1.5, delta_a=4.0, n_increments=60, alpha=0.9,
-            precision="mixed", notes="64^3 porous, 15% spherical pores r~U[3,6]")
+            precision="mixed", krylov_rtol=1e-5,
+            notes="64^3 porous, 15% spherical pores r~U[3,6]")
     if name == "cfg3_128cube_particles":
         n = 128
         pid, _ = spheres_random(n, 6.0, 6.0, 0.25, seed=4, gap=1.0, fixed_radius=6.0)
@@ -99,7 +100,7 @@ def problem_config(name: str) -> Problem:
             name=name, shape=(n, n, n),
             phases=[(1.0, 0.3, 1e-3), (8.0, 0.2, 5e-3)], phase_id=pid,
             mask=penny_crack_mask(n, 64, 64, 64, 10), f=f, l=2.0, delta_a=8.0,
-            n_increments=80, alpha=0.9, precision="mixed",
+            n_increments=80, alpha=0.9, precision="mixed", krylov_rtol=1e-5,
             notes="128^3 particle composite 25%, penny crack R=10, eps_zz:eps_xz=1:0.3")
     # ---- small parity cases ------------------------------------------------
     if name == "tiny16":
