@@ -74,14 +74,28 @@ def load_traffic(workload, kernel_id, launches_bytes):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(prob, seconds=15.0):
-    """Oracle tangent apply (NumPy FP64) on a frozen state of the workload."""
-    import numpy as np
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(prob, seconds=15.0, max_voxels=1 << 19):
+    """Oracle tangent apply (NumPy FP64) on a frozen state of the workload.
+    Workloads above max_voxels are timed on a corner crop of their phase map
+    (same phases and structure, fewer voxels): the rate is per voxel."""
+    import copy
 
     from oracle import fourier as fo
     from oracle.system import System
     from synth import random_state, random_vector
 
+    crop = None
+    if prob.nvox > max_voxels:
+        prob = copy.copy(prob)
+        n = 64 if prob.shape[0] > 1 else prob.shape[1]
+        crop = (min(n, prob.shape[0]), n, n)
+        prob.shape = crop
+        prob.phase_id = prob.phase_id[:crop[0], :crop[1], :crop[2]].copy()
+        prob.mask = None if prob.mask is None else prob.mask[:crop[0], :crop[1], :crop[2]].copy()
     sysm = System(prob)
     eps, phi, Hn, E = random_state(sysm.shape, sysm.ncomp, 7, f_mandel=sysm.f, E=0.004)
     eps_t = fo.G_mandel(eps - sysm.fE(E))
@@ -96,22 +110,54 @@ def cpu_baseline(prob, seconds=15.0):
     wall = time.perf_counter() - w0
     cpu = time.process_time() - c0
     cores = max(1, int(round(cpu / wall)))
+    where = ("the " + "x".join(map(str, crop[::-1])) + " corner crop of the workload"
+             if crop else "the workload")
     return {"value": n * sysm.N / wall / 1e6, "unit": "Mvoxel-applies/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{n} oracle tangent applies (NumPy FP64) on a frozen seeded state of the "
-                      f"{'x'.join(map(str, prob.shape[::-1]))} workload, {wall:.1f} s wall, "
+            "sample": f"{n} oracle tangent applies (NumPy FP64) on a frozen seeded state of "
+                      f"{where} ({sysm.N} voxels), {wall:.1f} s wall, "
                       f"host threads used ~{cpu / wall:.2f}"}
+
+
+def apply_mode(prob, args):
+    """Tangent applies on a frozen synthetic state (for counter runs)."""
+    import numpy as np
+    import torch
+
+    from paper_2412_17445_amd import Solver
+
+    s = Solver.from_problem(prob)
+    c = s.ncomp
+    rng = np.random.default_rng(0)
+    eps = rng.standard_normal((c,) + prob.shape) * 1e-3
+    eps[1 if c == 3 else 2] += 4e-3
+    phi = rng.uniform(0.0, 0.5, prob.shape)
+    s.set_state(eps, phi, np.full(prob.shape, 1e-6), 4e-3, 1.0, n=1)
+    s.residual(2.0, want_F=False)
+    dt = torch.float32 if prob.precision == "mixed" else torch.float64
+    v = torch.randn(s.M, dtype=dt, device="cuda") * 1e-3
+    out = torch.empty_like(v)
+    for _ in range(args.applies):
+        s.apply(v, out)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "apply", "workload": args.workload, "applies": args.applies,
+                      "alg_bytes_per_launch": kernel_bytes(prob.shape, prob.precision)}))
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg1_256sq_fibres")
+    ap.add_argument("--workload", default="cfg3_128cube_particles")
     ap.add_argument("--precision", default=None, help="override: fp64 or mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-every", type=int, default=8)
+    ap.add_argument("--mode", default="solve", choices=["solve", "apply", "copy"],
+                    help="solve: timed increments (default); apply: tangent applies on a frozen "
+                         "state (profiling counters); copy: plain device copy of 256 MiB "
+                         "(counter calibration)")
+    ap.add_argument("--applies", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs one RVE solve on one GPU; multi-GPU runs are not "
@@ -123,14 +169,30 @@ def main():
     from paper_2412_17445_amd import Solver
     from synth import problem_config
 
+    torch.cuda.set_device(0)
+    if args.mode == "copy":
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read_per_launch": src.numel() * 4,
+                          "bytes_written_per_launch": dst.numel() * 4, "launches": 3}))
+        return
     prob = problem_config(args.workload)
     if args.precision:
         prob.precision = args.precision
-    torch.cuda.set_device(0)
+    if args.mode == "apply":
+        apply_mode(prob, args)
+        return
+    log(f"workload {args.workload} {prob.shape[::-1]} {prob.precision}")
     s = Solver.from_problem(prob)
     s.bootstrap()
-    for _ in range(args.warmup):
+    log("bootstrap done")
+    for i in range(args.warmup):
         out = s.step()
+        log(f"warm-up increment {i + 1}: converged={out['converged']} "
+            f"newton={out['newton_iters']} krylov={out['krylov_iters']} {out['seconds']:.2f}s")
         if not out["converged"]:
             raise RuntimeError(f"warm-up increment did not converge: {out}")
     s.timing(args.timing_every)
@@ -138,8 +200,11 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     outs = []
-    for _ in range(args.steps):
+    for i in range(args.steps):
         outs.append(s.step())
+        log(f"timed increment {i + 1}: converged={outs[-1]['converged']} "
+            f"newton={outs[-1]['newton_iters']} krylov={outs[-1]['krylov_iters']} "
+            f"{outs[-1]['seconds']:.2f}s")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     a1, _ = s.counters()
@@ -189,6 +254,7 @@ def main():
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
+        log("timing the CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(line), flush=True)
 

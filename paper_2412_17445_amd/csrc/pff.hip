@@ -46,12 +46,16 @@ constexpr uint64_t kShadowSeed = 0x5EED;
 constexpr double kDiverged = 1e8;
 constexpr int kBisection = 100;
 constexpr int kMaxCycles = 8;
+constexpr int kNumVec = 13;          // Krylov work vectors
+constexpr double kMixedAccept = 1e-2;  // FP32 Newton step kept if its FP64 residual <= this
+constexpr int kMixedMaxit32 = 1500;    // FP32 BiCGSTAB iteration cap per Newton iteration
 
 // device scalar slots
 enum {
   SC_SIG = 0,      // 6 sums of sigma
   SC_GAMMA = 6, SC_F1 = 7, SC_F2 = 8,
   SC_NW = 9, SC_NEPS = 10, SC_NDPHI = 11, SC_NPHI = 12,
+  SC_ETA = 13,     // 2 slots: ||b - J x||^2, ||b||^2 of the FP64 check
   SC_CG = 16,      // CG scratch
   SC_KS = 32,      // Krylov scalars
   SC_COUNT = 64
@@ -101,9 +105,16 @@ struct pff_solver {
   double *eps_t = nullptr, *phi = nullptr, *Hn = nullptr, *Hcur = nullptr;
   double *eps_c = nullptr, *phi_c = nullptr, *phi_guess = nullptr, *dmask = nullptr;
   double* Edev = nullptr;   // [0] current E, [1] committed E
-  void* ts = nullptr;       // tangent state (TsLayout fields x N), working precision
-  void* kv[11] = {};        // Krylov vectors, working precision, M each
-  void* aux = nullptr;      // N, working precision
+  // tangent state (TsLayout fields x N), Krylov vectors (M each) and the
+  // apply's auxiliary field (N): FP64 always, FP32 copies in mixed mode
+  double* ts64 = nullptr;
+  float* ts32 = nullptr;
+  double* kv64[kNumVec] = {};
+  float* kv32[kNumVec] = {};
+  double* aux64 = nullptr;
+  float* aux32 = nullptr;
+  long long applies64 = 0;  // FP64 applies (all applies in FP64 mode)
+  int fallbacks = 0;        // mixed mode: Newton iterations corrected in FP64
   cpx<double>* spec_d = nullptr;
   cpx<float>* spec_f = nullptr;
   double *part0 = nullptr, *part1 = nullptr;
@@ -138,6 +149,16 @@ struct pff_solver {
   template <typename T> const DevTables<T>& tables() const;
   template <typename T> cpx<T>* spec() const;
 };
+
+template <typename T> T* vecs(pff_solver* s, int k);
+template <> double* vecs<double>(pff_solver* s, int k) { return s->kv64[k]; }
+template <> float* vecs<float>(pff_solver* s, int k) { return s->kv32[k]; }
+template <typename T> T* tstate(pff_solver* s);
+template <> double* tstate<double>(pff_solver* s) { return s->ts64; }
+template <> float* tstate<float>(pff_solver* s) { return s->ts32; }
+template <typename T> T* auxf(pff_solver* s);
+template <> double* auxf<double>(pff_solver* s) { return s->aux64; }
+template <> float* auxf<float>(pff_solver* s) { return s->aux32; }
 
 template <> const DevTables<double>& pff_solver::tables<double>() const { return td; }
 template <> const DevTables<float>& pff_solver::tables<float>() const { return tf; }
@@ -345,6 +366,34 @@ __global__ void __launch_bounds__(kBlock) k_newton_update(double* __restrict__ e
   write_partials<4>(acc, partials);
 }
 
+__global__ void __launch_bounds__(kBlock) k_widen(double* __restrict__ dst, const float* __restrict__ src,
+                                                  long long M) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = double(src[i]);
+}
+
+// out = b - t, partials of (out, out) and (b, b)
+__global__ void __launch_bounds__(kBlock) k_resid_pair(double* __restrict__ out, const double* __restrict__ b,
+                                                       const double* __restrict__ t, long long M,
+                                                       double* __restrict__ partials) {
+  double acc[2] = {0.0, 0.0};
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double r = b[i] - t[i];
+    out[i] = r;
+    acc[0] += r * r;
+    acc[1] += b[i] * b[i];
+  }
+  write_partials<2>(acc, partials);
+}
+
+__global__ void __launch_bounds__(kBlock) k_add(double* __restrict__ y, const double* __restrict__ x, long long M) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] += x[i];
+}
+
 __global__ void k_commit_history(double* __restrict__ Hn, const double* __restrict__ Hcur, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
@@ -363,14 +412,14 @@ struct FinNewton {
   }
 };
 
-template <typename TW>
 struct FinResid {
-  struct Args { double* scal; double a; TW* rhs_last; double* F_last; };
+  struct Args { double* scal; double a; double* rhs_last; float* rhs32_last; double* F_last; };
   __device__ static void run(const Args& F, const double* tot) {
     F.scal[SC_GAMMA] = tot[0];
     F.scal[SC_F1] = tot[1];
     F.scal[SC_F2] = tot[2];
-    F.rhs_last[0] = TW(F.a - tot[0]);
+    F.rhs_last[0] = F.a - tot[0];
+    if (F.rhs32_last) F.rhs32_last[0] = float(F.a - tot[0]);
     if (F.F_last) F.F_last[0] = tot[0] - F.a;
   }
 };
@@ -381,8 +430,8 @@ template <int DIM, typename TW>
 struct Impl {
   static constexpr int C = DIM == 2 ? 3 : 6;
 
-  static TW* vec(pff_solver* s, int k) { return static_cast<TW*>(s->kv[k]); }
-  enum { X0 = 0, X1, X2, R, RHAT, P, V, S, T, RHS, SOL };
+  static TW* vec(pff_solver* s, int k) { return vecs<TW>(s, k); }
+  enum { X0 = 0, X1, X2, R, RHAT, P, V, S, T, RHS, SOL, VB, VD };
 
   static void fill_tangent_args(pff_solver* s, typename TangentPipe<TW, DIM>::Args& A) {
     A.g = s->g;
@@ -390,10 +439,10 @@ struct Impl {
     A.l = TW(s->prm.l);
     A.k = TW(s->prm.k_resid);
     for (int k = 0; k < 6; ++k) A.f[k] = TW(s->fm[k]);
-    A.ts = static_cast<const TW*>(s->ts);
+    A.ts = tstate<TW>(s);
     A.pid = s->pid;
     A.mask = s->mask;
-    A.aux = static_cast<TW*>(s->aux);
+    A.aux = auxf<TW>(s);
     A.tab = spec_tables<TW>(s);
   }
 
@@ -409,11 +458,13 @@ struct Impl {
     k_reduce<FinLast<TW>><<<1, kBlock, 0, s->stream>>>(s->part0, nblk, 1, F);
     LAUNCH_CHECK();
     s->applies++;
+    if (std::is_same<TW, double>::value) s->applies64++;
   }
 
-  // residual at the current state for target a; rhs = -F in working precision
+  // residual at the current state for target a; rhs = -F (FP64, plus the
+  // FP32 copy in mixed mode); also refreshes the tangent state(s)
   static void residual(pff_solver* s, double a, double* F_dev) {
-    typename ResidualPipe<DIM, TW>::Args A;
+    typename ResidualPipe<DIM>::Args A;
     A.g = s->g;
     A.mat = s->mat;
     A.l = s->prm.l;
@@ -424,20 +475,23 @@ struct Impl {
     A.Hn = s->Hn;
     A.Hcur = s->Hcur;
     A.E = s->Edev;
-    A.ts = static_cast<TW*>(s->ts);
-    A.rhs = vec(s, RHS);
+    A.ts = s->ts64;
+    A.ts32 = s->ts32;
+    A.rhs = vecs<double>(s, RHS);
+    A.rhs32 = s->kv32[RHS];
     A.F = F_dev;
     A.pid = s->pid;
     A.mask = s->mask;
     A.tab = spec_tables<double>(s);
     int nblk = 0;
-    run_pipeline<ResidualPipe<DIM, TW>>(s, A, nblk);
+    run_pipeline<ResidualPipe<DIM>>(s, A, nblk);
     FinStore::Args fs{s->scal + SC_SIG, 6};
     k_reduce<FinStore><<<1, kBlock, 0, s->stream>>>(s->part0, nblk, 6, fs);
     LAUNCH_CHECK();
-    typename FinResid<TW>::Args fr{s->scal, a, vec(s, RHS) + (long long)(C + 1) * s->N,
-                                    F_dev ? F_dev + (long long)(C + 1) * s->N : nullptr};
-    k_reduce<FinResid<TW>><<<1, kBlock, 0, s->stream>>>(s->part1, nblk, 3, fr);
+    const long long last = (long long)(C + 1) * s->N;
+    FinResid::Args fr{s->scal, a, vecs<double>(s, RHS) + last,
+                      s->kv32[RHS] ? s->kv32[RHS] + last : nullptr, F_dev ? F_dev + last : nullptr};
+    k_reduce<FinResid><<<1, kBlock, 0, s->stream>>>(s->part1, nblk, 3, fr);
     LAUNCH_CHECK();
     s->ts_valid = true;
   }
@@ -610,6 +664,56 @@ struct Impl {
     LAUNCH_CHECK();
   }
 };
+
+// Newton linear solve J dq = -F into the FP64 vector SOL.  FP64 mode: one
+// BiCGSTAB in FP64.  Mixed mode: BiCGSTAB in FP32, then the step is checked
+// with one FP64 apply; when its FP64 relative residual exceeds
+// kMixedAccept, an FP64 BiCGSTAB solves for the correction (the FP32 tangent
+// cannot resolve the soft modes of a nearly broken crack, stiffness k).
+template <int DIM>
+void newton_linear_solve(pff_solver* s, int* kit, double* eta_out) {
+  using I64 = Impl<DIM, double>;
+  using I32 = Impl<DIM, float>;
+  const double rtol = s->prm.krylov_rtol;
+  const int maxit = s->prm.krylov_maxit;
+  if (!s->mixed()) {
+    I64::bicgstab(s, I64::vec(s, I64::RHS), I64::vec(s, I64::SOL), rtol, maxit, kit, eta_out);
+    return;
+  }
+  const long long M = s->M;
+  const int nb = red_blocks(M);
+  int k32 = 0, k64 = 0;
+  double rr32 = 0.0;
+  I32::bicgstab(s, I32::vec(s, I32::RHS), I32::vec(s, I32::SOL), rtol, std::min(maxit, kMixedMaxit32),
+                &k32, &rr32);
+  k_widen<<<nb, kBlock, 0, s->stream>>>(I64::vec(s, I64::SOL), I32::vec(s, I32::SOL), M);
+  LAUNCH_CHECK();
+  I64::apply(s, I64::vec(s, I64::SOL), I64::vec(s, I64::T));
+  k_resid_pair<<<nb, kBlock, 0, s->stream>>>(I64::vec(s, I64::VB), I64::vec(s, I64::RHS),
+                                             I64::vec(s, I64::T), M, s->part0);
+  LAUNCH_CHECK();
+  k_reduce<FinStore><<<1, kBlock, 0, s->stream>>>(s->part0, nb, 2, FinStore::Args{s->scal + SC_ETA, 2});
+  LAUNCH_CHECK();
+  sync_scal(s);
+  const double bb = s->hscal[SC_ETA + 1];
+  double eta = bb > 0.0 ? std::sqrt(s->hscal[SC_ETA] / bb) : 0.0;
+  if (eta > kMixedAccept) {
+    double rr64 = 0.0;
+    const double rt = std::min(0.5, rtol / eta);
+    I64::bicgstab(s, I64::vec(s, I64::VB), I64::vec(s, I64::VD), rt, maxit, &k64, &rr64);
+    k_add<<<nb, kBlock, 0, s->stream>>>(I64::vec(s, I64::SOL), I64::vec(s, I64::VD), M);
+    LAUNCH_CHECK();
+    eta *= rr64;
+    s->fallbacks++;
+  }
+  *kit = k32 + k64;
+  *eta_out = eta;
+}
+
+template <typename F> void dispatch_dim(pff_solver* s, F&& fn) {
+  if (s->dim == 2) fn(std::integral_constant<int, 2>());
+  else fn(std::integral_constant<int, 3>());
+}
 
 // ---- host-side predictor --------------------------------------------------------
 
@@ -850,10 +954,15 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     s->Hn = s->alloc<double>(N);
     s->Hcur = s->alloc<double>(N);
     s->Edev = s->alloc<double>(4);
-    const size_t wsz = s->mixed() ? sizeof(float) : sizeof(double);
-    s->ts = s->alloc<unsigned char>((size_t)(s->dim == 2 ? TsLayout<2>::COUNT : TsLayout<3>::COUNT) * N * wsz);
-    for (int k = 0; k < 11; ++k) s->kv[k] = s->alloc<unsigned char>((size_t)M * wsz);
-    s->aux = s->alloc<unsigned char>((size_t)N * wsz);
+    const size_t nts = (size_t)(s->dim == 2 ? TsLayout<2>::COUNT : TsLayout<3>::COUNT) * N;
+    s->ts64 = s->alloc<double>(nts);
+    s->aux64 = s->alloc<double>(N);
+    for (int k = 0; k < kNumVec; ++k) s->kv64[k] = s->alloc<double>(M);
+    if (s->mixed()) {
+      s->ts32 = s->alloc<float>(nts);
+      s->aux32 = s->alloc<float>(N);
+      for (int k = 0; k < kNumVec; ++k) s->kv32[k] = s->alloc<float>(M);
+    }
     s->spec_d = s->alloc<cpx<double>>((size_t)(C + 1) * s->Nh);
     if (s->mixed()) s->spec_f = s->alloc<cpx<float>>((size_t)(C + 1) * s->Nh);
     s->part_len = std::max<size_t>(kRedBlocks, (size_t)s->ny * s->nz + 16);
@@ -975,9 +1084,11 @@ pff_status pff_step(pff_solver* s, pff_increment_result* out) {
     int conv = 0, it = 0;
     double err[3] = {0, 0, 0};
     const bool trace = s->trace;
-    dispatch(s, [&](auto impl) {
-      using I = decltype(impl);
-      using TW = typename std::remove_pointer<decltype(I::vec(s, 0))>::type;
+    const int fb0 = s->fallbacks;
+    const long long a64_0 = s->applies64;
+    dispatch_dim(s, [&](auto dimc) {
+      constexpr int DIM = decltype(dimc)::value;
+      using I = Impl<DIM, double>;
       I::residual(s, a_new, nullptr);
       if (trace) {
         sync_scal(s);
@@ -987,7 +1098,7 @@ pff_status pff_step(pff_solver* s, pff_increment_result* out) {
       for (it = 1; it <= s->prm.newton_maxit; ++it) {
         int kit = 0;
         double rr = 0;
-        I::bicgstab(s, I::vec(s, I::RHS), I::vec(s, I::SOL), s->prm.krylov_rtol, s->prm.krylov_maxit, &kit, &rr);
+        newton_linear_solve<DIM>(s, &kit, &rr);
         I::newton_update(s, I::vec(s, I::SOL), s->prm.alpha);
         I::residual(s, a_new, nullptr);
         sync_scal(s);
@@ -1010,7 +1121,6 @@ pff_status pff_step(pff_solver* s, pff_increment_result* out) {
         }
         if (!std::isfinite(e)) break;
       }
-      (void)sizeof(TW);
     });
     if (it > s->prm.newton_maxit) it = s->prm.newton_maxit;
     const int g = grid1(N);
@@ -1020,6 +1130,8 @@ pff_status pff_step(pff_solver* s, pff_increment_result* out) {
       out->newton_iters = it;
       out->krylov_iters = (int)(s->kiters - ki0);
       out->applies = s->applies - ap0;
+      out->applies_fp64 = s->applies64 - a64_0;
+      out->fp64_fallbacks = s->fallbacks - fb0;
       out->converged = conv;
       out->target_a = a_new;
       for (int q = 0; q < 3; ++q) out->err[q] = err[q];

@@ -118,7 +118,7 @@ struct TangentPipe {
   }
 };
 
-template <int DIM, typename TW>
+template <int DIM>
 struct ResidualPipe {
   using real = double;
   using L = TsLayout<DIM>;
@@ -137,8 +137,10 @@ struct ResidualPipe {
     const double* Hn;
     double* Hcur;
     const double* E;
-    TW* ts;
-    TW* rhs;
+    double* ts;      // FP64 tangent state
+    float* ts32;     // FP32 copy for the mixed-precision apply, or null
+    double* rhs;     // -F, FP64 Krylov right-hand side
+    float* rhs32;    // FP32 copy, or null
     double* F;
     const uint8_t* pid;
     const uint8_t* mask;
@@ -173,19 +175,25 @@ struct ResidualPipe {
     A.Hcur[i] = Hs;
 #pragma unroll
     for (int k = 0; k < C; ++k) out[k] = sm[k];
+    double frame[L::FRAME];
     if constexpr (DIM == 2) {
 #pragma unroll
-      for (int k = 0; k < C; ++k) A.ts[k * N + i] = TW(eps[k]);
+      for (int k = 0; k < C; ++k) frame[k] = eps[k];
     } else {
-      double q[4];
-      rot_to_quat<double>(sp.e.V, q);
+      rot_to_quat<double>(sp.e.V, frame);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) A.ts[k * N + i] = TW(q[k]);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) A.ts[(4 + a) * N + i] = TW(sp.e.z[a]);
+      for (int a = 0; a < 3; ++a) frame[4 + a] = sp.e.z[a];
     }
-    A.ts[L::PHI * N + i] = TW(phi);
-    A.ts[L::HS * N + i] = TW(Hs);
+#pragma unroll
+    for (int k = 0; k < L::FRAME; ++k) A.ts[k * N + i] = frame[k];
+    A.ts[L::PHI * N + i] = phi;
+    A.ts[L::HS * N + i] = Hs;
+    if (A.ts32) {
+#pragma unroll
+      for (int k = 0; k < L::FRAME; ++k) A.ts32[k * N + i] = float(frame[k]);
+      A.ts32[L::PHI * N + i] = float(phi);
+      A.ts32[L::HS * N + i] = float(Hs);
+    }
     out[C] = phi;
     if constexpr (DIM == 2) {
       const double trp = sp.tr > 0.0 ? sp.tr : 0.0, trm = sp.tr < 0.0 ? sp.tr : 0.0;
@@ -216,15 +224,19 @@ struct ResidualPipe {
     const double lap = in[C];
     const double l = A.l;
     const double F2 = m ? 0.0 : (Gc / l + 2.0 * H) * phi - Gc * l * lap - 2.0 * H;
-    A.ts[L::R * N + i] = TW(phi / l - l * lap);
+    const double r = phi / l - l * lap;
+    A.ts[L::R * N + i] = r;
+    if (A.ts32) A.ts32[L::R * N + i] = float(r);
     double f1 = 0.0;
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-      A.rhs[k * N + i] = TW(-in[k]);
+      A.rhs[k * N + i] = -in[k];
+      if (A.rhs32) A.rhs32[k * N + i] = float(-in[k]);
       if (A.F) A.F[k * N + i] = in[k];
       f1 += in[k] * in[k];
     }
-    A.rhs[C * N + i] = TW(-F2);
+    A.rhs[C * N + i] = -F2;
+    if (A.rhs32) A.rhs32[C * N + i] = float(-F2);
     if (A.F) A.F[C * N + i] = F2;
     red[0] += phi * phi / (2.0 * l) - 0.5 * l * phi * lap;
     red[1] += f1;

@@ -42,7 +42,7 @@ def test_struct_layouts():
     assert C.sizeof(L.pff_phase) == 24
     # 4 doubles + f[9] + 3 doubles, then 3 ints (+ padding)
     assert C.sizeof(L.pff_params) == 8 * (2 + 9 + 4) + 4 * 3 + 4
-    assert C.sizeof(L.pff_increment_result) == 4 * 4 + 8 + 8 * (6 + 3 + 3 + 1)
+    assert C.sizeof(L.pff_increment_result) == 4 * 4 + 8 * 2 + 4 * 2 + 8 * (6 + 3 + 3 + 1)
 
 
 def _params(**kw):
