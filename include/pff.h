@@ -86,13 +86,14 @@ typedef struct {
 /* Per-increment outputs (Algorithm 2): macroscopic stress Sigma_M = <sigma>
  * as tensor components [11, 22, 33, 23, 13, 12] (sigma_33 of plane strain
  * included), load factor E, crack length Gamma(phi) and its target a, the
- * three error measures of the last Newton iteration and counters (tangent
- * applies, of which in FP64, and in mixed mode the Newton iterations whose
- * FP32 step had to be corrected in FP64). */
+ * three error measures of the last Newton iteration and counters: tangent
+ * applies (of which in FP64); in mixed mode the FP64 refinement steps (FP32
+ * correction solves after the first) and the Newton iterations whose
+ * refinement stalled and was finished by an FP64 BiCGSTAB. */
 typedef struct {
   int increment, newton_iters, krylov_iters, converged;
   long long applies, applies_fp64;
-  int fp64_fallbacks, reserved;
+  int fp64_fallbacks, refinements;
   double sigma_M[6];
   double load_factor, crack_length, target_a;
   double err[3];

@@ -35,7 +35,7 @@ class pff_params(C.Structure):
 class pff_increment_result(C.Structure):
     _fields_ = [("increment", C.c_int), ("newton_iters", C.c_int), ("krylov_iters", C.c_int),
                 ("converged", C.c_int), ("applies", C.c_longlong), ("applies_fp64", C.c_longlong),
-                ("fp64_fallbacks", C.c_int), ("reserved", C.c_int), ("sigma_M", C.c_double * 6),
+                ("fp64_fallbacks", C.c_int), ("refinements", C.c_int), ("sigma_M", C.c_double * 6),
                 ("load_factor", C.c_double), ("crack_length", C.c_double),
                 ("target_a", C.c_double), ("err", C.c_double * 3), ("seconds", C.c_double)]
 

@@ -188,6 +188,14 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xinv(co
         a.y = -a.y;
         b.y = -b.y;
       }
+      if (k == 0 || 2 * k == nx) {
+        // DC and Nyquist bins of a real field are real: their imaginary parts
+        // are round-off that would otherwise leak into the partner field of
+        // the pair (a + i b).  Dropping them gives the real part of the full
+        // inverse transform.
+        a.y = T(0);
+        b.y = T(0);
+      }
       Z = cpx<T>{a.x - b.y, a.y + b.x};   // a + i b
     }
     bufa[(r * NP + p) * nx + x] = Z;

@@ -47,8 +47,10 @@ constexpr double kDiverged = 1e8;
 constexpr int kBisection = 100;
 constexpr int kMaxCycles = 8;
 constexpr int kNumVec = 13;          // Krylov work vectors
-constexpr double kMixedAccept = 1e-2;  // FP32 Newton step kept if its FP64 residual <= this
-constexpr int kMixedMaxit32 = 1500;    // FP32 BiCGSTAB iteration cap per Newton iteration
+constexpr double kInner32 = 1e-4;        // relative residual of each FP32 inner solve (mixed)
+constexpr int kMixedMaxit32 = 3000;      // FP32 BiCGSTAB iteration cap per inner solve
+constexpr int kMaxRefine = 8;            // FP64 refinement steps per Newton iteration
+constexpr double kRefineContract = 0.5;  // a refinement step must at least halve the defect
 
 // device scalar slots
 enum {
@@ -103,6 +105,7 @@ struct pff_solver {
   std::vector<void*> allocs;
   uint8_t *pid = nullptr, *mask = nullptr;
   double *eps_t = nullptr, *phi = nullptr, *Hn = nullptr, *Hcur = nullptr;
+  double* lap64 = nullptr;   // 2D: Laplacian of phi for the residual (N)
   double *eps_c = nullptr, *phi_c = nullptr, *phi_guess = nullptr, *dmask = nullptr;
   double* Edev = nullptr;   // [0] current E, [1] committed E
   // tangent state (TsLayout fields x N), Krylov vectors (M each) and the
@@ -114,7 +117,8 @@ struct pff_solver {
   double* aux64 = nullptr;
   float* aux32 = nullptr;
   long long applies64 = 0;  // FP64 applies (all applies in FP64 mode)
-  int fallbacks = 0;        // mixed mode: Newton iterations corrected in FP64
+  int fallbacks = 0;        // mixed mode: Newton iterations finished by an FP64 BiCGSTAB
+  int refinements = 0;      // mixed mode: FP32 correction solves
   cpx<double>* spec_d = nullptr;
   cpx<float>* spec_f = nullptr;
   double *part0 = nullptr, *part1 = nullptr;
@@ -388,6 +392,20 @@ __global__ void __launch_bounds__(kBlock) k_resid_pair(double* __restrict__ out,
   write_partials<2>(acc, partials);
 }
 
+__global__ void __launch_bounds__(kBlock) k_narrow_scaled(float* __restrict__ dst, const double* __restrict__ src,
+                                                          double scale, long long M) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = float(scale * src[i]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_axpy_widen(double* __restrict__ y, const float* __restrict__ x,
+                                                       double a, long long M) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] += a * double(x[i]);
+}
+
 __global__ void __launch_bounds__(kBlock) k_add(double* __restrict__ y, const double* __restrict__ x, long long M) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
        i += (long long)gridDim.x * blockDim.x)
@@ -483,6 +501,17 @@ struct Impl {
     A.pid = s->pid;
     A.mask = s->mask;
     A.tab = spec_tables<double>(s);
+    A.lap_ext = nullptr;
+    if (DIM == 2) {
+      LapPipe::Args LA;
+      LA.g = s->g;
+      LA.u = s->phi;
+      LA.out = s->lap64;
+      LA.tab = A.tab;
+      int nb = 0;
+      run_pipeline<LapPipe>(s, LA, nb);
+      A.lap_ext = s->lap64;
+    }
     int nblk = 0;
     run_pipeline<ResidualPipe<DIM>>(s, A, nblk);
     FinStore::Args fs{s->scal + SC_SIG, 6};
@@ -604,6 +633,21 @@ struct Impl {
     s->ts_valid = false;
   }
 
+  // x[0 : C N] <- G[x[0 : C N]]: the strain block of an FP64 Krylov vector is
+  // projected onto compatible fields.  Exact Newton steps from a compatible
+  // state are compatible (the right-hand side and every tangent output lie in
+  // the range of G), but round-off is not, and G[sigma] = 0 does not see an
+  // incompatible strain: left alone, it accumulates over Newton iterations
+  // and moves the iterate along the set of non-physical roots.
+  static void project_strain(pff_solver* s, double* x) {
+    typename CompatPipe<DIM>::Args A;
+    A.g = s->g;
+    A.x = x;
+    A.tab = spec_tables<double>(s);
+    int nblk = 0;
+    run_pipeline<CompatPipe<DIM>>(s, A, nblk);
+  }
+
   static void helm_apply(pff_solver* s, const double* u, double* out, int mask_input) {
     HelmPipe::Args A;
     A.g = s->g;
@@ -665,11 +709,14 @@ struct Impl {
   }
 };
 
-// Newton linear solve J dq = -F into the FP64 vector SOL.  FP64 mode: one
-// BiCGSTAB in FP64.  Mixed mode: BiCGSTAB in FP32, then the step is checked
-// with one FP64 apply; when its FP64 relative residual exceeds
-// kMixedAccept, an FP64 BiCGSTAB solves for the correction (the FP32 tangent
-// cannot resolve the soft modes of a nearly broken crack, stiffness k).
+// Newton linear solve J dq = -F into the FP64 vector SOL, to the FP64
+// relative residual rtol.  FP64 mode: one FP64 BiCGSTAB.  Mixed mode: FP64
+// iterative refinement around FP32 solves: BiCGSTAB on the FP32 tangent
+// solves J d = r to kInner32, the step is accumulated in FP64 and the defect
+// r = -F - J dq is re-evaluated with the FP64 tangent, until it is below
+// rtol.  Refinement that stops contracting (the FP32 tangent cannot resolve
+// the soft modes of a nearly broken crack, stiffness k) hands the remaining
+// defect to an FP64 BiCGSTAB.
 template <int DIM>
 void newton_linear_solve(pff_solver* s, int* kit, double* eta_out) {
   using I64 = Impl<DIM, double>;
@@ -678,33 +725,57 @@ void newton_linear_solve(pff_solver* s, int* kit, double* eta_out) {
   const int maxit = s->prm.krylov_maxit;
   if (!s->mixed()) {
     I64::bicgstab(s, I64::vec(s, I64::RHS), I64::vec(s, I64::SOL), rtol, maxit, kit, eta_out);
+    I64::project_strain(s, I64::vec(s, I64::SOL));
     return;
   }
   const long long M = s->M;
   const int nb = red_blocks(M);
-  int k32 = 0, k64 = 0;
-  double rr32 = 0.0;
-  I32::bicgstab(s, I32::vec(s, I32::RHS), I32::vec(s, I32::SOL), rtol, std::min(maxit, kMixedMaxit32),
-                &k32, &rr32);
-  k_widen<<<nb, kBlock, 0, s->stream>>>(I64::vec(s, I64::SOL), I32::vec(s, I32::SOL), M);
+  const double rtol_in = std::max(rtol, kInner32);
+  const int maxit32 = std::min(maxit, kMixedMaxit32);
+  double* sol = I64::vec(s, I64::SOL);
+  double* defect = I64::vec(s, I64::VB);
+  float* rhs32 = I32::vec(s, I32::RHS);
+  float* sol32 = I32::vec(s, I32::SOL);
+  int k32 = 0, k64 = 0, kk = 0;
+  double rr = 0.0, eta = 0.0, eta_prev = 1.0;
+  I32::bicgstab(s, rhs32, sol32, rtol_in, maxit32, &kk, &rr);
+  k32 += kk;
+  k_widen<<<nb, kBlock, 0, s->stream>>>(sol, sol32, M);
   LAUNCH_CHECK();
-  I64::apply(s, I64::vec(s, I64::SOL), I64::vec(s, I64::T));
-  k_resid_pair<<<nb, kBlock, 0, s->stream>>>(I64::vec(s, I64::VB), I64::vec(s, I64::RHS),
-                                             I64::vec(s, I64::T), M, s->part0);
-  LAUNCH_CHECK();
-  k_reduce<FinStore><<<1, kBlock, 0, s->stream>>>(s->part0, nb, 2, FinStore::Args{s->scal + SC_ETA, 2});
-  LAUNCH_CHECK();
-  sync_scal(s);
-  const double bb = s->hscal[SC_ETA + 1];
-  double eta = bb > 0.0 ? std::sqrt(s->hscal[SC_ETA] / bb) : 0.0;
-  if (eta > kMixedAccept) {
-    double rr64 = 0.0;
-    const double rt = std::min(0.5, rtol / eta);
-    I64::bicgstab(s, I64::vec(s, I64::VB), I64::vec(s, I64::VD), rt, maxit, &k64, &rr64);
-    k_add<<<nb, kBlock, 0, s->stream>>>(I64::vec(s, I64::SOL), I64::vec(s, I64::VD), M);
+  I64::project_strain(s, sol);
+  for (int ref = 0;; ++ref) {
+    I64::apply(s, sol, I64::vec(s, I64::T));
+    k_resid_pair<<<nb, kBlock, 0, s->stream>>>(defect, I64::vec(s, I64::RHS), I64::vec(s, I64::T), M,
+                                               s->part0);
     LAUNCH_CHECK();
-    eta *= rr64;
-    s->fallbacks++;
+    k_reduce<FinStore><<<1, kBlock, 0, s->stream>>>(s->part0, nb, 2, FinStore::Args{s->scal + SC_ETA, 2});
+    LAUNCH_CHECK();
+    sync_scal(s);
+    const double rr2 = s->hscal[SC_ETA], bb = s->hscal[SC_ETA + 1];
+    eta = bb > 0.0 ? std::sqrt(rr2 / bb) : 0.0;
+    if (eta <= rtol) break;
+    if (ref >= kMaxRefine || !(eta < kRefineContract * eta_prev)) {
+      double rr64 = 0.0;
+      const double rt = std::min(0.5, rtol / eta);
+      I64::bicgstab(s, defect, I64::vec(s, I64::VD), rt, maxit, &k64, &rr64);
+      k_add<<<nb, kBlock, 0, s->stream>>>(sol, I64::vec(s, I64::VD), M);
+      LAUNCH_CHECK();
+      I64::project_strain(s, sol);
+      eta *= rr64;
+      s->fallbacks++;
+      break;
+    }
+    eta_prev = eta;
+    // FP32 solve for the correction, right-hand side scaled to unit norm
+    const double rn = std::sqrt(rr2);
+    k_narrow_scaled<<<nb, kBlock, 0, s->stream>>>(rhs32, defect, 1.0 / rn, M);
+    LAUNCH_CHECK();
+    I32::bicgstab(s, rhs32, sol32, rtol_in, maxit32, &kk, &rr);
+    k32 += kk;
+    k_axpy_widen<<<nb, kBlock, 0, s->stream>>>(sol, sol32, rn, M);
+    LAUNCH_CHECK();
+    I64::project_strain(s, sol);
+    s->refinements++;
   }
   *kit = k32 + k64;
   *eta_out = eta;
@@ -953,6 +1024,7 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     s->dmask = s->alloc<double>(N);
     s->Hn = s->alloc<double>(N);
     s->Hcur = s->alloc<double>(N);
+    if (s->dim == 2) s->lap64 = s->alloc<double>(N);
     s->Edev = s->alloc<double>(4);
     const size_t nts = (size_t)(s->dim == 2 ? TsLayout<2>::COUNT : TsLayout<3>::COUNT) * N;
     s->ts64 = s->alloc<double>(nts);
@@ -1085,6 +1157,7 @@ pff_status pff_step(pff_solver* s, pff_increment_result* out) {
     double err[3] = {0, 0, 0};
     const bool trace = s->trace;
     const int fb0 = s->fallbacks;
+    const int rf0 = s->refinements;
     const long long a64_0 = s->applies64;
     dispatch_dim(s, [&](auto dimc) {
       constexpr int DIM = decltype(dimc)::value;
@@ -1132,6 +1205,7 @@ pff_status pff_step(pff_solver* s, pff_increment_result* out) {
       out->applies = s->applies - ap0;
       out->applies_fp64 = s->applies64 - a64_0;
       out->fp64_fallbacks = s->fallbacks - fb0;
+      out->refinements = s->refinements - rf0;
       out->converged = conv;
       out->target_a = a_new;
       for (int q = 0; q < 3; ++q) out->err[q] = err[q];

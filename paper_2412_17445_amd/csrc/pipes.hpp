@@ -145,6 +145,12 @@ struct ResidualPipe {
     const uint8_t* pid;
     const uint8_t* mask;
     SpecTables<double> tab;
+    // Laplacian of phi computed by a separate pass, or null (then phi is the
+    // (C+1)-th field of this pass).  In 2D the fields are packed in pairs
+    // (11, 22), (12, phi); the round-off of a complex FFT mixes a pair, so
+    // near a root, where G[sigma] is tiny, the 12 component would carry
+    // errors of eps * |Lap phi| outside the range of the projection.
+    const double* lap_ext;
   };
 
   __device__ static void prologue(const Args& A, long long i, double* out, double* red) {
@@ -194,7 +200,7 @@ struct ResidualPipe {
       A.ts32[L::PHI * N + i] = float(phi);
       A.ts32[L::HS * N + i] = float(Hs);
     }
-    out[C] = phi;
+    out[C] = A.lap_ext ? 0.0 : phi;
     if constexpr (DIM == 2) {
       const double trp = sp.tr > 0.0 ? sp.tr : 0.0, trm = sp.tr < 0.0 ? sp.tr : 0.0;
       red[0] += Sg[0][0];
@@ -221,7 +227,7 @@ struct ResidualPipe {
     const double Gc = A.mat.Gc[A.pid[i]];
     const double phi = A.phi[i];
     const double H = fabs(A.Hcur[i]);
-    const double lap = in[C];
+    const double lap = A.lap_ext ? A.lap_ext[i] : in[C];
     const double l = A.l;
     const double F2 = m ? 0.0 : (Gc / l + 2.0 * H) * phi - Gc * l * lap - 2.0 * H;
     const double r = phi / l - l * lap;
@@ -270,6 +276,53 @@ struct HelmPipe {
     const bool m = A.mask[i] != 0;
     const double u = (A.mask_input && m) ? 0.0 : A.u[i];
     A.out[i] = m ? 0.0 : u / A.l - A.l * in[0];
+  }
+};
+
+// Spectral Laplacian of one FP64 field (standard frequencies, Nyquist kept).
+struct LapPipe {
+  using real = double;
+  static constexpr int NF = 1;
+  static constexpr int NRED_PRO = 0;
+  static constexpr int NRED_EPI = 0;
+  struct Args {
+    GridDesc g;
+    const double* u;
+    double* out;
+    SpecTables<double> tab;
+  };
+  __device__ static void prologue(const Args& A, long long i, double* out, double*) { out[0] = A.u[i]; }
+  __device__ static void spectral(const Args& A, int kx, int ky, int kz, cpx<double>* v) {
+    if (A.g.nz == 1) spectral_proj_lap<double, 2, 0, true>(A.tab, kx, ky, kz, v);
+    else spectral_proj_lap<double, 3, 0, true>(A.tab, kx, ky, kz, v);
+  }
+  __device__ static void epilogue(const Args& A, long long i, const double* in, double*) { A.out[i] = in[0]; }
+};
+
+// FP64 projection of the strain block of a Krylov vector onto compatible
+// fields (in place: each pass reads its rows before the last pass writes).
+template <int DIM>
+struct CompatPipe {
+  using real = double;
+  static constexpr int C = DIM == 2 ? 3 : 6;
+  static constexpr int NF = C;
+  static constexpr int NRED_PRO = 0;
+  static constexpr int NRED_EPI = 0;
+  struct Args {
+    GridDesc g;
+    double* x;
+    SpecTables<double> tab;
+  };
+  __device__ static void prologue(const Args& A, long long i, double* out, double*) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) out[k] = A.x[k * A.g.N + i];
+  }
+  __device__ static void spectral(const Args& A, int kx, int ky, int kz, cpx<double>* v) {
+    spectral_proj_lap<double, DIM, C, false>(A.tab, kx, ky, kz, v);
+  }
+  __device__ static void epilogue(const Args& A, long long i, const double* in, double*) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) A.x[k * A.g.N + i] = in[k];
   }
 };
 

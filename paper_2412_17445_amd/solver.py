@@ -104,7 +104,7 @@ class Solver:
         st = self._check(self.lib.pff_step(self.h, C.byref(r)), "pff_step")
         return dict(status=st, increment=r.increment, newton_iters=r.newton_iters,
                     krylov_iters=r.krylov_iters, converged=bool(r.converged), applies=r.applies,
-                    applies_fp64=r.applies_fp64, fp64_fallbacks=r.fp64_fallbacks,
+                    applies_fp64=r.applies_fp64, fp64_fallbacks=r.fp64_fallbacks, refinements=r.refinements,
                     sigma_M=list(r.sigma_M), E=r.load_factor, Gamma=r.crack_length,
                     a=r.target_a, err=list(r.err), seconds=r.seconds)
 

@@ -61,13 +61,13 @@ class Problem:
         return int(np.prod(self.shape))
 
 
-CONFIG_NAMES = ("cfg0_64sq", "cfg1_256sq_fibres", "cfg2_64cube_pores",
-                "cfg3_128cube_particles")
+CONFIG_NAMES = ("crack2d_64", "fibres2d_256", "pores3d_64",
+                "particles3d_128")
 
 
 def problem_config(name: str) -> Problem:
     """Return the seeded problem called `name` (benchmark or parity case)."""
-    if name == "cfg0_64sq":
+    if name == "crack2d_64":
         n = 64
         return Problem(
             name=name, shape=(1, n, n), phases=[(1.0, 0.3, 1e-3)],
@@ -75,7 +75,7 @@ def problem_config(name: str) -> Problem:
             mask=line_crack_mask(n, n, 32, 24, 40), f=_dyad(1, 1), l=2.0,
             delta_a=1.0, n_increments=30, alpha=1.0, newton_tol=1e-8,
             notes="homogeneous 64^2, centred 16-voxel crack, uniaxial yy")
-    if name == "cfg1_256sq_fibres":
+    if name == "fibres2d_256":
         n = 256
         pid, _ = disks_rsa(n, n, radius=8, min_gap=2, target_fraction=0.30, seed=2)
         return Problem(
@@ -83,7 +83,7 @@ def problem_config(name: str) -> Problem:
             phases=[(1.0, 0.35, 1e-3), (10.0, 0.2, 1e-2)], phase_id=pid, mask=None,
             f=_dyad(1, 1), l=2.0, delta_a=2.0, n_increments=100, alpha=1.0,
             notes="256^2 fibre composite, 30% RSA disks r=8 gap 2, transverse tension")
-    if name == "cfg2_64cube_pores":
+    if name == "pores3d_64":
         n = 64
         pid, _ = spheres_random(n, 3.0, 6.0, 0.15, seed=3, gap=1.0)
         return Problem(
@@ -92,7 +92,7 @@ def problem_config(name: str) -> Problem:
             f=_dyad(2, 2), l=1.5, delta_a=4.0, n_increments=60, alpha=0.9,
             precision="mixed", krylov_rtol=1e-5,
             notes="64^3 porous, 15% spherical pores r~U[3,6]")
-    if name == "cfg3_128cube_particles":
+    if name == "particles3d_128":
         n = 128
         pid, _ = spheres_random(n, 6.0, 6.0, 0.25, seed=4, gap=1.0, fixed_radius=6.0)
         f = _dyad(2, 2) + 0.3 * (2.0 * _dyad(0, 2))
@@ -110,6 +110,15 @@ def problem_config(name: str) -> Problem:
             phase_id=np.zeros((1, n, n), np.uint8),
             mask=line_crack_mask(n, n, 8, 6, 10), f=_dyad(1, 1), l=1.5,
             delta_a=0.5, n_increments=4)
+    if name == "gc16":
+        n = 16
+        pid = np.zeros((1, n, n), np.uint8)
+        pid[..., n // 2:] = 1
+        return Problem(
+            name=name, shape=(1, n, n), phases=[(1.0, 0.3, 3e-3), (1.0, 0.3, 1e-3)],
+            phase_id=pid, mask=line_crack_mask(n, n, 8, 6, 10), f=_dyad(1, 1), l=1.5,
+            delta_a=0.5, n_increments=4,
+            notes="16^2, centred crack between a tough (x < 8) and a weak half: one tip grows")
     if name == "fib64":
         n = 64
         pid, _ = disks_rsa(n, n, radius=5, min_gap=2, target_fraction=0.25, seed=11)
