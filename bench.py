@@ -119,6 +119,46 @@ def cpu_baseline(prob, seconds=15.0, max_voxels=1 << 19):
                       f"host threads used ~{cpu / wall:.2f}"}
 
 
+def compare_fp64(prob, args, mixed_outs, mixed_s_per_step):
+    """The same increments solved by the plain FP64 GPU solver: its time per
+    increment and the largest relative difference of the per-increment
+    outputs (load factor, crack length, macroscopic stress)."""
+    import copy
+
+    import numpy as np
+    import torch
+
+    from paper_2412_17445_amd import Solver
+
+    p64 = copy.copy(prob)
+    p64.precision = "fp64"
+    log("plain FP64 solve of the same increments")
+    s = Solver.from_problem(p64)
+    s.bootstrap()
+    d = {"E": 0.0, "Gamma": 0.0, "sigma_M": 0.0}
+    t = []
+    for i, ref in enumerate(mixed_outs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = s.step()
+        torch.cuda.synchronize()
+        t.append(time.perf_counter() - t0)
+        if not o["converged"]:
+            raise RuntimeError(f"FP64 increment {i + 1} did not converge")
+        log(f"fp64 increment {i + 1}: newton={o['newton_iters']} krylov={o['krylov_iters']} {t[-1]:.2f}s")
+        d["E"] = max(d["E"], abs(ref["E"] - o["E"]) / abs(o["E"]))
+        d["Gamma"] = max(d["Gamma"], abs(ref["Gamma"] - o["Gamma"]) / abs(o["Gamma"]))
+        sm, so = np.array(ref["sigma_M"]), np.array(o["sigma_M"])
+        d["sigma_M"] = max(d["sigma_M"], float(np.abs(sm - so).max() / np.abs(so).max()))
+    s.close()
+    timed = t[args.warmup:] or t
+    fp64_s = sum(timed) / len(timed)
+    return {"increments": len(mixed_outs), "fp64_ms_per_step": round(fp64_s * 1e3, 2),
+            "mixed_ms_per_step": round(mixed_s_per_step * 1e3, 2),
+            "fp64_time_over_mixed_time": round(fp64_s / mixed_s_per_step, 3),
+            "max_rel_diff": {k: float("%.3e" % v) for k, v in d.items()}}
+
+
 def apply_mode(prob, args):
     """Tangent applies on a frozen synthetic state (for counter runs)."""
     import numpy as np
@@ -158,6 +198,8 @@ def main():
                          "state (profiling counters); copy: plain device copy of 256 MiB "
                          "(counter calibration)")
     ap.add_argument("--applies", type=int, default=20)
+    ap.add_argument("--no-compare", action="store_true",
+                    help="mixed workloads: skip the plain-FP64 solve of the same increments")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs one RVE solve on one GPU; multi-GPU runs are not "
@@ -189,8 +231,10 @@ def main():
     s = Solver.from_problem(prob)
     s.bootstrap()
     log("bootstrap done")
+    warm = []
     for i in range(args.warmup):
         out = s.step()
+        warm.append(out)
         log(f"warm-up increment {i + 1}: converged={out['converged']} "
             f"newton={out['newton_iters']} krylov={out['krylov_iters']} {out['seconds']:.2f}s")
         if not out["converged"]:
@@ -249,10 +293,16 @@ def main():
                    "tangent_applies": applies,
                    "newton_iters": sum(o["newton_iters"] for o in outs),
                    "krylov_iters": sum(o["krylov_iters"] for o in outs),
+                   "fp64_applies": sum(o["applies_fp64"] for o in outs),
+                   "fp64_refinements": sum(o["refinements"] for o in outs),
+                   "fp64_fallback_solves": sum(o["fp64_fallbacks"] for o in outs),
                    "apply_us_avg": round(apply_ms / max(apply_n, 1) * 1e3, 2),
                    "parallelism": "single GPU"},
         "roofline": roofline,
     }
+    if prob.precision == "mixed" and not args.no_compare:
+        s.close()
+        line["mixed_vs_fp64"] = compare_fp64(prob, args, warm + outs, elapsed / args.steps)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(prob)

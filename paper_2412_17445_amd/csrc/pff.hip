@@ -47,7 +47,7 @@ constexpr double kDiverged = 1e8;
 constexpr int kBisection = 100;
 constexpr int kMaxCycles = 8;
 constexpr int kNumVec = 13;          // Krylov work vectors
-constexpr double kInner32 = 1e-4;        // relative residual of each FP32 inner solve (mixed)
+constexpr double kInner32 = 5e-2;        // relative residual of each FP32 inner solve (mixed)
 constexpr int kMixedMaxit32 = 3000;      // FP32 BiCGSTAB iteration cap per inner solve
 constexpr int kMaxRefine = 8;            // FP64 refinement steps per Newton iteration
 constexpr double kRefineContract = 0.5;  // a refinement step must at least halve the defect
@@ -134,6 +134,7 @@ struct pff_solver {
   int tim_every = 0;        // sampled kernel timing of the tangent apply
   // launch tuning (env PFF_AXIS_THREADS, PFF_SPEC_THREADS, PFF_AXIS_TX, PFF_SPEC_TX, PFF_X_ROWS)
   int axis_threads = 0, spec_threads = 0, axis_tx = 64, spec_tx = 64, x_rows = 64;
+  double inner32 = 0.0;     // mixed: FP32 inner-solve tolerance (env PFF_INNER32)
   std::vector<std::array<hipEvent_t, 6>> tim_pending, tim_free;
   double tim_ms[6] = {0, 0, 0, 0, 0, 0};
   long long tim_n[6] = {0, 0, 0, 0, 0, 0};
@@ -730,7 +731,7 @@ void newton_linear_solve(pff_solver* s, int* kit, double* eta_out) {
   }
   const long long M = s->M;
   const int nb = red_blocks(M);
-  const double rtol_in = std::max(rtol, kInner32);
+  const double rtol_in = std::max(rtol, s->inner32);
   const int maxit32 = std::min(maxit, kMixedMaxit32);
   double* sol = I64::vec(s, I64::SOL);
   double* defect = I64::vec(s, I64::VB);
@@ -1009,6 +1010,11 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     s->axis_tx = envi("PFF_AXIS_TX", 16);
     s->spec_tx = envi("PFF_SPEC_TX", 8);
     s->x_rows = envi("PFF_X_ROWS", 64);
+    {
+      const char* v = std::getenv("PFF_INNER32");
+      s->inner32 = v ? std::atof(v) : kInner32;
+      if (!(s->inner32 > 0.0 && s->inner32 < 1.0)) s->inner32 = kInner32;
+    }
     // device memory
     const long long N = s->N, M = s->M;
     const int C = s->C;
