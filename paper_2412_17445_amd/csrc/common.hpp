@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fastdiv.hpp"
+
 namespace pff {
 
 constexpr int kBlock = 256;          // threads per workgroup of vector kernels (4 wavefronts)
@@ -32,10 +34,14 @@ template <typename T, int S> __device__ __forceinline__ cpx<T> mul_si(cpx<T> a) 
 }
 
 // One FFT axis: length n = prod(radix), twiddles tw[k] = exp(-2 pi i k / n).
+// Per stage st (Stockham, Ns = product of the earlier radices) the
+// reciprocal divisors of n / radix[st] and of Ns, and of n itself.
 struct AxisPlan {
   int n;
   int nstage;
   int radix[kMaxStages];
+  FastDiv dn;
+  FastDiv dnb[kMaxStages], dns[kMaxStages];
 };
 
 // Per-phase material constants (Lame lambda, mu and toughness Gc).
@@ -50,9 +56,16 @@ struct Vec16 {
 };
 
 // Geometry of the voxel grid and of the x-halved spectrum.
+// Half spectrum of one field (Nh points): a main block [z][y][kx], kx in
+// [0, nxm), with row pitch nxm (= nx/2 for even nx: 128-byte aligned rows for
+// the benchmark sizes), followed, for even nx, by the Nyquist plane
+// kx = nx/2 stored as [z][y].
 struct GridDesc {
   int nx, ny, nz, nxh;   // nxh = nx/2 + 1
   long long N, Nh;       // voxels, half-spectrum points per field
+  int nxm, nyq;          // main-block columns; 1 if the Nyquist plane exists
+  long long Nm;          // points of the main block (nz ny nxm)
+  FastDiv dnxm;          // division by nxm
 };
 
 // Deterministic block reduction of NR double accumulators; thread 0 of the

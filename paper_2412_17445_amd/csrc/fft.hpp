@@ -80,7 +80,7 @@ template <typename T, int S, int R> __device__ __forceinline__ void dftR(cpx<T>*
 
 template <typename T, int S, int R, int MAXE>
 __device__ __forceinline__ void stockham_stage(cpx<T>* buf, int n, int Ns, int nseq, int ltx,
-                                               const cpx<T>* tw) {
+                                               const cpx<T>* tw, const FastDiv& dnb, const FastDiv& dns) {
   constexpr int MB = (MAXE + R - 1) / R;        // butterflies per thread
   const int TX = 1 << ltx;
   const int nb = n / R;
@@ -93,7 +93,7 @@ __device__ __forceinline__ void stockham_stage(cpx<T>* buf, int n, int Ns, int n
     if (idx < total) {
       const int t = idx & (TX - 1);
       const int rest = idx >> ltx;
-      const int s = rest / nb;
+      const int s = (int)fdiv((uint32_t)rest, dnb);
       const int j = rest - s * nb;
       const int base_in = (s * n + j) * TX + t;
 #pragma unroll
@@ -107,9 +107,9 @@ __device__ __forceinline__ void stockham_stage(cpx<T>* buf, int n, int Ns, int n
     if (idx < total) {
       const int t = idx & (TX - 1);
       const int rest = idx >> ltx;
-      const int s = rest / nb;
+      const int s = (int)fdiv((uint32_t)rest, dnb);
       const int j = rest - s * nb;
-      const int kk = j % Ns;
+      const int kk = j - (int)fdiv((uint32_t)j, dns) * Ns;
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -128,19 +128,102 @@ __device__ __forceinline__ void stockham_stage(cpx<T>* buf, int n, int Ns, int n
   __syncthreads();
 }
 
+// ---- lengths known at compile time ----------------------------------------
+// The radix sequence of factor23 (8s, then one 4 or 2, then 3s), as constexpr.
+constexpr int c_pow2(int n) { return n % 2 == 0 ? 1 + c_pow2(n / 2) : 0; }
+constexpr int c_pow3(int n) { return n % 3 == 0 ? 1 + c_pow3(n / 3) : 0; }
+constexpr int c_nstage(int n) {
+  return c_pow2(n) / 3 + (c_pow2(n) % 3 != 0 ? 1 : 0) + c_pow3(n);
+}
+constexpr int c_radix(int n, int st) {
+  return st < c_pow2(n) / 3 ? 8
+       : (c_pow2(n) % 3 != 0 && st == c_pow2(n) / 3) ? (c_pow2(n) % 3 == 2 ? 4 : 2)
+       : 3;
+}
+
+// Stage with compile-time length N, radix R and span NS: all strides of the
+// index arithmetic are constants (shifts for powers of two).
+template <typename T, int S, int N, int R, int NS, int MAXE>
+__device__ __forceinline__ void stockham_stage_c(cpx<T>* buf, int nseq, int ltx, const cpx<T>* tw) {
+  constexpr int MB = (MAXE + R - 1) / R;
+  constexpr int NB = N / R;
+  constexpr int TWS = N / (NS * R);
+  const int TX = 1 << ltx;
+  const int total = (NB * nseq) << ltx;
+  cpx<T> v[MB][R];
+#pragma unroll
+  for (int q = 0; q < MB; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    if (idx < total) {
+      const int t = idx & (TX - 1);
+      const int rest = idx >> ltx;
+      const int s = rest / NB;
+      const int j = rest - s * NB;
+      const int base_in = ((s * N + j) << ltx) + t;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = buf[base_in + ((r * NB) << ltx)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MB; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    if (idx < total) {
+      const int t = idx & (TX - 1);
+      const int rest = idx >> ltx;
+      const int s = rest / NB;
+      const int j = rest - s * NB;
+      const int kk = j % NS;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cpx<T> w = tw[r * kk * TWS];
+          if (S > 0) w.y = -w.y;
+          v[q][r] = cmul(v[q][r], w);
+        }
+      }
+      dftR<T, S, R>(v[q]);
+      const int base_out = ((s * N + (j - kk) * R + kk) << ltx) + t;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[base_out + ((r * NS) << ltx)] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int S, int N, int ST, int NS, int MAXE>
+__device__ __forceinline__ void fft_c(cpx<T>* buf, int nseq, int ltx, const cpx<T>* tw) {
+  if constexpr (ST < c_nstage(N)) {
+    constexpr int R = c_radix(N, ST);
+    stockham_stage_c<T, S, N, R, NS, MAXE>(buf, nseq, ltx, tw);
+    fft_c<T, S, N, ST + 1, NS * R, MAXE>(buf, nseq, ltx, tw);
+  }
+}
+
 // In-place transform of nseq sequences (times TX = 2^ltx interleaved
 // columns) of length pl.n held in buf; tw is the LDS twiddle table
-// exp(-2 pi i k/n).
+// exp(-2 pi i k/n).  Lengths 32..512 (powers of two) take the compile-time
+// path, every other 3-smooth length the generic one.
 // Must be called by every thread of the block; ends with a barrier.
 template <typename T, int S, int MAXE>
 __device__ void fft_lds(cpx<T>* buf, int nseq, int ltx, const AxisPlan& pl, const cpx<T>* tw) {
+  switch (pl.n) {
+    case 32: fft_c<T, S, 32, 0, 1, MAXE>(buf, nseq, ltx, tw); return;
+    case 64: fft_c<T, S, 64, 0, 1, MAXE>(buf, nseq, ltx, tw); return;
+    case 128: fft_c<T, S, 128, 0, 1, MAXE>(buf, nseq, ltx, tw); return;
+    case 256: fft_c<T, S, 256, 0, 1, MAXE>(buf, nseq, ltx, tw); return;
+    case 512: fft_c<T, S, 512, 0, 1, MAXE>(buf, nseq, ltx, tw); return;
+    default: break;
+  }
   int Ns = 1;
   for (int st = 0; st < pl.nstage; ++st) {
     const int R = pl.radix[st];
-    if (R == 8) stockham_stage<T, S, 8, MAXE>(buf, pl.n, Ns, nseq, ltx, tw);
-    else if (R == 4) stockham_stage<T, S, 4, MAXE>(buf, pl.n, Ns, nseq, ltx, tw);
-    else if (R == 3) stockham_stage<T, S, 3, MAXE>(buf, pl.n, Ns, nseq, ltx, tw);
-    else stockham_stage<T, S, 2, MAXE>(buf, pl.n, Ns, nseq, ltx, tw);
+    const FastDiv& a = pl.dnb[st];
+    const FastDiv& b = pl.dns[st];
+    if (R == 8) stockham_stage<T, S, 8, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
+    else if (R == 4) stockham_stage<T, S, 4, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
+    else if (R == 3) stockham_stage<T, S, 3, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
+    else stockham_stage<T, S, 2, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
     Ns *= R;
   }
 }

@@ -1,12 +1,14 @@
 // FFT pass kernels with fused point-wise stages.
 //
 // A multi-dimensional real FFT round trip is split into axis passes over a
-// half spectrum stored per field as [z][y][kx], kx in [0, nx/2]:
+// half spectrum stored per field as a main block [z][y][kx], kx < nxm, and
+// (even nx) the Nyquist plane kx = nx/2 as [z][y] (see GridDesc):
 //   k_xfwd : per row (y, z): a "prologue" computes NF real values per voxel,
 //            pairs of fields are packed as one complex sequence, transformed
 //            along x in LDS and unpacked into two half spectra;
 //   k_axis : complex FFT along y or z for a tile of consecutive kx columns
-//            (coalesced loads), optionally followed by the point-wise
+//            (aligned 128-byte row segments) or of the Nyquist plane,
+//            optionally followed by the point-wise
 //            "spectral" stage and the inverse transform along the same axis
 //            (the last axis of the forward transform);
 //   k_xinv : per row: the half spectra of two fields are packed into one
@@ -54,7 +56,7 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xfwd(co
 #pragma unroll
   for (int q = 0; q < (NR > 0 ? NR : 1); ++q) red[q] = 0.0;
   for (int idx = threadIdx.x; idx < RB * nx; idx += blockDim.x) {
-    const int r = idx / nx, x = idx - r * nx;
+    const int r = (int)fdiv((uint32_t)idx, pl.dn), x = idx - r * nx;
     const long long row = row0 + r;
     T vals[2 * NP];
 #pragma unroll
@@ -67,20 +69,32 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xfwd(co
   fft_lds<T, -1, FftCap<T>::MAXE>(bufa, RB * NP, 0, pl, tw);
   const cpx<T>* res = bufa;
   const long long Nh = A.g.Nh;
-  for (int idx = threadIdx.x; idx < RB * NP * nxh; idx += blockDim.x) {
-    const int k = idx % nxh;
-    const int rest = idx / nxh;
-    const int p = rest % NP, r = rest / NP;
-    const long long row = row0 + r;
-    if (row >= nrows) continue;
-    const cpx<T> Z = res[(r * NP + p) * nx + k];
-    const cpx<T> Zm = res[(r * NP + p) * nx + (k == 0 ? 0 : nx - k)];
-    // X_a = (Z + conj Zm)/2, X_b = (Z - conj Zm)/(2i)
-    const cpx<T> Xa = {T(0.5) * (Z.x + Zm.x), T(0.5) * (Z.y - Zm.y)};
-    const cpx<T> Xb = {T(0.5) * (Z.y + Zm.y), T(-0.5) * (Z.x - Zm.x)};
-    const long long o = k + (long long)nxh * row;
-    spec[(2 * p) * Nh + o] = Xa;
-    if (2 * p + 1 < NF) spec[(2 * p + 1) * Nh + o] = Xb;
+  const int nxm = A.g.nxm;
+  const int nrow_here = (int)((nrows - row0) < RB ? (nrows - row0) : RB);
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    cpx<T>* sa = spec + (long long)(2 * p) * Nh;
+    cpx<T>* sb = spec + (long long)(2 * p + 1) * Nh;
+    // main block: the rows of this block are contiguous with pitch nxm
+    for (int idx = threadIdx.x; idx < nrow_here * nxm; idx += blockDim.x) {
+      const int r = (int)fdiv((uint32_t)idx, A.g.dnxm);
+      const int k = idx - r * nxm;
+      const cpx<T> Z = res[(r * NP + p) * nx + k];
+      const cpx<T> Zm = res[(r * NP + p) * nx + (k == 0 ? 0 : nx - k)];
+      // X_a = (Z + conj Zm)/2, X_b = (Z - conj Zm)/(2i)
+      const long long o = row0 * nxm + idx;
+      sa[o] = cpx<T>{T(0.5) * (Z.x + Zm.x), T(0.5) * (Z.y - Zm.y)};
+      if (2 * p + 1 < NF) sb[o] = cpx<T>{T(0.5) * (Z.y + Zm.y), T(-0.5) * (Z.x - Zm.x)};
+    }
+    // Nyquist plane (even nx): one value per row
+    if (A.g.nyq) {
+      for (int r = threadIdx.x; r < nrow_here; r += blockDim.x) {
+        const cpx<T> Z = res[(r * NP + p) * nx + nx / 2];
+        const long long o = A.g.Nm + row0 + r;
+        sa[o] = cpx<T>{Z.x, T(0)};
+        if (2 * p + 1 < NF) sb[o] = cpx<T>{Z.y, T(0)};
+      }
+    }
   }
   if constexpr (NR > 0) {
     __syncthreads();
@@ -90,66 +104,119 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xfwd(co
   }
 }
 
-// Complex FFT along y (axis 1) or z (axis 2) for a tile of TX consecutive
-// kx columns, one index of the remaining axis (blockIdx.y) and a group of
-// NFB fields (blockIdx.z).  With SPECTRAL (NFB = NF) the point-wise spectral
-// stage and the inverse transform along the same axis follow.
+constexpr int kXcds = 8;   // MI355X: workgroups are dispatched round-robin over 8 XCDs
+
+// Complex FFT along y (axis 1) or z (axis 2) for one tile and a group of NFB
+// fields (blockIdx.z).  Tiles (blockIdx.x, blockIdx.y):
+//   main block: TX consecutive kx columns (one 128-byte row segment for
+//   TX * sizeof(complex) = 128) at z = blockIdx.y (y pass) or y = blockIdx.y
+//   (z pass);
+//   Nyquist plane (blockIdx.x = number of main tiles, even nx only): TX
+//   consecutive z (y pass: pencils of [z][y] along y) or TX consecutive y
+//   (z pass) starting at blockIdx.y * TX; blocks past the plane exit.
+// With SPECTRAL (NFB = NF) the point-wise spectral stage and the inverse
+// transform along the same axis follow.  With remap, consecutive tiles are
+// given to workgroups on the same XCD, so that two tiles sharing 128-byte
+// lines meet in that XCD's L2.
 template <class P, int S, bool SPECTRAL>
 __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_axis(const typename P::Args A, const AxisPlan pl,
                                                  const cpx<typename P::real>* __restrict__ tw_g,
                                                  cpx<typename P::real>* __restrict__ spec, int axis,
-                                                 int ltx, int NFB) {
+                                                 int ltx, int NFB, int remap) {
   using T = typename P::real;
   constexpr int NF = P::NF;
   constexpr int MAXE = FftCap<T>::MAXE;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const GridDesc& g = A.g;
   const int n = pl.n;
   const int TX = 1 << ltx;
-  const int nxh = A.g.nxh, ny = A.g.ny;
-  const long long Nh = A.g.Nh;
-  const int kx0 = blockIdx.x * TX;
-  const int o = blockIdx.y;                       // z for the y pass, y for the z pass
+  int bx = blockIdx.x, by = blockIdx.y;
+  if (remap) {
+    const int nb = gridDim.x * gridDim.y;
+    const int per = nb / kXcds;
+    int b = blockIdx.y * gridDim.x + blockIdx.x;
+    if (b < per * kXcds) b = (b % kXcds) * per + b / kXcds;
+    bx = b % gridDim.x;
+    by = b / gridDim.x;
+  }
+  const int nkt = (g.nxm + TX - 1) >> ltx;
+  // element (j, t) of a field at off0 + j * js + t * ts, valid for t < tc;
+  // its mode (kx, ky, kz) = (kxb + t kxs, ., .) with j on the pass axis
+  long long off0;
+  int js, ts, tc, kxb, kxs, kb, ks;   // kb + t ks: the index of the third axis
+  if (bx < nkt) {
+    const int kx0 = bx << ltx;
+    tc = min(TX, g.nxm - kx0);
+    ts = 1;
+    kxb = kx0;
+    kxs = 1;
+    kb = by;
+    ks = 0;
+    if (axis == 1) {
+      off0 = (long long)by * g.ny * g.nxm + kx0;
+      js = g.nxm;
+    } else {
+      off0 = (long long)by * g.nxm + kx0;
+      js = g.ny * g.nxm;
+    }
+  } else {
+    kxb = g.nx / 2;
+    kxs = 0;
+    const int q0 = by << ltx;
+    const int lim = axis == 1 ? g.nz : g.ny;
+    if (q0 >= lim) return;
+    tc = min(TX, lim - q0);
+    kb = q0;
+    ks = 1;
+    if (axis == 1) {
+      off0 = g.Nm + (long long)q0 * g.ny;
+      js = 1;
+      ts = g.ny;
+    } else {
+      off0 = g.Nm + q0;
+      js = g.ny;
+      ts = 1;
+    }
+  }
   const int f0 = blockIdx.z * NFB;
   const int nfb = (f0 + NFB <= NF) ? NFB : NF - f0;
-  const long long stride = axis == 1 ? (long long)nxh : (long long)nxh * ny;
-  const long long base = axis == 1 ? (long long)nxh * ny * o : (long long)nxh * o;
-  const int seq = nfb * n * TX;
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* tw = buf + NFB * n * TX;
   for (int t = threadIdx.x; t < n; t += blockDim.x) tw[t] = tw_g[t];
-  for (int idx = threadIdx.x; idx < seq; idx += blockDim.x) {
-    const int t = idx & (TX - 1);
-    const int rest = idx >> ltx;                  // = f*n + j
-    const int j = rest % n, f = rest / n;
-    const int kx = kx0 + t;
-    cpx<T> val = {T(0), T(0)};
-    if (kx < nxh) val = spec[(f0 + f) * Nh + base + kx + stride * j];
-    buf[idx] = val;
+  const int per_field = n << ltx;
+  for (int f = 0; f < nfb; ++f) {
+    const cpx<T>* src = spec + (long long)(f0 + f) * g.Nh + off0;
+    for (int i2 = threadIdx.x; i2 < per_field; i2 += blockDim.x) {
+      const int t = i2 & (TX - 1), j = i2 >> ltx;
+      cpx<T> val = {T(0), T(0)};
+      if (t < tc) val = src[j * js + t * ts];
+      buf[f * per_field + i2] = val;
+    }
   }
   __syncthreads();
   fft_lds<T, S, MAXE>(buf, nfb, ltx, pl, tw);
   if constexpr (SPECTRAL) {
-    for (int idx = threadIdx.x; idx < TX * n; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < per_field; idx += blockDim.x) {
       const int t = idx & (TX - 1), j = idx >> ltx;
-      const int kx = kx0 + t;
-      if (kx >= nxh) continue;
+      if (t >= tc) continue;
+      const int kx = kxb + t * kxs, kq = kb + t * ks;
       cpx<T> v[NF];
 #pragma unroll
-      for (int f = 0; f < NF; ++f) v[f] = buf[(f * n + j) * TX + t];
-      if (axis == 1) P::spectral(A, kx, j, 0, v);
-      else P::spectral(A, kx, o, j, v);
+      for (int f = 0; f < NF; ++f) v[f] = buf[f * per_field + idx];
+      if (axis == 1) P::spectral(A, kx, j, kq, v);
+      else P::spectral(A, kx, kq, j, v);
 #pragma unroll
-      for (int f = 0; f < NF; ++f) buf[(f * n + j) * TX + t] = v[f];
+      for (int f = 0; f < NF; ++f) buf[f * per_field + idx] = v[f];
     }
     __syncthreads();
     fft_lds<T, -S, MAXE>(buf, nfb, ltx, pl, tw);
   }
-  for (int idx = threadIdx.x; idx < seq; idx += blockDim.x) {
-    const int t = idx & (TX - 1);
-    const int rest = idx >> ltx;
-    const int j = rest % n, f = rest / n;
-    const int kx = kx0 + t;
-    if (kx < nxh) spec[(f0 + f) * Nh + base + kx + stride * j] = buf[idx];
+  for (int f = 0; f < nfb; ++f) {
+    cpx<T>* dst = spec + (long long)(f0 + f) * g.Nh + off0;
+    for (int i2 = threadIdx.x; i2 < per_field; i2 += blockDim.x) {
+      const int t = i2 & (TX - 1), j = i2 >> ltx;
+      if (t < tc) dst[j * js + t * ts] = buf[f * per_field + i2];
+    }
   }
 }
 
@@ -172,33 +239,38 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xinv(co
   cpx<T>* tw = bufa + seq;
   for (int t = threadIdx.x; t < nx; t += blockDim.x) tw[t] = tw_g[t];
   const long long row0 = (long long)blockIdx.x * RB;
-  for (int idx = threadIdx.x; idx < seq; idx += blockDim.x) {
-    const int x = idx % nx;
-    const int rest = idx / nx;
-    const int p = rest % NP, r = rest / NP;
-    const long long row = row0 + r;
-    cpx<T> Z = {T(0), T(0)};
-    if (row < nrows) {
-      const bool mirror = x > nx / 2;
-      const int k = mirror ? nx - x : x;
-      const long long o = k + (long long)nxh * row;
-      cpx<T> a = spec[(2 * p) * Nh + o];
-      cpx<T> b = (2 * p + 1 < NF) ? spec[(2 * p + 1) * Nh + o] : cpx<T>{T(0), T(0)};
-      if (mirror) {
-        a.y = -a.y;
-        b.y = -b.y;
+  const int nxm = A.g.nxm;
+  const int nrow_here = (int)((nrows - row0) < RB ? (nrows - row0) : RB);
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const cpx<T>* sa = spec + (long long)(2 * p) * Nh;
+    const cpx<T>* sb = spec + (long long)(2 * p + 1) * Nh;
+    for (int idx = threadIdx.x; idx < RB * nx; idx += blockDim.x) {
+      const int r = (int)fdiv((uint32_t)idx, pl.dn);
+      const int x = idx - r * nx;
+      cpx<T> Z = {T(0), T(0)};
+      if (r < nrow_here) {
+        const bool mirror = x > nx / 2;
+        const int k = mirror ? nx - x : x;
+        const long long o = k < nxm ? (row0 + r) * nxm + k : A.g.Nm + row0 + r;
+        cpx<T> a = sa[o];
+        cpx<T> b = (2 * p + 1 < NF) ? sb[o] : cpx<T>{T(0), T(0)};
+        if (mirror) {
+          a.y = -a.y;
+          b.y = -b.y;
+        }
+        if (k == 0 || 2 * k == nx) {
+          // DC and Nyquist bins of a real field are real: their imaginary parts
+          // are round-off that would otherwise leak into the partner field of
+          // the pair (a + i b).  Dropping them gives the real part of the full
+          // inverse transform.
+          a.y = T(0);
+          b.y = T(0);
+        }
+        Z = cpx<T>{a.x - b.y, a.y + b.x};   // a + i b
       }
-      if (k == 0 || 2 * k == nx) {
-        // DC and Nyquist bins of a real field are real: their imaginary parts
-        // are round-off that would otherwise leak into the partner field of
-        // the pair (a + i b).  Dropping them gives the real part of the full
-        // inverse transform.
-        a.y = T(0);
-        b.y = T(0);
-      }
-      Z = cpx<T>{a.x - b.y, a.y + b.x};   // a + i b
+      bufa[(r * NP + p) * nx + x] = Z;
     }
-    bufa[(r * NP + p) * nx + x] = Z;
   }
   __syncthreads();
   fft_lds<T, 1, FftCap<T>::MAXE>(bufa, RB * NP, 0, pl, tw);
@@ -207,7 +279,7 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xinv(co
 #pragma unroll
   for (int q = 0; q < (NR > 0 ? NR : 1); ++q) red[q] = 0.0;
   for (int idx = threadIdx.x; idx < RB * nx; idx += blockDim.x) {
-    const int r = idx / nx, x = idx - r * nx;
+    const int r = (int)fdiv((uint32_t)idx, pl.dn), x = idx - r * nx;
     const long long row = row0 + r;
     if (row >= nrows) continue;
     T vals[2 * NP];

@@ -74,7 +74,15 @@ bool factor23(int n, AxisPlan& pl) {
   if (a == 2) pl.radix[pl.nstage++] = 4;
   else if (a == 1) pl.radix[pl.nstage++] = 2;
   for (int i = 0; i < b; ++i) pl.radix[pl.nstage++] = 3;
-  return pl.nstage <= kMaxStages;
+  if (pl.nstage > kMaxStages) return false;
+  pl.dn = make_fastdiv((uint32_t)n);
+  int Ns = 1;
+  for (int st = 0; st < pl.nstage; ++st) {
+    pl.dnb[st] = make_fastdiv((uint32_t)(n / pl.radix[st]));
+    pl.dns[st] = make_fastdiv((uint32_t)Ns);
+    Ns *= pl.radix[st];
+  }
+  return true;
 }
 
 template <typename T> struct DevTables {
@@ -135,6 +143,7 @@ struct pff_solver {
   // launch tuning (env PFF_AXIS_THREADS, PFF_SPEC_THREADS, PFF_AXIS_TX, PFF_SPEC_TX, PFF_X_ROWS)
   int axis_threads = 0, spec_threads = 0, axis_tx = 64, spec_tx = 64, x_rows = 64;
   double inner32 = 0.0;     // mixed: FP32 inner-solve tolerance (env PFF_INNER32)
+  int xcd_remap = 1;        // z pass: consecutive tiles on one XCD (env PFF_XCD_REMAP)
   std::vector<std::array<hipEvent_t, 6>> tim_pending, tim_free;
   double tim_ms[6] = {0, 0, 0, 0, 0, 0};
   long long tim_n[6] = {0, 0, 0, 0, 0, 0};
@@ -261,13 +270,13 @@ void run_pipeline(pff_solver* s, const typename P::Args& A, int& nblk_x, hipEven
   const int last = s->dim == 2 ? 1 : 2;
   const int nl = s->dim == 2 ? s->ny : s->nz;
   const int sthr = s->spec_threads > 0 ? std::min(s->spec_threads, nthr) : nthr;
-  const int txs = choose_tx(nl, NF, csz, s->nxh, sthr, s->spec_tx);
+  const int txs = choose_tx(nl, NF, csz, s->g.nxm, sthr, s->spec_tx);
   const size_t ldss = lds_axis(nl, NF, txs, csz);
   if (ldss > kLdsBudget || size_t(NF) * nl * txs > size_t(maxe_of(csz)) * sthr)
     throw Fail("axis too long for the LDS budget", PFF_ERR_ARG);
-  const dim3 gs((s->nxh + txs - 1) / txs, last == 1 ? s->nz : s->ny, 1);
+  const dim3 gs((s->g.nxm + txs - 1) / txs + s->g.nyq, last == 1 ? s->nz : s->ny, 1);
   if (s->dim == 2) {
-    k_axis<P, -1, true><<<gs, sthr, ldss, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txs), NF);
+    k_axis<P, -1, true><<<gs, sthr, ldss, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txs), NF, 0);
     LAUNCH_CHECK();
     if (ev) {
       HC(hipEventRecord(ev[2], s->stream));
@@ -277,16 +286,17 @@ void run_pipeline(pff_solver* s, const typename P::Args& A, int& nblk_x, hipEven
   } else {
     // forward / inverse y passes: one field per block, wide tiles
     const int athr = s->axis_threads > 0 ? std::min(s->axis_threads, nthr) : nthr;
-    const int txy = choose_tx(s->ny, 1, csz, s->nxh, athr, s->axis_tx);
+    const int txy = choose_tx(s->ny, 1, csz, s->g.nxm, athr, s->axis_tx);
     const size_t ldsy = lds_axis(s->ny, 1, txy, csz);
-    const dim3 gy((s->nxh + txy - 1) / txy, s->nz, NF);
-    k_axis<P, -1, false><<<gy, athr, ldsy, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txy), 1);
+    const dim3 gy((s->g.nxm + txy - 1) / txy + s->g.nyq, s->nz, NF);
+    k_axis<P, -1, false><<<gy, athr, ldsy, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txy), 1, 0);
     LAUNCH_CHECK();
     if (ev) HC(hipEventRecord(ev[2], s->stream));
-    k_axis<P, -1, true><<<gs, sthr, ldss, s->stream>>>(A, s->plan[2], tb.tw[2], spec, 2, log2i(txs), NF);
+    k_axis<P, -1, true><<<gs, sthr, ldss, s->stream>>>(A, s->plan[2], tb.tw[2], spec, 2, log2i(txs), NF,
+                                                       s->xcd_remap);
     LAUNCH_CHECK();
     if (ev) HC(hipEventRecord(ev[3], s->stream));
-    k_axis<P, 1, false><<<gy, athr, ldsy, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txy), 1);
+    k_axis<P, 1, false><<<gy, athr, ldsy, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txy), 1, 0);
     LAUNCH_CHECK();
     if (ev) HC(hipEventRecord(ev[4], s->stream));
   }
@@ -961,7 +971,12 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     s->N = (long long)s->nx * s->ny * s->nz;
     s->Nh = (long long)s->nxh * s->ny * s->nz;
     s->M = (long long)(s->C + 1) * s->N + 1;
-    s->g = GridDesc{s->nx, s->ny, s->nz, s->nxh, s->N, s->Nh};
+    {
+      const int nxm = s->nx % 2 == 0 ? s->nx / 2 : s->nxh;
+      const long long Nm = (long long)nxm * s->ny * s->nz;
+      s->g = GridDesc{s->nx, s->ny, s->nz, s->nxh, s->N, s->Nh, nxm, s->nx % 2 == 0 ? 1 : 0, Nm,
+                      make_fastdiv((uint32_t)nxm)};
+    }
     s->prm = *params;
     const pff_params& p = s->prm;
     if (!(p.l > 0) || !(p.k_resid >= 0) || !(p.delta_a > 0) || !(p.alpha > 0) || p.alpha > 1 ||
@@ -1010,6 +1025,7 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     s->axis_tx = envi("PFF_AXIS_TX", 16);
     s->spec_tx = envi("PFF_SPEC_TX", 8);
     s->x_rows = envi("PFF_X_ROWS", 64);
+    s->xcd_remap = envi("PFF_XCD_REMAP", 1) != 0 ? 1 : 0;
     {
       const char* v = std::getenv("PFF_INNER32");
       s->inner32 = v ? std::atof(v) : kInner32;
