@@ -35,7 +35,7 @@ KERNEL_NAMES = {0: "x-forward pass (R2C, tangent prologue)",
 
 def kernel_bytes(shape, precision):
     """Algorithmic HBM bytes per launch of each tangent-apply pass kernel
-    (compulsory reads + writes of that kernel, see the design notes)."""
+    (the compulsory reads and writes of that kernel)."""
     nz, ny, nx = shape
     N = nx * ny * nz
     c = 3 if nz == 1 else 6
@@ -159,6 +159,58 @@ def compare_fp64(prob, args, mixed_outs, mixed_s_per_step):
             "max_rel_diff": {k: float("%.3e" % v) for k, v in d.items()}}
 
 
+def serve_stream(args):
+    """Seeded request stream (synth.stream) through the request server:
+    Poisson arrivals, admission by footprint into slots, per-request latency
+    (submission to last increment) and whole-stream throughput."""
+    import numpy as np
+
+    from paper_2412_17445_amd import Server, problem_kwargs
+    from synth.stream import arrival_times, served_request
+
+    log(f"served stream: {args.serve_requests} requests at {args.serve_rate}/s, "
+        f"{args.serve_slots} slots, increments x{args.serve_inc_scale}")
+    reqs = [served_request(k, args.serve_inc_scale) for k in range(args.serve_requests)]
+    arr = arrival_times(len(reqs), args.serve_rate)
+    srv = Server(int(args.serve_budget_gb * (1 << 30)), args.serve_slots)
+    t0 = time.perf_counter()
+    tickets = []
+    for (prob, n), ta in zip(reqs, arr):
+        dt = ta - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(n, **problem_kwargs(prob)))
+    infos, applies_vox, incs, failed = [], 0, 0, 0
+    for k, tk in enumerate(tickets):
+        srv.wait(tk)
+        info = srv.info(tk)
+        res = srv.results(tk)
+        infos.append(info)
+        prob = reqs[k][0]
+        applies_vox += sum(r["applies"] for r in res) * prob.nvox
+        incs += len(res)
+        failed += info["status"] != 0
+        log(f"request {k}: {prob.notes}, {len(res)} increments, status {info['status']}, "
+            f"latency {info['t_done'] - info['t_submit']:.2f}s")
+    makespan = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lat = np.array([i["t_done"] - i["t_submit"] for i in infos])
+    wait = np.array([i["t_admit"] - i["t_submit"] for i in infos])
+    return {"requests": len(reqs), "failed": int(failed), "increments": int(incs),
+            "latency_p50_s": round(float(np.percentile(lat, 50)), 3),
+            "latency_p99_s": round(float(np.percentile(lat, 99)), 3),
+            "latency_max_s": round(float(lat.max()), 3),
+            "queue_wait_p50_s": round(float(np.percentile(wait, 50)), 3),
+            "makespan_s": round(makespan, 3),
+            "throughput_requests_per_s": round(len(reqs) / makespan, 3),
+            "throughput_mvoxel_applies_per_s": round(applies_vox / makespan / 1e6, 1),
+            "slots": args.serve_slots, "max_running": st["max_running"],
+            "peak_bytes": st["peak_bytes"], "budget_bytes": st["budget"],
+            "stream": f"synth.stream seeds 0..{len(reqs) - 1}, Poisson {args.serve_rate}/s, "
+                      f"increments scaled by {args.serve_inc_scale}"}
+
+
 def apply_mode(prob, args):
     """Tangent applies on a frozen synthetic state (for counter runs)."""
     import numpy as np
@@ -193,13 +245,20 @@ def main():
     ap.add_argument("--precision", default=None, help="override: fp64 or mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-every", type=int, default=8)
-    ap.add_argument("--mode", default="solve", choices=["solve", "apply", "copy"],
+    ap.add_argument("--mode", default="solve", choices=["solve", "apply", "copy", "serve"],
                     help="solve: timed increments (default); apply: tangent applies on a frozen "
                          "state (profiling counters); copy: plain device copy of 256 MiB "
                          "(counter calibration)")
     ap.add_argument("--applies", type=int, default=20)
     ap.add_argument("--no-compare", action="store_true",
                     help="mixed workloads: skip the plain-FP64 solve of the same increments")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served request stream")
+    ap.add_argument("--serve-requests", type=int, default=16)
+    ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-inc-scale", type=float, default=0.1,
+                    help="fraction of each request's 20-60 increments that is run")
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs one RVE solve on one GPU; multi-GPU runs are not "
@@ -220,6 +279,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"mode": "copy", "bytes_read_per_launch": src.numel() * 4,
                           "bytes_written_per_launch": dst.numel() * 4, "launches": 3}))
+        return
+    if args.mode == "serve":
+        out = serve_stream(args)
+        print(json.dumps({"metric": "RVE latency p50/p99 (served stream)", "value": out["latency_p50_s"],
+                          "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+                          "serving": out}), flush=True)
         return
     prob = problem_config(args.workload)
     if args.precision:
@@ -303,6 +368,8 @@ def main():
     if prob.precision == "mixed" and not args.no_compare:
         s.close()
         line["mixed_vs_fp64"] = compare_fp64(prob, args, warm + outs, elapsed / args.steps)
+    if not args.no_serve:
+        line["serving"] = serve_stream(args)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(prob)

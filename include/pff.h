@@ -46,6 +46,7 @@ typedef int pff_status;
 enum {
   PFF_OK = 0,
   PFF_NOT_CONVERGED = 1,   /* Newton or Krylov limit reached; state rolled back */
+  PFF_QUEUED = 2,          /* request server: the request has not finished yet */
   PFF_ERR_ARG = -1,        /* invalid argument (NULL, size, range) */
   PFF_ERR_OOM = -2,        /* device allocation failed */
   PFF_ERR_DEVICE = -3,     /* HIP runtime error */
@@ -110,7 +111,7 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
                       const uint8_t* phase_id, const uint8_t* crack_mask,
                       const pff_params* params, void* hip_stream, pff_solver** out);
 
-/* Bootstrap (paper silent; see the design notes): damage-free Helmholtz
+/* Bootstrap (the paper is silent on the start of the path): damage-free Helmholtz
  * solution phi0 with phi = 1 on the crack mask, a0 = Gamma(phi0), and the
  * homogeneous-solution predictor E_s for the first increment.
  * Outputs (host, may be NULL): a0, E_s. */
@@ -178,6 +179,69 @@ pff_status pff_load(pff_solver* s, const void* buf, size_t bytes);
 const char* pff_last_error(const pff_solver* s);
 
 void pff_destroy(pff_solver* s);
+
+/* Device bytes held by a solver (all of its buffers). */
+pff_status pff_solver_bytes(pff_solver* s, size_t* bytes);
+
+/* Device bytes a solver of this grid and precision (PFF_PREC_*) allocates,
+ * computed on the host without touching the device (the request server's
+ * admission estimate; equal to pff_solver_bytes of such a solver). */
+pff_status pff_footprint_bytes(const pff_grid* grid, int precision, size_t* bytes);
+
+/* ---- Request server (continuous batching of RVE solves on one GPU) ----------
+ * The paper solves one RVE; a service running many RVE problems (a
+ * parametric or multiscale study) submits them here.  A request is one
+ * problem as in pff_create plus a number of crack-length increments; its
+ * results are the per-increment outputs of pff_step.  Requests wait in
+ * arrival order and are admitted while one of max_slots slots is free and
+ * their footprint (pff_footprint_bytes) fits into hbm_budget_bytes minus the
+ * footprints of the running requests; a request that has been overtaken 8
+ * times stops further overtaking.  Each slot is a host thread with its own
+ * non-blocking HIP stream on the device current at pff_server_create, so
+ * running requests overlap on the device.  A request gives the same
+ * results alone and in a mix.  Inputs are copied at submission.  All
+ * functions are thread-safe.  Times are seconds since pff_server_create. */
+typedef struct pff_server pff_server;
+
+typedef struct {
+  uint64_t ticket;
+  int state;              /* 0 queued, 1 running, 2 done */
+  int status;             /* final status of the solve once done */
+  int n_done;             /* increments finished */
+  int slot;               /* slot that ran it, -1 before admission */
+  size_t footprint;       /* admission estimate, bytes */
+  double t_submit, t_admit, t_done;
+  double a0, E_s;         /* bootstrap outputs */
+} pff_request_info;
+
+typedef struct {
+  long long submitted, completed, queued, running, max_running;
+  int slots, reserved;
+  size_t budget, bytes_in_use, peak_bytes;
+  double clock;           /* server time of this snapshot */
+} pff_server_stats;
+
+/* Starts max_slots (1..64) worker threads.  PFF_ERR_DEVICE without a GPU. */
+pff_status pff_server_create(size_t hbm_budget_bytes, int max_slots, pff_server** out);
+/* Queues a request; *ticket identifies it.  PFF_ERR_ARG if its footprint
+ * exceeds the budget. */
+pff_status pff_server_submit(pff_server* srv, const pff_grid* grid, const pff_phase* phases, int n_phases,
+                             const uint8_t* phase_id, const uint8_t* crack_mask, const pff_params* params,
+                             int n_increments, uint64_t* ticket);
+/* Blocks until the request is done (timeout_seconds < 0: no limit).
+ * PFF_OK when done, PFF_QUEUED on time-out. */
+pff_status pff_server_wait(pff_server* srv, uint64_t ticket, double timeout_seconds);
+pff_status pff_server_info(pff_server* srv, uint64_t ticket, pff_request_info* out);
+/* Copies up to capacity per-increment results of a finished request;
+ * *n_out = number available.  PFF_QUEUED if not finished. */
+pff_status pff_server_results(pff_server* srv, uint64_t ticket, pff_increment_result* out, int capacity,
+                              int* n_out);
+/* Forgets a finished request. */
+pff_status pff_server_release(pff_server* srv, uint64_t ticket);
+pff_status pff_server_get_stats(pff_server* srv, pff_server_stats* out);
+const char* pff_server_last_error(pff_server* srv);
+/* Finishes the running requests, drops the queued ones, joins the slots. */
+void pff_server_destroy(pff_server* srv);
 
 #ifdef __cplusplus
 }

@@ -5,6 +5,6 @@ this package only builds it and marshals arguments to it.
 """
 
 from ._lib import load as load_library  # noqa: F401
-from .solver import PffError, Solver  # noqa: F401
+from .solver import PffError, Server, Solver, footprint_bytes, problem_kwargs  # noqa: F401
 
-__all__ = ["Solver", "PffError", "load_library"]
+__all__ = ["Solver", "Server", "PffError", "footprint_bytes", "problem_kwargs", "load_library"]

@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpff.so")
 
-PFF_OK, PFF_NOT_CONVERGED = 0, 1
+PFF_OK, PFF_NOT_CONVERGED, PFF_QUEUED = 0, 1, 2
 PFF_ERR_ARG, PFF_ERR_OOM, PFF_ERR_DEVICE, PFF_ERR_STATE = -1, -2, -3, -4
 PFF_PREC_FP64, PFF_PREC_MIXED = 0, 1
 
@@ -40,6 +40,21 @@ class pff_increment_result(C.Structure):
                 ("target_a", C.c_double), ("err", C.c_double * 3), ("seconds", C.c_double)]
 
 
+class pff_request_info(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("state", C.c_int), ("status", C.c_int),
+                ("n_done", C.c_int), ("slot", C.c_int), ("footprint", C.c_size_t),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("a0", C.c_double), ("E_s", C.c_double)]
+
+
+class pff_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_longlong), ("completed", C.c_longlong),
+                ("queued", C.c_longlong), ("running", C.c_longlong),
+                ("max_running", C.c_longlong), ("slots", C.c_int), ("reserved", C.c_int),
+                ("budget", C.c_size_t), ("bytes_in_use", C.c_size_t),
+                ("peak_bytes", C.c_size_t), ("clock", C.c_double)]
+
+
 EXPORTS = {
     "pff_abi_version": (C.c_int, []),
     "pff_create": (C.c_int, [C.POINTER(pff_grid), C.POINTER(pff_phase), C.c_int, C.c_void_p,
@@ -64,6 +79,20 @@ EXPORTS = {
     "pff_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "pff_last_error": (C.c_char_p, [C.c_void_p]),
     "pff_destroy": (None, [C.c_void_p]),
+    "pff_solver_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "pff_footprint_bytes": (C.c_int, [C.POINTER(pff_grid), C.c_int, C.POINTER(C.c_size_t)]),
+    "pff_server_create": (C.c_int, [C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),
+    "pff_server_submit": (C.c_int, [C.c_void_p, C.POINTER(pff_grid), C.POINTER(pff_phase), C.c_int,
+                                    C.c_void_p, C.c_void_p, C.POINTER(pff_params), C.c_int,
+                                    C.POINTER(C.c_uint64)]),
+    "pff_server_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.c_double]),
+    "pff_server_info": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(pff_request_info)]),
+    "pff_server_results": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(pff_increment_result),
+                                     C.c_int, C.POINTER(C.c_int)]),
+    "pff_server_release": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "pff_server_get_stats": (C.c_int, [C.c_void_p, C.POINTER(pff_server_stats)]),
+    "pff_server_last_error": (C.c_char_p, [C.c_void_p]),
+    "pff_server_destroy": (None, [C.c_void_p]),
 }
 
 _lib = None

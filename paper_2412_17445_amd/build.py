@@ -9,9 +9,10 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpff.so")
-SOURCES = [os.path.join(HERE, "csrc", "pff.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "pff.hip"), os.path.join(HERE, "csrc", "server.hip")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in
-           ("common.hpp", "fft.hpp", "pointlaw.hpp", "passes.hpp", "pipes.hpp", "krylov.hpp")]
+           ("common.hpp", "fastdiv.hpp", "fft.hpp", "pointlaw.hpp", "passes.hpp", "pipes.hpp",
+            "krylov.hpp")]
 HEADERS.append(os.path.join(ROOT, "include", "pff.h"))
 
 

@@ -154,10 +154,13 @@ struct pff_solver {
 
   bool mixed() const { return prm.precision == PFF_PREC_MIXED; }
 
+  size_t bytes_alloc = 0;    // device bytes held by this solver
   template <typename T> T* alloc(size_t count) {
     void* p = nullptr;
-    HC(hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)));
+    const size_t b = std::max<size_t>(count, 1) * sizeof(T);
+    HC(hipMalloc(&p, b));
     allocs.push_back(p);
+    bytes_alloc += b;
     return static_cast<T*>(p);
   }
   template <typename T> const DevTables<T>& tables() const;
@@ -1068,14 +1071,16 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     HC(hipHostMalloc((void**)&s->hstage, 8 * sizeof(double), hipHostMallocDefault));
     upload_tables<double>(s, s->td);
     upload_tables<float>(s, s->tf);
-    HC(hipMemset(s->eps_t, 0, C * N * sizeof(double)));
-    HC(hipMemset(s->eps_c, 0, C * N * sizeof(double)));
-    HC(hipMemset(s->phi, 0, N * sizeof(double)));
-    HC(hipMemset(s->phi_c, 0, N * sizeof(double)));
-    HC(hipMemset(s->Hn, 0, N * sizeof(double)));
-    HC(hipMemset(s->Edev, 0, 4 * sizeof(double)));
-    HC(hipMemset(s->scal, 0, SC_COUNT * sizeof(double)));
-    HC(hipDeviceSynchronize());
+    // stream-ordered: a solver created beside others running on their own
+    // streams (the request server) does not wait for their work
+    HC(hipMemsetAsync(s->eps_t, 0, C * N * sizeof(double), s->stream));
+    HC(hipMemsetAsync(s->eps_c, 0, C * N * sizeof(double), s->stream));
+    HC(hipMemsetAsync(s->phi, 0, N * sizeof(double), s->stream));
+    HC(hipMemsetAsync(s->phi_c, 0, N * sizeof(double), s->stream));
+    HC(hipMemsetAsync(s->Hn, 0, N * sizeof(double), s->stream));
+    HC(hipMemsetAsync(s->Edev, 0, 4 * sizeof(double), s->stream));
+    HC(hipMemsetAsync(s->scal, 0, SC_COUNT * sizeof(double), s->stream));
+    HC(hipStreamSynchronize(s->stream));
     return PFF_OK;
   });
   if (st != PFF_OK) {
@@ -1401,6 +1406,37 @@ pff_status pff_counters(pff_solver* s, long long* applies, long long* krylov_ite
     if (krylov_iters) *krylov_iters = s->kiters;
     return PFF_OK;
   });
+}
+
+pff_status pff_solver_bytes(pff_solver* s, size_t* bytes) {
+  if (!s || !bytes) return PFF_ERR_ARG;
+  *bytes = s->bytes_alloc;
+  return PFF_OK;
+}
+
+pff_status pff_footprint_bytes(const pff_grid* grid, int precision, size_t* bytes) {
+  if (!grid || !bytes || grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return PFF_ERR_ARG;
+  if (precision != PFF_PREC_FP64 && precision != PFF_PREC_MIXED) return PFF_ERR_ARG;
+  const size_t nx = grid->nx, ny = grid->ny, nz = grid->nz;
+  const size_t N = nx * ny * nz, dim = nz == 1 ? 2 : 3, C = dim == 2 ? 3 : 6;
+  const size_t M = (C + 1) * N + 1, Nh = (nx / 2 + 1) * ny * nz;
+  const size_t nts = (dim == 2 ? TsLayout<2>::COUNT : TsLayout<3>::COUNT) * N;
+  const bool mixed = precision == PFF_PREC_MIXED;
+  const size_t D = sizeof(double), F = sizeof(float);
+  size_t b = 2 * N;                                   // phase ids, crack mask
+  b += 2 * C * N * D;                                 // strain fluctuation, committed copy
+  b += 6 * N * D;                                     // phi, committed phi, guess, mask, Hn, H
+  if (dim == 2) b += N * D;                           // Laplacian of phi
+  b += 4 * D;                                         // E
+  b += nts * D + N * D + kNumVec * M * D;             // tangent state, aux, Krylov vectors
+  if (mixed) b += nts * F + N * F + kNumVec * M * F;
+  b += (C + 1) * Nh * 2 * D;                          // FP64 spectra
+  if (mixed) b += (C + 1) * Nh * 2 * F;               // FP32 spectra
+  const size_t part_len = std::max<size_t>(kRedBlocks, ny * nz + 16);
+  b += 2 * part_len * kMaxRed * D + SC_COUNT * D + 4 * N * D;
+  for (size_t n : {nx, ny, nz}) b += n * (2 * D + 3 * D) + n * (2 * F + 3 * F);   // FFT and spectral tables
+  *bytes = b;
+  return PFF_OK;
 }
 
 pff_status pff_save(pff_solver* s, void* buf, size_t* bytes) {

@@ -27,6 +27,47 @@ def _torch():
     return torch
 
 
+def marshal_problem(shape, phases, phase_id, mask, f, l, k=1e-6, delta_a=1.0, alpha=1.0,
+                    newton_tol=1e-8, krylov_rtol=1e-10, newton_maxit=50, krylov_maxit=5000,
+                    precision="fp64"):
+    """C structs and host arrays of one RVE problem (pff_create's inputs)."""
+    nz, ny, nx = shape
+    grid = L.pff_grid(nx, ny, nz)
+    ph = (L.pff_phase * len(phases))(*[L.pff_phase(*map(float, p)) for p in phases])
+    pid = np.ascontiguousarray(np.asarray(phase_id, dtype=np.uint8).reshape(-1))
+    if pid.size != nx * ny * nz:
+        raise ValueError("phase_id does not match the grid")
+    msk = None if mask is None else np.ascontiguousarray(np.asarray(mask, dtype=np.uint8).reshape(-1))
+    prm = L.pff_params()
+    prm.l, prm.k_resid = float(l), float(k)
+    fa = np.asarray(f, dtype=np.float64).reshape(-1)
+    for i in range(9):
+        prm.f[i] = float(fa[i])
+    prm.delta_a, prm.alpha = float(delta_a), float(alpha)
+    prm.newton_tol, prm.krylov_rtol = float(newton_tol), float(krylov_rtol)
+    prm.newton_maxit, prm.krylov_maxit = int(newton_maxit), int(krylov_maxit)
+    prm.precision = L.PFF_PREC_MIXED if precision == "mixed" else L.PFF_PREC_FP64
+    return grid, ph, pid, msk, prm
+
+
+def problem_kwargs(prob, **over):
+    kw = dict(shape=prob.shape, phases=prob.phases, phase_id=prob.phase_id, mask=prob.mask,
+              f=prob.f, l=prob.l, k=prob.k, delta_a=prob.delta_a, alpha=prob.alpha,
+              newton_tol=prob.newton_tol, krylov_rtol=prob.krylov_rtol,
+              newton_maxit=prob.newton_maxit, krylov_maxit=prob.krylov_maxit,
+              precision=prob.precision)
+    kw.update(over)
+    return kw
+
+
+def _result_dict(r):
+    return dict(increment=r.increment, newton_iters=r.newton_iters, krylov_iters=r.krylov_iters,
+                converged=bool(r.converged), applies=r.applies, applies_fp64=r.applies_fp64,
+                fp64_fallbacks=r.fp64_fallbacks, refinements=r.refinements,
+                sigma_M=list(r.sigma_M), E=r.load_factor, Gamma=r.crack_length,
+                a=r.target_a, err=list(r.err), seconds=r.seconds)
+
+
 class Solver:
     """One RVE solve.  `precision` is "fp64" or "mixed"."""
 
@@ -42,20 +83,10 @@ class Solver:
         self.M = (self.ncomp + 1) * self.N + 1
         self.mixed = precision == "mixed"
         self.wdtype = torch.float32 if self.mixed else torch.float64
-        grid = L.pff_grid(nx, ny, nz)
-        ph = (L.pff_phase * len(phases))(*[L.pff_phase(*map(float, p)) for p in phases])
-        pid = np.ascontiguousarray(np.asarray(phase_id, dtype=np.uint8).reshape(-1))
-        msk = None if mask is None else np.ascontiguousarray(
-            np.asarray(mask, dtype=np.uint8).reshape(-1))
-        prm = L.pff_params()
-        prm.l, prm.k_resid = float(l), float(k)
-        fa = np.asarray(f, dtype=np.float64).reshape(3, 3)
-        for i in range(9):
-            prm.f[i] = float(fa.reshape(-1)[i])
-        prm.delta_a, prm.alpha = float(delta_a), float(alpha)
-        prm.newton_tol, prm.krylov_rtol = float(newton_tol), float(krylov_rtol)
-        prm.newton_maxit, prm.krylov_maxit = int(newton_maxit), int(krylov_maxit)
-        prm.precision = L.PFF_PREC_MIXED if self.mixed else L.PFF_PREC_FP64
+        grid, ph, pid, msk, prm = marshal_problem(
+            shape, phases, phase_id, mask, f, l, k=k, delta_a=delta_a, alpha=alpha,
+            newton_tol=newton_tol, krylov_rtol=krylov_rtol, newton_maxit=newton_maxit,
+            krylov_maxit=krylov_maxit, precision=precision)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self._stream = stream
@@ -102,11 +133,14 @@ class Solver:
     def step(self):
         r = L.pff_increment_result()
         st = self._check(self.lib.pff_step(self.h, C.byref(r)), "pff_step")
-        return dict(status=st, increment=r.increment, newton_iters=r.newton_iters,
-                    krylov_iters=r.krylov_iters, converged=bool(r.converged), applies=r.applies,
-                    applies_fp64=r.applies_fp64, fp64_fallbacks=r.fp64_fallbacks, refinements=r.refinements,
-                    sigma_M=list(r.sigma_M), E=r.load_factor, Gamma=r.crack_length,
-                    a=r.target_a, err=list(r.err), seconds=r.seconds)
+        out = _result_dict(r)
+        out["status"] = st
+        return out
+
+    def device_bytes(self):
+        b = C.c_size_t()
+        self._check(self.lib.pff_solver_bytes(self.h, C.byref(b)), "pff_solver_bytes")
+        return b.value
 
     def get_state(self):
         c, N = self.ncomp, self.N
@@ -194,3 +228,87 @@ class Solver:
     def load(self, data):
         buf = (C.c_ubyte * len(data)).from_buffer_copy(data)
         self._check(self.lib.pff_load(self.h, buf, len(data)), "pff_load")
+
+
+def footprint_bytes(shape, precision):
+    """Device bytes of a solver of this grid (host-side estimate, no GPU)."""
+    nz, ny, nx = shape
+    lib = L.load()
+    b = C.c_size_t()
+    st = lib.pff_footprint_bytes(C.byref(L.pff_grid(nx, ny, nz)),
+                                 L.PFF_PREC_MIXED if precision == "mixed" else L.PFF_PREC_FP64,
+                                 C.byref(b))
+    if st != L.PFF_OK:
+        raise PffError(st, "pff_footprint_bytes")
+    return b.value
+
+
+class Server:
+    """Request server of the C ABI: RVE solves admitted by memory footprint
+    into `slots` concurrent slots on the current device."""
+
+    def __init__(self, budget_bytes, slots):
+        _torch()
+        self.lib = L.load()
+        h = C.c_void_p()
+        st = self.lib.pff_server_create(int(budget_bytes), int(slots), C.byref(h))
+        if st != L.PFF_OK:
+            raise PffError(st, "pff_server_create")
+        self.h = h
+
+    def submit(self, n_increments, **problem):
+        grid, ph, pid, msk, prm = marshal_problem(**problem)
+        t = C.c_uint64()
+        st = self.lib.pff_server_submit(self.h, C.byref(grid), ph, len(ph), pid.ctypes.data,
+                                        None if msk is None else msk.ctypes.data, C.byref(prm),
+                                        int(n_increments), C.byref(t))
+        if st != L.PFF_OK:
+            raise PffError(st, (self.lib.pff_server_last_error(self.h) or b"").decode())
+        return t.value
+
+    def wait(self, ticket, timeout=-1.0):
+        st = self.lib.pff_server_wait(self.h, C.c_uint64(ticket), float(timeout))
+        if st < 0:
+            raise PffError(st, "pff_server_wait")
+        return st == L.PFF_OK
+
+    def info(self, ticket):
+        i = L.pff_request_info()
+        st = self.lib.pff_server_info(self.h, C.c_uint64(ticket), C.byref(i))
+        if st != L.PFF_OK:
+            raise PffError(st, "pff_server_info")
+        return {k: getattr(i, k) for k, _ in L.pff_request_info._fields_}
+
+    def results(self, ticket):
+        n = C.c_int()
+        st = self.lib.pff_server_results(self.h, C.c_uint64(ticket), None, 0, C.byref(n))
+        if st != L.PFF_OK:
+            raise PffError(st, "pff_server_results")
+        arr = (L.pff_increment_result * max(n.value, 1))()
+        st = self.lib.pff_server_results(self.h, C.c_uint64(ticket), arr, n.value, C.byref(n))
+        if st != L.PFF_OK:
+            raise PffError(st, "pff_server_results")
+        return [_result_dict(arr[k]) for k in range(n.value)]
+
+    def release(self, ticket):
+        st = self.lib.pff_server_release(self.h, C.c_uint64(ticket))
+        if st != L.PFF_OK:
+            raise PffError(st, "pff_server_release")
+
+    def stats(self):
+        s = L.pff_server_stats()
+        st = self.lib.pff_server_get_stats(self.h, C.byref(s))
+        if st != L.PFF_OK:
+            raise PffError(st, "pff_server_get_stats")
+        return {k: getattr(s, k) for k, _ in L.pff_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pff_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,136 @@
+"""Request server of the C ABI (continuous batching of RVE solves).
+
+CPU: the admission estimate pff_footprint_bytes is host-only, and the
+server refuses to start without a device.  GPU: the estimate equals what a
+solver allocates; a request gives the same results alone and in a mix of
+concurrent requests; admission keeps the running footprints within the
+budget and overlaps requests on the device.
+"""
+
+import ctypes as C
+import os
+
+import numpy as np
+import pytest
+
+from paper_2412_17445_amd import _lib as L
+
+built = pytest.mark.skipif(not os.path.exists(L.LIB_PATH), reason="libpff.so not built")
+
+
+def _fp(shape, precision):
+    nz, ny, nx = shape
+    b = C.c_size_t()
+    st = L.load().pff_footprint_bytes(C.byref(L.pff_grid(nx, ny, nz)), precision, C.byref(b))
+    return st, b.value
+
+
+@built
+def test_footprint_is_host_side_and_scales_with_the_grid():
+    st, b2 = _fp((1, 256, 256), L.PFF_PREC_FP64)
+    assert st == L.PFF_OK
+    st, b2m = _fp((1, 256, 256), L.PFF_PREC_MIXED)
+    assert b2m > b2                      # FP32 copies added
+    _, small = _fp((64, 64, 64), L.PFF_PREC_MIXED)
+    _, big = _fp((128, 128, 128), L.PFF_PREC_MIXED)
+    assert 7.5 < big / small < 8.5       # linear in the voxel count
+    # 128^3 mixed: Krylov vectors dominate: 13 FP64 + 13 FP32 vectors of 7N+1
+    assert big > 13 * 12 * 7 * 128 ** 3
+    assert _fp((1, 8, 8), 5)[0] == L.PFF_ERR_ARG
+    assert L.load().pff_footprint_bytes(None, 0, None) == L.PFF_ERR_ARG
+
+
+@built
+def test_server_refuses_to_start_without_a_device():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = C.c_void_p()
+    assert L.load().pff_server_create(1 << 30, 2, C.byref(h)) == L.PFF_ERR_DEVICE
+    assert not h.value
+    assert L.load().pff_server_create(0, 2, C.byref(h)) == L.PFF_ERR_ARG
+
+
+# ---- GPU ----------------------------------------------------------------------
+
+def _problem(name, **over):
+    from synth import problem_config
+    p = problem_config(name)
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def _kw(prob, precision):
+    from paper_2412_17445_amd import problem_kwargs
+    return problem_kwargs(prob, precision=precision)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name,precision", [("tiny16", "fp64"), ("gc16", "mixed"), ("fib64", "mixed"),
+                                            ("pore24", "fp64"), ("part24", "mixed")])
+def test_footprint_equals_solver_allocation(name, precision):
+    from paper_2412_17445_amd import Solver, footprint_bytes
+    prob = _problem(name)
+    s = Solver.from_problem(prob, precision=precision)
+    assert s.device_bytes() == footprint_bytes(prob.shape, precision)
+    s.close()
+
+
+def _same(a, b):
+    assert len(a) == len(b)
+    for x, y in zip(a, b):
+        assert x["converged"] and y["converged"]
+        assert x["newton_iters"] == y["newton_iters"] and x["krylov_iters"] == y["krylov_iters"]
+        for k in ("E", "Gamma"):
+            assert abs(x[k] - y[k]) <= 1e-12 * abs(y[k]), (k, x[k], y[k])
+        sx, sy = np.array(x["sigma_M"]), np.array(y["sigma_M"])
+        assert np.abs(sx - sy).max() <= 1e-12 * np.abs(sy).max()
+
+
+@pytest.mark.gpu
+def test_request_gives_the_same_results_alone_and_in_a_mix():
+    from paper_2412_17445_amd import Server
+    target = (_problem("gc16"), "mixed", 3)
+    others = [(_problem("pore24"), "mixed", 2), (_problem("fib64"), "fp64", 2),
+              (_problem("part24"), "mixed", 1), (_problem("tiny16"), "fp64", 3)]
+    alone = Server(64 << 30, 1)
+    t = alone.submit(target[2], **_kw(target[0], target[1]))
+    assert alone.wait(t, 120.0)
+    ref = alone.results(t)
+    assert alone.info(t)["status"] == L.PFF_OK
+    alone.close()
+
+    mix = Server(64 << 30, 3)
+    tickets = [mix.submit(n, **_kw(p, prec)) for p, prec, n in others[:2]]
+    tt = mix.submit(target[2], **_kw(target[0], target[1]))
+    tickets += [mix.submit(n, **_kw(p, prec)) for p, prec, n in others[2:]]
+    for tk in tickets + [tt]:
+        assert mix.wait(tk, 300.0)
+        assert mix.info(tk)["status"] == L.PFF_OK, mix.info(tk)
+    _same(mix.results(tt), ref)
+    st = mix.stats()
+    assert st["completed"] == 5 and st["max_running"] >= 2 and st["bytes_in_use"] == 0
+    infos = [mix.info(tk) for tk in tickets + [tt]]
+    # requests overlapped in time on the device
+    assert any(a["t_admit"] < b["t_done"] and b["t_admit"] < a["t_done"]
+               for i, a in enumerate(infos) for b in infos[i + 1:])
+    mix.close()
+
+
+@pytest.mark.gpu
+def test_admission_respects_the_memory_budget():
+    from paper_2412_17445_amd import PffError, Server, footprint_bytes
+    small = _problem("tiny16")
+    fp = footprint_bytes(small.shape, "fp64")
+    srv = Server(2 * fp + fp // 2, 4)          # room for two at a time
+    tickets = [srv.submit(1, **_kw(small, "fp64")) for _ in range(6)]
+    for tk in tickets:
+        assert srv.wait(tk, 120.0)
+        assert srv.info(tk)["status"] == L.PFF_OK
+    st = srv.stats()
+    assert st["peak_bytes"] <= st["budget"] and st["max_running"] <= 2 and st["completed"] == 6
+    big = _problem("pore24")
+    with pytest.raises(PffError):
+        srv.submit(1, **_kw(big, "mixed"))     # footprint above the whole budget
+    srv.close()
