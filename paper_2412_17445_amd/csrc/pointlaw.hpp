@@ -256,23 +256,45 @@ __device__ __forceinline__ void sigma0(const Split<T, D>& sp, T lam, T mu, T (&S
 }
 
 // C:w for a Mandel strain w (output Mandel), C at the split state sp.
+// The eigenbasis components W' = V^T W V are formed as V^T (W V) and the
+// result V (theta o W') V^T as (V Wp) V^T, upper triangles only (both are
+// symmetric): about 90 multiply-adds in 3D.
 template <typename T, int D>
 __device__ __forceinline__ void tangent_apply(const Split<T, D>& sp, T lam, T mu, T g,
                                              const T* w_m, T* out_m) {
   T W[D][D];
   mandel_to_tensor<T, D>(w_m, W);
-  // eigenbasis components W' = V^T W V, scaled by theta
-  T Wp[D][D];
+  const auto& V = sp.e.V;
+  T WV[D][D];
 #pragma unroll
-  for (int a = 0; a < D; ++a)
+  for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int b = 0; b < D; ++b) {
       T acc = T(0);
 #pragma unroll
-      for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j) acc += W[i][j] * V[j][b];
+      WV[i][b] = acc;
+    }
+  T Wp[D][D];   // theta o (V^T W V), symmetric
 #pragma unroll
-        for (int j = 0; j < D; ++j) acc += sp.e.V[i][a] * W[i][j] * sp.e.V[j][b];
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = a; b < D; ++b) {
+      T acc = T(0);
+#pragma unroll
+      for (int i = 0; i < D; ++i) acc += V[i][a] * WV[i][b];
       Wp[a][b] = sp.theta[a][b] * acc;
+      Wp[b][a] = Wp[a][b];
+    }
+  T VW[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      T acc = T(0);
+#pragma unroll
+      for (int a = 0; a < D; ++a) acc += V[i][a] * Wp[a][b];
+      VW[i][b] = acc;
     }
   T trw = T(0);
 #pragma unroll
@@ -282,13 +304,12 @@ __device__ __forceinline__ void tangent_apply(const Split<T, D>& sp, T lam, T mu
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
+    for (int j = i; j < D; ++j) {
       T acc = T(0);
 #pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = 0; b < D; ++b) acc += sp.e.V[i][a] * Wp[a][b] * sp.e.V[j][b];
+      for (int b = 0; b < D; ++b) acc += VW[i][b] * V[j][b];
       O[i][j] = T(2) * mu * (W[i][j] + (g - T(1)) * acc) + (i == j ? lam_eff * trw : T(0));
+      O[j][i] = O[i][j];
     }
   tensor_to_mandel<T, D>(O, out_m);
 }
