@@ -7,7 +7,7 @@ path.  `value` is the in-solver throughput in Mvoxel tangent-applies/s
 (voxels x tangent applications / wall time of the K timed increments, all
 inputs resident in HBM).  The roofline object covers the dominant FFT pass
 kernel of the tangent apply, timed live with HIP events on the solver stream
-(every 8th apply sampled); `cpu_baseline` times the CPU oracle's tangent
+(every 7th apply sampled); `cpu_baseline` times the CPU oracle's tangent
 apply on a bounded sample of the same workload.
 """
 
@@ -33,9 +33,13 @@ KERNEL_NAMES = {0: "x-forward pass (R2C, tangent prologue)",
                 4: "x-inverse pass (C2R, tangent epilogue)"}
 
 
-def kernel_bytes(shape, precision):
+def kernel_bytes(shape, precision, variant=0):
     """Algorithmic HBM bytes per launch of each tangent-apply pass kernel
-    (the compulsory reads and writes of that kernel)."""
+    (the compulsory reads and writes of that kernel).  Variants 1-4 are the
+    applies fused with BiCGSTAB steps: the x-inverse pass also reads the
+    vector of its inner product (r_hat or s); in variants 3 and 4 the
+    x-forward pass also forms the direction p (reads r, p, v, rewrites p) or
+    s (reads r, v, writes s)."""
     nz, ny, nx = shape
     N = nx * ny * nz
     c = 3 if nz == 1 else 6
@@ -44,9 +48,18 @@ def kernel_bytes(shape, precision):
     T = 4 if precision == "mixed" else 8
     spec = nf * nh * 2 * T                       # all half spectra of one pass
     ts_fields = 6 if nz == 1 else 10          # strain frame, phi, Hs, r
-    xf = (c + 1) * N * T + T + ts_fields * N * T + 2 * N + spec + N * T
+    V = (c + 1) * N * T                          # voxel part of one Krylov vector
+    xf = V + T + ts_fields * N * T + 2 * N + spec + N * T
     ax = 2 * spec
-    xi = spec + N * T + 2 * N + (c + 1) * N * T
+    xi = spec + N * T + 2 * N + V
+    if variant in (1, 2):
+        xi += V
+    elif variant == 3:
+        xf += 3 * V
+        xi += V
+    elif variant == 4:
+        xf += 2 * V
+        xi += V
     if nz == 1:
         return {0: xf, 1: ax, 2: 0, 3: 0, 4: xi}
     return {0: xf, 1: ax, 2: ax, 3: ax, 4: xi}
@@ -244,7 +257,8 @@ def main():
     ap.add_argument("--workload", default="particles3d_128")
     ap.add_argument("--precision", default=None, help="override: fp64 or mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--timing-every", type=int, default=8)
+    ap.add_argument("--timing-every", type=int, default=7,
+                    help="sample every n-th apply (odd: the fused applies alternate modes)")
     ap.add_argument("--mode", default="solve", choices=["solve", "apply", "copy", "serve"],
                     help="solve: timed increments (default); apply: tangent applies on a frozen "
                          "state (profiling counters); copy: plain device copy of 256 MiB "
@@ -325,21 +339,38 @@ def main():
     value = applies * N / elapsed / 1e6
 
     tim = s.timing_read()
-    kb = kernel_bytes(prob.shape, prob.precision)
-    kern = {}
-    for k in range(5):
-        n, ms = tim[k]
-        if n > 0 and kb[k] > 0:
-            kern[k] = (ms / n, n, ms)
-    dom = max(kern, key=lambda k: kern[k][2])
-    avg_ms = kern[dom][0]
-    achieved = kb[dom] / (avg_ms * 1e-3) / 1e9
-    traffic = load_traffic(args.workload, dom, kb[dom])
+    # per (precision, pass kernel): algorithmic bytes and time over the timed
+    # launches of every apply mode
+    agg = {}
+    for slot, (n, ms) in tim.items():
+        group, k = divmod(slot, 6)
+        if k == 5:
+            continue
+        prec = "mixed" if group >= 5 else "fp64"
+        b = kernel_bytes(prob.shape, prec, group % 5)[k]
+        if b <= 0:
+            continue
+        a = agg.setdefault((prec, k), [0, 0.0, 0.0])
+        a[0] += n
+        a[1] += ms
+        a[2] += n * b
+    dom = max(agg, key=lambda q: agg[q][1])
+    n_dom, ms_dom, bytes_dom = agg[dom]
+    avg_ms = ms_dom / n_dom
+    alg_per_launch = bytes_dom / n_dom
+    achieved = alg_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = load_traffic(args.workload, dom[1], alg_per_launch) if dom[0] == "mixed" else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": KERNEL_NAMES[dom], "alg_bytes_per_launch": kb[dom],
-                "avg_launch_us": round(avg_ms * 1e3, 2), "timed_launches": kern[dom][1]}
-    apply_n, apply_ms = tim[5]
+                "kernel": KERNEL_NAMES[dom[1]] + (" FP32" if dom[0] == "mixed" else " FP64"),
+                "alg_bytes_per_launch": round(alg_per_launch), "avg_launch_us": round(avg_ms * 1e3, 2),
+                "timed_launches": n_dom}
+    by_mode = {"fp32": [0] * 5, "fp64": [0] * 5}
+    for sl, (n, _) in tim.items():
+        if sl % 6 == 5:
+            by_mode["fp32" if sl // 6 >= 5 else "fp64"][(sl // 6) % 5] += n
+    whole = [v for sl, v in tim.items() if sl % 6 == 5]
+    apply_n, apply_ms = sum(v[0] for v in whole), sum(v[1] for v in whole)
     line = {
         "metric": "Mvoxel tangent-applies/s",
         "value": round(value, 2),
@@ -362,6 +393,7 @@ def main():
                    "fp64_refinements": sum(o["refinements"] for o in outs),
                    "fp64_fallback_solves": sum(o["fp64_fallbacks"] for o in outs),
                    "apply_us_avg": round(apply_ms / max(apply_n, 1) * 1e3, 2),
+                   "sampled_applies_by_mode": by_mode,
                    "parallelism": "single GPU"},
         "roofline": roofline,
     }

@@ -158,9 +158,13 @@ pff_status pff_krylov_solve(pff_solver* s, const void* b_dev, void* x_dev, doubl
 
 /* Kernel timing (measurement support).  With every > 0, each every-th
  * tangent apply brackets its FFT pass kernels with HIP events on the solver
- * stream; every = 0 disables.  pff_timing_read(kernel k) returns the number
- * of timed launches and their summed duration in milliseconds for
- * k = 0 x-forward pass (with the tangent prologue), 1 first strided-axis
+ * stream; every = 0 disables.  pff_timing_read(slot) returns the number of
+ * timed launches and their summed duration in milliseconds for
+ * slot = 6 * (5 * prec + variant) + k, with prec 1 for FP32 applies and 0
+ * for FP64 ones; variant 0 a plain apply, 1 (3) the apply whose epilogue
+ * forms the BiCGSTAB product (r_hat, v) (and whose prologue forms the
+ * direction p), 2 (4) the apply whose epilogue forms (t, s), (t, t) (and
+ * whose prologue forms s); k = 0 x-forward pass (with the tangent prologue), 1 first strided-axis
  * pass (y; with the spectral stage in 2D), 2 z pass with the spectral stage
  * (3D), 3 inverse y pass (3D), 4 x-inverse pass (with the epilogue),
  * 5 the whole apply.  Reading synchronises the stream and resets nothing. */

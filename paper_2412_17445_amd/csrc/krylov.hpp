@@ -13,7 +13,7 @@ namespace pff {
 
 enum KrylovScalar {
   KS_RHO = 0, KS_RHO_OLD, KS_ALPHA, KS_OMEGA, KS_BETA, KS_RR, KS_BNORM, KS_FLAG,
-  KS_RV, KS_TS, KS_TT, KS_RNORM, KS_TRUE, KS_COUNT
+  KS_RV, KS_TS, KS_TT, KS_RNORM, KS_TRUE, KS_ULAST, KS_COUNT
 };
 
 constexpr int kRedBlocks = 1024;   // upper bound on the blocks of a vector reduction
@@ -265,6 +265,68 @@ struct FinRR {      // ||r||^2 and the next rho, beta
     }
   }
 };
+
+// Finisher of a fused tangent apply (mode 1 or 2): fixed-order totals of the
+// prologue partials (the border row J3) and of the epilogue partials (the
+// voxel part of the inner products); writes J u and the updated vector at
+// their trailing entries, adds the trailing terms to the inner products and
+// forms alpha (mode 1) or omega (mode 2) with the breakdown flags.
+// vout_last and dv_last are the same entry in mode 2 (no __restrict__).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fin_fused(const double* __restrict__ part0,
+                                                      const double* __restrict__ part1, int nblk, int mode,
+                                                      int pro, T* Jv_last, T* vout_last, const T* dv_last,
+                                                      double* ks) {
+  __shared__ double lds[kBlock];
+  __shared__ double tot[3];
+  const double* src[3] = {part0, part1, part1 + nblk};
+  for (int q = 0; q < 3; ++q) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc += src[q][b];
+    lds[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+      if (threadIdx.x < h) lds[threadIdx.x] += lds[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) tot[q] = lds[0];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const T j3 = T(tot[0]);
+  // mode 1 pairs J u with r_hat; mode 2 with u itself, whose trailing entry
+  // the prologue formed (pro) or the caller holds in dv
+  T dlast;
+  if (pro) {
+    const T ulast = T(ks[KS_ULAST]);
+    dlast = mode == 1 ? *dv_last : ulast;
+    *vout_last = ulast;
+  } else {
+    dlast = *dv_last;
+  }
+  *Jv_last = j3;
+  if (mode == 1) {
+    const double rv = tot[1] + double(dlast) * double(j3);
+    ks[KS_RV] = rv;
+    if (rv == 0.0 || !isfinite(rv)) {
+      ks[KS_FLAG] = 1.0;
+      ks[KS_ALPHA] = 0.0;
+    } else {
+      ks[KS_ALPHA] = ks[KS_RHO] / rv;
+    }
+  } else {
+    const double ts = tot[1] + double(j3) * double(dlast);
+    const double tt = tot[2] + double(j3) * double(j3);
+    ks[KS_TS] = ts;
+    ks[KS_TT] = tt;
+    if (tt == 0.0 || !isfinite(tt)) {
+      ks[KS_FLAG] = 2.0;
+      ks[KS_OMEGA] = 0.0;
+    } else {
+      ks[KS_OMEGA] = ts / tt;
+    }
+  }
+}
 
 template <typename T>
 struct FinLast {    // write the reduced total into the trailing entry of a vector

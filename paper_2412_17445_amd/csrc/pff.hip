@@ -47,6 +47,7 @@ constexpr double kDiverged = 1e8;
 constexpr int kBisection = 100;
 constexpr int kMaxCycles = 8;
 constexpr int kNumVec = 13;          // Krylov work vectors
+constexpr int kTimSlots = 60;        // pass timing: 6 kernels x 5 apply variants x 2 precisions
 constexpr double kInner32 = 5e-2;        // relative residual of each FP32 inner solve (mixed)
 constexpr int kMixedMaxit32 = 3000;      // FP32 BiCGSTAB iteration cap per inner solve
 constexpr int kMaxRefine = 8;            // FP64 refinement steps per Newton iteration
@@ -139,14 +140,20 @@ struct pff_solver {
   bool bootstrapped = false;
   bool ts_valid = false;
   bool trace = false;       // PFF_TRACE=1: per-Newton-iteration log on stderr
+  bool ktrace = false;      // PFF_TRACE=2: the first BiCGSTAB scalars of every solve
   int tim_every = 0;        // sampled kernel timing of the tangent apply
   // launch tuning (env PFF_AXIS_THREADS, PFF_SPEC_THREADS, PFF_AXIS_TX, PFF_SPEC_TX, PFF_X_ROWS)
   int axis_threads = 0, spec_threads = 0, axis_tx = 64, spec_tx = 64, x_rows = 64;
   double inner32 = 0.0;     // mixed: FP32 inner-solve tolerance (env PFF_INNER32)
   int xcd_remap = 1;        // z pass: consecutive tiles on one XCD (env PFF_XCD_REMAP)
+  int fused = 1;            // BiCGSTAB steps fused into the applies (env PFF_FUSED): 0 none,
+                            // 1 inner products in the epilogues, 2 also the p / s updates in the prologues
+  hipEvent_t ev_scal = nullptr;   // marks the scalar copy of a BiCGSTAB iteration
+  // sampled pass timing per slot 6 * (5 * fp32 + variant) + kernel, variant = mode + 2 * pro
   std::vector<std::array<hipEvent_t, 6>> tim_pending, tim_free;
-  double tim_ms[6] = {0, 0, 0, 0, 0, 0};
-  long long tim_n[6] = {0, 0, 0, 0, 0, 0};
+  std::vector<int> tim_group;
+  double tim_ms[kTimSlots] = {};
+  long long tim_n[kTimSlots] = {};
   int n = 0;
   double a = 0.0, E = 0.0, E_s = 0.0;
   long long applies = 0, kiters = 0;
@@ -288,7 +295,8 @@ void run_pipeline(pff_solver* s, const typename P::Args& A, int& nblk_x, hipEven
     }
   } else {
     // forward / inverse y passes: one field per block, wide tiles
-    const int athr = s->axis_threads > 0 ? std::min(s->axis_threads, nthr) : nthr;
+    // measured: 256 threads for FP32 tiles, 512 for FP64 (unless set by env)
+    const int athr = s->axis_threads > 0 ? std::min(s->axis_threads, nthr) : (csz == 8 ? 256 : 512);
     const int txy = choose_tx(s->ny, 1, csz, s->g.nxm, athr, s->axis_tx);
     const size_t ldsy = lds_axis(s->ny, 1, txy, csz);
     const dim3 gy((s->g.nxm + txy - 1) / txy + s->g.nyq, s->nz, NF);
@@ -310,7 +318,7 @@ void run_pipeline(pff_solver* s, const typename P::Args& A, int& nblk_x, hipEven
 
 // ---- live kernel timing (sampled event pairs on the solver stream) -------------
 
-hipEvent_t* timing_acquire(pff_solver* s);
+hipEvent_t* timing_acquire(pff_solver* s, int group);
 void timing_harvest(pff_solver* s);
 
 void sync_scal(pff_solver* s) {
@@ -478,13 +486,47 @@ struct Impl {
     A.tab = spec_tables<TW>(s);
   }
 
+  // Fused BiCGSTAB apply (mode 1: u = r + beta (v - omega w) -> v, J u -> Jv,
+  // alpha = rho / (dv, J u); mode 2: u = r - alpha w -> vout, J u -> Jv,
+  // omega = (J u, dv) / (J u, J u)); see TangentPipe.
+  static void apply_fused(pff_solver* s, int mode, int pro, const TW* v, const TW* r, const TW* w,
+                          TW* vout, TW* Jv, const TW* dv) {
+    typename TangentPipe<TW, DIM>::Args A;
+    fill_tangent_args(s, A);
+    A.v = v;
+    A.Jv = Jv;
+    A.mode = mode;
+    A.pro = pro;
+    A.r = r;
+    A.w = w;
+    A.vout = vout;
+    A.dv = dv;
+    A.ks = s->scal + SC_KS;
+    int nblk = 0;
+    const int grp = 5 * (std::is_same<TW, float>::value ? 1 : 0) + mode + 2 * pro;
+    hipEvent_t* ev = (s->tim_every > 0 && s->applies % s->tim_every == 0) ? timing_acquire(s, grp) : nullptr;
+    run_pipeline<TangentPipe<TW, DIM>>(s, A, nblk, ev);
+    const long long last = (long long)(C + 1) * s->N;
+    k_fin_fused<TW><<<1, kBlock, 0, s->stream>>>(s->part0, s->part1, nblk, mode, pro, Jv + last,
+                                                 pro ? vout + last : nullptr, dv + last, s->scal + SC_KS);
+    LAUNCH_CHECK();
+    s->applies++;
+    if (std::is_same<TW, double>::value) s->applies64++;
+  }
+
   static void apply(pff_solver* s, const TW* v, TW* Jv) {
     typename TangentPipe<TW, DIM>::Args A;
     fill_tangent_args(s, A);
     A.v = v;
     A.Jv = Jv;
+    A.mode = 0;
+    A.pro = 0;
+    A.r = A.w = A.dv = nullptr;
+    A.vout = nullptr;
+    A.ks = nullptr;
     int nblk = 0;
-    hipEvent_t* ev = (s->tim_every > 0 && s->applies % s->tim_every == 0) ? timing_acquire(s) : nullptr;
+    const int grp = 5 * (std::is_same<TW, float>::value ? 1 : 0);
+    hipEvent_t* ev = (s->tim_every > 0 && s->applies % s->tim_every == 0) ? timing_acquire(s, grp) : nullptr;
     run_pipeline<TangentPipe<TW, DIM>>(s, A, nblk, ev);
     typename FinLast<TW>::Args F{Jv + (long long)(C + 1) * s->N};
     k_reduce<FinLast<TW>><<<1, kBlock, 0, s->stream>>>(s->part0, nblk, 1, F);
@@ -579,26 +621,63 @@ struct Impl {
       k_bicg_shadow<TW><<<g1, kBlock, 0, s->stream>>>(r, rhat, ks, kShadowSeed, M, s->part0);
       LAUNCH_CHECK();
       reduce_ks(s, 1, 1);
+      bool issued = false;   // this iteration's direction apply is already queued
       while (total < maxit) {
         ++total;
-        k_bicg_p<TW><<<g1, kBlock, 0, s->stream>>>(p, r, v, ks, M);
-        LAUNCH_CHECK();
-        apply(s, p, v);
-        k_dots<TW, 1><<<g1, kBlock, 0, s->stream>>>(rhat, v, nullptr, nullptr, nullptr, nullptr, M, s->part0);
-        LAUNCH_CHECK();
-        reduce_ks(s, 1, 2);
-        k_bicg_s<TW><<<g1, kBlock, 0, s->stream>>>(sv, r, v, ks, M);
-        LAUNCH_CHECK();
-        apply(s, sv, t);
-        k_dots<TW, 2><<<g1, kBlock, 0, s->stream>>>(t, sv, t, t, nullptr, nullptr, M, s->part0);
-        LAUNCH_CHECK();
-        reduce_ks(s, 2, 3);
+        if (s->fused == 2) {
+          // p = r + beta (p - omega v) formed in the prologue; v = J p; alpha = rho / (r_hat, v)
+          if (!issued) apply_fused(s, 1, 1, p, r, v, p, v, rhat);
+          issued = false;
+          // s = r - alpha v formed in the prologue; t = J s; omega = (t, s) / (t, t)
+          apply_fused(s, 2, 1, nullptr, r, v, sv, t, sv);
+        } else if (s->fused == 1) {
+          // streaming p / s updates; inner products in the apply epilogues
+          if (!issued) {
+            k_bicg_p<TW><<<g1, kBlock, 0, s->stream>>>(p, r, v, ks, M);
+            LAUNCH_CHECK();
+            apply_fused(s, 1, 0, p, nullptr, nullptr, nullptr, v, rhat);
+          }
+          issued = false;
+          k_bicg_s<TW><<<g1, kBlock, 0, s->stream>>>(sv, r, v, ks, M);
+          LAUNCH_CHECK();
+          apply_fused(s, 2, 0, sv, nullptr, nullptr, nullptr, t, sv);
+        } else {
+          k_bicg_p<TW><<<g1, kBlock, 0, s->stream>>>(p, r, v, ks, M);
+          LAUNCH_CHECK();
+          apply(s, p, v);
+          k_dots<TW, 1><<<g1, kBlock, 0, s->stream>>>(rhat, v, nullptr, nullptr, nullptr, nullptr, M, s->part0);
+          LAUNCH_CHECK();
+          reduce_ks(s, 1, 2);
+          k_bicg_s<TW><<<g1, kBlock, 0, s->stream>>>(sv, r, v, ks, M);
+          LAUNCH_CHECK();
+          apply(s, sv, t);
+          k_dots<TW, 2><<<g1, kBlock, 0, s->stream>>>(t, sv, t, t, nullptr, nullptr, M, s->part0);
+          LAUNCH_CHECK();
+          reduce_ks(s, 2, 3);
+        }
         int nxt = 0;
         while (nxt == cur || nxt == best) ++nxt;
         k_bicg_xr<TW><<<g1, kBlock, 0, s->stream>>>(xb[nxt], xb[cur], p, sv, t, r, rhat, ks, M, s->part0);
         LAUNCH_CHECK();
         reduce_ks(s, 2, 4);
-        sync_scal(s);
+        // Copy the scalars, then queue the next iteration's direction apply
+        // before waiting for them, so that the device does not idle during
+        // the host's decision.  The apply only needs device scalars; when the
+        // run stops here its result is not used (a new run zeroes p and v,
+        // and x is untouched).
+        HC(hipMemcpyAsync(s->hscal, s->scal, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HC(hipEventRecord(s->ev_scal, s->stream));
+        if (s->fused != 0 && total < maxit) {
+          if (s->fused == 1) {
+            k_bicg_p<TW><<<g1, kBlock, 0, s->stream>>>(p, r, v, ks, M);
+            LAUNCH_CHECK();
+            apply_fused(s, 1, 0, p, nullptr, nullptr, nullptr, v, rhat);
+          } else {
+            apply_fused(s, 1, 1, p, r, v, p, v, rhat);
+          }
+          issued = true;
+        }
+        HC(hipEventSynchronize(s->ev_scal));
         s->kiters++;
         const double flag = s->hscal[SC_KS + KS_FLAG];
         if (flag == 1.0 || flag == 2.0) {   // breakdown before the update
@@ -608,6 +687,11 @@ struct Impl {
         }
         cur = nxt;
         const double res = std::sqrt(s->hscal[SC_KS + KS_RR]);
+        if (s->ktrace && total <= 6) {
+          const double* h = s->hscal + SC_KS;
+          std::fprintf(stderr, "[kry %d] it %d alpha %.17g omega %.17g rv %.17g ts %.17g tt %.17g rr %.17g\n",
+                       (int)sizeof(TW), total, h[KS_ALPHA], h[KS_OMEGA], h[KS_RV], h[KS_TS], h[KS_TT], h[KS_RR]);
+        }
         if (res < res_best) {
           best = cur;
           res_best = res;
@@ -894,7 +978,7 @@ void upload_tables(pff_solver* s, DevTables<T>& t) {
   }
 }
 
-hipEvent_t* timing_acquire(pff_solver* s) {
+hipEvent_t* timing_acquire(pff_solver* s, int group) {
   if (s->tim_pending.size() >= 512) timing_harvest(s);
   std::array<hipEvent_t, 6> ev;
   if (!s->tim_free.empty()) {
@@ -903,6 +987,7 @@ hipEvent_t* timing_acquire(pff_solver* s) {
   } else {
     for (auto& e : ev) HC(hipEventCreate(&e));
   }
+  s->tim_group.push_back(group);
   s->tim_pending.push_back(ev);
   return s->tim_pending.back().data();
 }
@@ -910,20 +995,23 @@ hipEvent_t* timing_acquire(pff_solver* s) {
 void timing_harvest(pff_solver* s) {
   if (s->tim_pending.empty()) return;
   HC(hipEventSynchronize(s->tim_pending.back()[5]));
-  for (auto& ev : s->tim_pending) {
+  for (size_t e = 0; e < s->tim_pending.size(); ++e) {
+    auto& ev = s->tim_pending[e];
+    const int base = 6 * s->tim_group[e];
     float ms[5];
     for (int k = 0; k < 5; ++k) HC(hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]));
     float all = 0.f;
     HC(hipEventElapsedTime(&all, ev[0], ev[5]));
     for (int k = 0; k < 5; ++k) {
-      s->tim_ms[k] += ms[k];
-      s->tim_n[k] += 1;
+      s->tim_ms[base + k] += ms[k];
+      s->tim_n[base + k] += 1;
     }
-    s->tim_ms[5] += all;
-    s->tim_n[5] += 1;
+    s->tim_ms[base + 5] += all;
+    s->tim_n[base + 5] += 1;
     s->tim_free.push_back(ev);
   }
   s->tim_pending.clear();
+  s->tim_group.clear();
 }
 
 void destroy_buffers(pff_solver* s) {
@@ -933,6 +1021,9 @@ void destroy_buffers(pff_solver* s) {
     for (auto e : ev) (void)hipEventDestroy(e);
   s->tim_pending.clear();
   s->tim_free.clear();
+  s->tim_group.clear();
+  if (s->ev_scal) (void)hipEventDestroy(s->ev_scal);
+  s->ev_scal = nullptr;
   for (void* p : s->allocs) (void)hipFree(p);
   s->allocs.clear();
   if (s->hscal) (void)hipHostFree(s->hscal);
@@ -1019,16 +1110,18 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     s->stream = static_cast<hipStream_t>(hip_stream);
     const char* tr = std::getenv("PFF_TRACE");
     s->trace = tr && tr[0] == '1';
+    s->ktrace = tr && tr[0] == '2';
     auto envi = [](const char* k, int d) {
       const char* v = std::getenv(k);
       return v ? std::atoi(v) : d;
     };
-    s->axis_threads = envi("PFF_AXIS_THREADS", 256);
+    s->axis_threads = envi("PFF_AXIS_THREADS", 0);
     s->spec_threads = envi("PFF_SPEC_THREADS", 512);
     s->axis_tx = envi("PFF_AXIS_TX", 16);
     s->spec_tx = envi("PFF_SPEC_TX", 8);
     s->x_rows = envi("PFF_X_ROWS", 64);
     s->xcd_remap = envi("PFF_XCD_REMAP", 1) != 0 ? 1 : 0;
+    s->fused = std::min(2, std::max(0, envi("PFF_FUSED", 1)));
     {
       const char* v = std::getenv("PFF_INNER32");
       s->inner32 = v ? std::atof(v) : kInner32;
@@ -1068,6 +1161,7 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     s->scal = s->alloc<double>(SC_COUNT);
     for (int k = 0; k < 4; ++k) s->cgv[k] = s->alloc<double>(N);
     HC(hipHostMalloc((void**)&s->hscal, SC_COUNT * sizeof(double), hipHostMallocDefault));
+    HC(hipEventCreateWithFlags(&s->ev_scal, hipEventDisableTiming));
     HC(hipHostMalloc((void**)&s->hstage, 8 * sizeof(double), hipHostMallocDefault));
     upload_tables<double>(s, s->td);
     upload_tables<float>(s, s->tf);
@@ -1391,7 +1485,7 @@ pff_status pff_timing(pff_solver* s, int every) {
 
 pff_status pff_timing_read(pff_solver* s, int kernel, long long* count, double* ms) {
   return guarded(s, [&]() -> pff_status {
-    if (kernel < 0 || kernel > 5) throw Fail("pff_timing_read: kernel id out of range", PFF_ERR_ARG);
+    if (kernel < 0 || kernel >= kTimSlots) throw Fail("pff_timing_read: kernel id out of range", PFF_ERR_ARG);
     HC(hipStreamSynchronize(s->stream));
     timing_harvest(s);
     if (count) *count = s->tim_n[kernel];

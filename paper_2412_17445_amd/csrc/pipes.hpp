@@ -19,6 +19,7 @@
 // otherwise, and r = phi/l - l Lap(phi) is the crack-length gradient.
 #pragma once
 
+#include "krylov.hpp"
 #include "passes.hpp"
 #include "pointlaw.hpp"
 
@@ -37,7 +38,16 @@ struct TangentPipe {
   static constexpr int D = DIM == 2 ? 2 : 3;
   static constexpr int NF = C + 1;
   static constexpr int NRED_PRO = 1;
-  static constexpr int NRED_EPI = 0;
+  static constexpr int NRED_EPI = 2;
+  // Fused BiCGSTAB steps (mode 0: plain J v).  The epilogue accumulates
+  // (dv, J u) (mode 1) or (J u, dv) and (J u, J u) (mode 2) over the voxel
+  // entries.  With pro != 0 the prologue also forms the input u:
+  //   mode 1: u = r + beta (v - omega w)   (direction update, written to vout = v)
+  //   mode 2: u = r - alpha w              (intermediate residual, written to vout)
+  // with the scalars of ks; the trailing (load factor) entry of u is computed
+  // by every thread from the old values and stored once in ks[KS_ULAST]
+  // (the finisher writes it to vout after the pass, when no block reads the
+  // old value any more).  Without pro, u = v.
   struct Args {
     GridDesc g;
     Material mat;
@@ -50,21 +60,45 @@ struct TangentPipe {
     T* Jv;
     T* aux;
     SpecTables<T> tab;
+    int mode;
+    int pro;
+    const T* r;
+    const T* w;
+    T* vout;
+    const T* dv;
+    double* ks;
   };
+
+  __device__ static T input(const Args& A, long long j) {
+    if (A.pro == 0) return A.v[j];
+    if (A.mode == 1) {
+      const T beta = T(A.ks[KS_BETA]), omega = T(A.ks[KS_OMEGA]);
+      return A.r[j] + beta * (A.v[j] - omega * A.w[j]);
+    }
+    const T alpha = T(A.ks[KS_ALPHA]);
+    return A.r[j] - alpha * A.w[j];
+  }
 
   __device__ static void prologue(const Args& A, long long i, T* out, double* red) {
     const long long N = A.g.N;
     const int p = A.pid[i];
     const bool m = A.mask[i] != 0;
     const T lam = T(A.mat.lam[p]), mu = T(A.mat.mu[p]), Gc = T(A.mat.Gc[p]);
-    const T dE = A.v[(long long)(C + 1) * N];
+    const long long last = (long long)(C + 1) * N;
+    const T dE = input(A, last);
+    if (A.pro != 0 && i == 0) A.ks[KS_ULAST] = double(dE);
     T w[C];
 #pragma unroll
-    for (int k = 0; k < C; ++k) w[k] = A.v[k * N + i] + A.f[k] * dE;
+    for (int k = 0; k < C; ++k) {
+      const T uk = input(A, k * N + i);
+      if (A.pro != 0) A.vout[k * N + i] = uk;
+      w[k] = uk + A.f[k] * dE;
+    }
     const T phi = A.ts[L::PHI * N + i];
     const T Hs = A.ts[L::HS * N + i];
     const T r = A.ts[L::R * N + i];
-    const T dphi = A.v[C * N + i];
+    const T dphi = input(A, C * N + i);
+    if (A.pro != 0) A.vout[C * N + i] = dphi;
     const T dphf = m ? T(0) : dphi;
     Split<T, D> sp;
     if constexpr (DIM == 2) {
@@ -108,13 +142,27 @@ struct TangentPipe {
     spectral_proj_lap<T, DIM, C, true>(A.tab, kx, ky, kz, v);
   }
 
-  __device__ static void epilogue(const Args& A, long long i, const T* in, double*) {
+  __device__ static void epilogue(const Args& A, long long i, const T* in, double* red) {
     const long long N = A.g.N;
 #pragma unroll
     for (int k = 0; k < C; ++k) A.Jv[k * N + i] = in[k];
     const bool m = A.mask[i] != 0;
     const T Gc = T(A.mat.Gc[A.pid[i]]);
-    A.Jv[C * N + i] = A.aux[i] - (m ? T(0) : Gc * A.l * in[C]);
+    const T j2 = A.aux[i] - (m ? T(0) : Gc * A.l * in[C]);
+    A.Jv[C * N + i] = j2;
+    if (A.mode == 1) {
+#pragma unroll
+      for (int k = 0; k < C; ++k) red[0] += double(A.dv[k * N + i]) * double(in[k]);
+      red[0] += double(A.dv[C * N + i]) * double(j2);
+    } else if (A.mode == 2) {
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
+        red[0] += double(in[k]) * double(A.dv[k * N + i]);
+        red[1] += double(in[k]) * double(in[k]);
+      }
+      red[0] += double(j2) * double(A.dv[C * N + i]);
+      red[1] += double(j2) * double(j2);
+    }
   }
 };
 

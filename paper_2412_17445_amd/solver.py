@@ -204,13 +204,14 @@ class Solver:
         self._check(self.lib.pff_timing(self.h, int(every)), "pff_timing")
 
     def timing_read(self):
-        """{kernel id: (timed launches, summed ms)} for ids 0..5 (see pff.h)."""
+        """{slot: (launches, ms)} for every slot with timed launches (see
+        pff_timing_read: slot = 6 * (5 * fp32 + variant) + kernel)."""
         out = {}
-        for k in range(6):
+        for k in range(60):
             n, ms = C.c_longlong(), C.c_double()
-            self._check(self.lib.pff_timing_read(self.h, k, C.byref(n), C.byref(ms)),
-                        "pff_timing_read")
-            out[k] = (n.value, ms.value)
+            self._check(self.lib.pff_timing_read(self.h, k, C.byref(n), C.byref(ms)), "pff_timing_read")
+            if n.value:
+                out[k] = (n.value, ms.value)
         return out
 
     def counters(self):
