@@ -9,9 +9,12 @@
 namespace pff {
 
 constexpr int kBlock = 256;          // threads per workgroup of vector kernels (4 wavefronts)
-// threads per workgroup of the FFT pass kernels: 8 LDS elements per thread
-// and 64 KB of LDS per block for either precision
-template <typename T> struct FftThreads { static constexpr int value = sizeof(T) == 4 ? 1024 : 512; };
+// threads per workgroup of the FFT pass kernels (at most 8 LDS elements per
+// thread).  512 for both precisions: FP32 x-pass tiles of 32 KB let three to
+// four blocks share a CU, so one block's loads overlap another's transform
+// (1024-thread, 64 KB blocks left the x-forward pass latency-bound in the
+// solve: 89 us against 55 us per launch at 128^3).
+template <typename T> struct FftThreads { static constexpr int value = 512; };
 constexpr int kMaxPhases = 16;
 constexpr int kMaxRed = 12;          // reduction slots per pass
 constexpr int kMaxStages = 10;

@@ -214,7 +214,7 @@ int grid1(long long M) {
 size_t g_lds_budget = kLdsBudget;
 
 int maxe_of(size_t) { return 8; }
-int fft_threads(size_t csz) { return csz == 8 ? 1024 : 512; }
+int fft_threads(size_t) { return 512; }
 
 int choose_rb(int nx, int np, size_t csz, int rows_max) {
   const size_t cap = size_t(maxe_of(csz)) * fft_threads(csz);
