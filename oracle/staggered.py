@@ -33,6 +33,8 @@ Readings:
   range of G (compatible strain fields).
 * The start state is the monolithic oracle's bootstrap damage phi0
   (the damage-free profile around the crack mask), eps~ = 0, E = 0, H = 0.
+* A relative error whose numerator is zero is zero, also over a zero norm
+  (the unloaded state E = 0, eps = 0 is then converged at once).
 """
 
 from __future__ import annotations
@@ -43,6 +45,13 @@ from . import fourier as fo
 from . import krylov
 from .newton import Solver as _Monolithic
 from .system import System
+
+
+def _rel(num, den):
+    """num / den, with 0 / x = 0 for any x (the error of an unchanged field)."""
+    if num == 0.0:
+        return 0.0
+    return num / den if den > 0.0 else np.inf
 
 
 class StaggeredSolver:
@@ -106,8 +115,8 @@ class StaggeredSolver:
             phi_new, k = self.helmholtz(H)
             cgh += k
             eps_full = eps_new + s.fE(E)
-            err = max(np.linalg.norm(eps_new - eps_t) / np.linalg.norm(eps_full),
-                      np.linalg.norm(phi_new - phi) / max(np.linalg.norm(phi_new), 1e-300))
+            err = max(_rel(np.linalg.norm(eps_new - eps_t), np.linalg.norm(eps_full)),
+                      _rel(np.linalg.norm(phi_new - phi), np.linalg.norm(phi_new)))
             eps_t, phi = eps_new, phi_new
             if err < self.tol_sta:
                 break

@@ -10,6 +10,9 @@
 * Unloading keeps the damage (history) and scales the stress down.
 """
 
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -55,6 +58,16 @@ def test_reaches_the_crack_length_controlled_root(case):
     assert np.abs(sm - so).max() <= 1e-7 * np.abs(so).max()
 
 
+def test_zero_load_is_the_bootstrap_state():
+    prob = problem_config("tiny16")
+    st = StaggeredSolver(prob, dE=0.0)
+    phi0 = st.phi.copy()
+    out = st.step()
+    assert out["stagger_iters"] == 1 and out["newton_iters"] == 1
+    assert np.abs(st.phi - phi0).max() <= 1e-9 and not st.eps_t.any()   # CG rtol 1e-11 vs 1e-14
+    assert np.abs(out["sigma_M"]).max() == 0.0
+
+
 def test_unloading_keeps_the_damage():
     prob = problem_config("gc16")
     st = StaggeredSolver(prob, dE=3e-3)
@@ -65,3 +78,19 @@ def test_unloading_keeps_the_damage():
     out = st.step()
     assert np.abs(st.phi - phi_peak).max() <= 1e-9
     assert out["E"] == pytest.approx(4e-3)
+
+
+def test_stored_increments_are_the_oracle_s():
+    """tests/golden/stagger_gc16.json (used by the GPU tests) is what the
+    committed oracle computes now."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "stagger_gc16.json")) as fh:
+        g = json.load(fh)
+    st = StaggeredSolver(problem_config("gc16"), dE=0.0, **g["params"])
+    idx = np.array(g["sample_index"])
+    for ref in g["increments"]:
+        st.dE = ref["dE"]
+        out = st.step()
+        assert out["Gamma"] == pytest.approx(ref["Gamma"], rel=1e-12)
+        assert out["stagger_iters"] == ref["stagger_iters"]
+        assert out["newton_iters"] == ref["newton_iters"]
+        assert np.abs(st.phi.ravel()[idx] - ref["phi_samples"]).max() <= 1e-12
