@@ -121,6 +121,53 @@ pff_status pff_bootstrap(pff_solver* s, double* a0, double* E_s);
  * is rolled back to the last converged increment. */
 pff_status pff_step(pff_solver* s, pff_increment_result* out);
 
+/* Strain-controlled implicit staggered scheme (Sec. 3.1, Algorithm 1): the
+ * baseline the crack-length control is compared with.  Tolerances:
+ * tol_mech on max|d eps~| / (|E| ||f||) of a mechanical Newton step
+ * (eq. errors_strain), tol_sta on the stagger error
+ * max(||eps~_s - eps~_{s-1}|| / ||f E + eps~_s||, ||phi_s - phi_{s-1}|| / ||phi_s||),
+ * cg_rtol on each conjugate-gradient solve (relative residual). */
+typedef struct {
+  double tol_mech;     /* default 1e-9 */
+  double tol_sta;      /* default 1e-8 */
+  double cg_rtol;      /* default 1e-11 */
+  int max_stagger;     /* default 500 */
+  int max_newton;      /* mechanical Newton steps per stagger iteration, default 50 */
+  int cg_maxit;        /* default 20000 */
+} pff_stagger_params;
+
+typedef struct {
+  int increment;
+  int converged;
+  int stagger_iters;
+  int newton_iters;        /* mechanical Newton steps over all stagger iterations */
+  long long cg_mech;       /* CG iterations of the mechanical solves */
+  long long cg_helm;       /* CG iterations of the Helmholtz solves */
+  double E;                /* prescribed load after the increment */
+  double crack_length;     /* Gamma(phi) */
+  double sigma_M[6];       /* Mandel */
+  double err;              /* last stagger error */
+  double seconds;
+} pff_stagger_result;
+
+/* Fill *p with the defaults above.  Errors: PFF_ERR_ARG (p NULL). */
+pff_status pff_stagger_defaults(pff_stagger_params* p);
+
+/* One strain-controlled increment: E <- E + dE, then stagger iterations of
+ * (i) the mechanical problem G[sigma(f E + eps~, phi)] = 0 at fixed phi,
+ * Newton with G[C_i : d eps~] = -G[sigma_i] (eq. LinearOpe_Mech) solved by
+ * FP64 conjugate gradients, and (ii) the Helmholtz problem (Gc/l + 2H) phi -
+ * Gc l Lap phi = 2H (eq. LinearOpe_Helm) with H = max(psi+(eps), Hn) of the
+ * new strain, phi = 1 on the crack mask, divided by Gc and solved by CG, until
+ * the stagger error is below tol_sta; then the history is committed.  Starts
+ * from the committed state (after pff_bootstrap: phi0, eps~ = 0, E = 0), and
+ * leaves a = Gamma(phi) so that crack-length increments may follow.  Runs in
+ * FP64 whatever the solver precision.  params may be NULL (defaults).  On
+ * PFF_NOT_CONVERGED the state is rolled back.  Errors: PFF_ERR_STATE before
+ * bootstrap, PFF_ERR_ARG for a non-positive tolerance or count. */
+pff_status pff_stagger_step(pff_solver* s, double dE, const pff_stagger_params* params,
+                            pff_stagger_result* out);
+
 /* Copy the committed state to host buffers (any may be NULL):
  * eps_total C*N, phi N, Hn N (history), and scalars E, a. */
 pff_status pff_get_state(pff_solver* s, double* eps_total, double* phi, double* Hn,

@@ -40,6 +40,18 @@ class pff_increment_result(C.Structure):
                 ("target_a", C.c_double), ("err", C.c_double * 3), ("seconds", C.c_double)]
 
 
+class pff_stagger_params(C.Structure):
+    _fields_ = [("tol_mech", C.c_double), ("tol_sta", C.c_double), ("cg_rtol", C.c_double),
+                ("max_stagger", C.c_int), ("max_newton", C.c_int), ("cg_maxit", C.c_int)]
+
+
+class pff_stagger_result(C.Structure):
+    _fields_ = [("increment", C.c_int), ("converged", C.c_int), ("stagger_iters", C.c_int),
+                ("newton_iters", C.c_int), ("cg_mech", C.c_longlong), ("cg_helm", C.c_longlong),
+                ("E", C.c_double), ("crack_length", C.c_double), ("sigma_M", C.c_double * 6),
+                ("err", C.c_double), ("seconds", C.c_double)]
+
+
 class pff_request_info(C.Structure):
     _fields_ = [("ticket", C.c_uint64), ("state", C.c_int), ("status", C.c_int),
                 ("n_done", C.c_int), ("slot", C.c_int), ("footprint", C.c_size_t),
@@ -61,6 +73,9 @@ EXPORTS = {
                              C.c_void_p, C.POINTER(pff_params), C.c_void_p, C.POINTER(C.c_void_p)]),
     "pff_bootstrap": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pff_step": (C.c_int, [C.c_void_p, C.POINTER(pff_increment_result)]),
+    "pff_stagger_defaults": (C.c_int, [C.POINTER(pff_stagger_params)]),
+    "pff_stagger_step": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(pff_stagger_params),
+                                   C.POINTER(pff_stagger_result)]),
     "pff_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pff_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,

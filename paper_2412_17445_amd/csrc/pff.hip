@@ -59,7 +59,7 @@ enum {
   SC_GAMMA = 6, SC_F1 = 7, SC_F2 = 8,
   SC_NW = 9, SC_NEPS = 10, SC_NDPHI = 11, SC_NPHI = 12,
   SC_ETA = 13,     // 2 slots: ||b - J x||^2, ||b||^2 of the FP64 check
-  SC_CG = 16,      // CG scratch
+  SC_CG = 16,      // CG scratch; staggered scheme: [17] max |d eps~|, [18..21] stagger norms
   SC_KS = 32,      // Krylov scalars
   SC_COUNT = 64
 };
@@ -335,6 +335,12 @@ __global__ void k_lincomb(double* __restrict__ out, double a, const double* __re
     out[i] = a * x[i] + (y ? b * y[i] : 0.0);
 }
 
+__global__ void k_axpy(double* x, double a, const double* __restrict__ y, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    x[i] += a * y[i];
+}
+
 __global__ void k_mask_to_double(double* __restrict__ out, const uint8_t* __restrict__ m, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
@@ -347,6 +353,74 @@ __global__ void k_phi0(double* __restrict__ phi, const double* __restrict__ u,
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     phi[i] = m[i] ? 1.0 : u[i];
+}
+
+// right-hand side of the Helmholtz solve: b = (1-m) (2|H|/Gc - B m), where b
+// holds (1-m) B m on entry
+__global__ void k_helm_rhs(double* __restrict__ b, const double* __restrict__ H,
+                           const uint8_t* __restrict__ m, const uint8_t* __restrict__ pid, Material mat,
+                           long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    b[i] = m[i] ? 0.0 : (H ? 2.0 * fabs(H[i]) / mat.Gc[pid[i]] : 0.0) - b[i];
+}
+
+// per-block partials: max |x_i| over the first n entries
+__global__ void __launch_bounds__(kBlock) k_absmax(const double* __restrict__ x, long long n,
+                                                   double* __restrict__ partials) {
+  __shared__ double lds[kBlock];
+  double mx = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    mx = fmax(mx, fabs(x[i]));
+  lds[threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) lds[threadIdx.x] = fmax(lds[threadIdx.x], lds[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = lds[0];
+}
+
+__global__ void __launch_bounds__(kBlock) k_max_final(const double* __restrict__ partials, int nb,
+                                                      double* __restrict__ out) {
+  __shared__ double lds[kBlock];
+  double mx = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) mx = fmax(mx, partials[b]);
+  lds[threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) lds[threadIdx.x] = fmax(lds[threadIdx.x], lds[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = lds[0];
+}
+
+// stagger error partials: ||eps~ - eps~prev||^2, ||f E + eps~||^2,
+// ||phi - phi_prev||^2, ||phi||^2
+template <int C>
+__global__ void __launch_bounds__(kBlock) k_stagger_norms(const double* __restrict__ eps, const double* __restrict__ eps_prev,
+                                                          const double* __restrict__ phi,
+                                                          const double* __restrict__ phi_prev, Vec16 fm,
+                                                          const double* __restrict__ Edev, long long N,
+                                                          double* __restrict__ partials) {
+  const double E = Edev[0];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      const double e = eps[k * N + i];
+      const double d = e - eps_prev[k * N + i];
+      const double t = e + fm.v[k] * E;
+      acc[0] += d * d;
+      acc[1] += t * t;
+    }
+    const double p = phi[i], dp = p - phi_prev[i];
+    acc[2] += dp * dp;
+    acc[3] += p * p;
+  }
+  write_partials<4>(acc, partials);
 }
 
 // predictor guess: phi = max(phi0, (1-m) phi_loc(phase))
@@ -497,6 +571,7 @@ struct Impl {
     A.Jv = Jv;
     A.mode = mode;
     A.pro = pro;
+    A.mech = 0;
     A.r = r;
     A.w = w;
     A.vout = vout;
@@ -514,13 +589,14 @@ struct Impl {
     if (std::is_same<TW, double>::value) s->applies64++;
   }
 
-  static void apply(pff_solver* s, const TW* v, TW* Jv) {
+  static void apply(pff_solver* s, const TW* v, TW* Jv, int mech = 0) {
     typename TangentPipe<TW, DIM>::Args A;
     fill_tangent_args(s, A);
     A.v = v;
     A.Jv = Jv;
     A.mode = 0;
     A.pro = 0;
+    A.mech = mech;
     A.r = A.w = A.dv = nullptr;
     A.vout = nullptr;
     A.ks = nullptr;
@@ -746,7 +822,8 @@ struct Impl {
     run_pipeline<CompatPipe<DIM>>(s, A, nblk);
   }
 
-  static void helm_apply(pff_solver* s, const double* u, double* out, int mask_input) {
+  static void helm_apply(pff_solver* s, const double* u, double* out, int mask_input,
+                         const double* H = nullptr) {
     HelmPipe::Args A;
     A.g = s->g;
     A.l = s->prm.l;
@@ -755,6 +832,9 @@ struct Impl {
     A.mask_input = mask_input;
     A.mask = s->mask;
     A.tab = spec_tables<double>(s);
+    A.H = H;
+    A.pid = s->pid;
+    A.mat = s->mat;
     int nblk = 0;
     run_pipeline<HelmPipe>(s, A, nblk);
   }
@@ -768,6 +848,160 @@ struct Impl {
     LAUNCH_CHECK();
     sync_scal(s);
     return s->hscal[SC_CG];
+  }
+
+  // Conjugate gradients on an SPD operator (FP64): x = op^-1 b, x0 = 0,
+  // stop at ||r|| <= rtol ||b||; work vectors w[0..2] (r, p, Ap) of length n.
+  template <typename Op>
+  static int cg(pff_solver* s, Op&& op, const double* b, double* x, double* const* w, long long n,
+                double rtol, int maxit, double* relres) {
+    const int g = grid1(n);
+    double *r = w[0], *p = w[1], *Ap = w[2];
+    k_fill<double><<<g, kBlock, 0, s->stream>>>(x, 0.0, n);
+    k_copy<double><<<g, kBlock, 0, s->stream>>>(r, b, n);
+    k_copy<double><<<g, kBlock, 0, s->stream>>>(p, b, n);
+    LAUNCH_CHECK();
+    double rr = dot(s, r, r, n);
+    const double bnorm = std::sqrt(rr);
+    int it = 0;
+    if (relres) *relres = 0.0;
+    while (bnorm > 0.0 && it < maxit) {
+      ++it;
+      op(p, Ap);
+      const double pAp = dot(s, p, Ap, n);
+      if (!(pAp > 0.0)) break;
+      const double al = rr / pAp;
+      k_lincomb<<<g, kBlock, 0, s->stream>>>(x, 1.0, x, al, p, n);
+      k_lincomb<<<g, kBlock, 0, s->stream>>>(r, 1.0, r, -al, Ap, n);
+      LAUNCH_CHECK();
+      const double rr_new = dot(s, r, r, n);
+      if (relres) *relres = std::sqrt(rr_new) / bnorm;
+      if (std::sqrt(rr_new) <= rtol * bnorm) break;
+      k_lincomb<<<g, kBlock, 0, s->stream>>>(p, 1.0, r, rr_new / rr, p, n);
+      LAUNCH_CHECK();
+      rr = rr_new;
+    }
+    return it;
+  }
+
+  // Damage field of the Helmholtz problem with history H (signed, as written
+  // by the residual pass): (1/l + 2H/Gc) phi - l Lap phi = 2H/Gc off the crack
+  // mask, phi = 1 on it (paper eq. LinearOpe_Helm divided by Gc).  phi =
+  // m + (1-m) u, CG on u.
+  static int helm_solve(pff_solver* s, const double* H, double* phi, double rtol, int maxit) {
+    const long long N = s->N;
+    const int g = grid1(N);
+    double* b = s->cgv[0];
+    double* u = s->cgv[1];
+    double* w[3] = {s->cgv[2], s->cgv[3], vec(s, X0)};
+    k_mask_to_double<<<g, kBlock, 0, s->stream>>>(s->dmask, s->mask, N);
+    LAUNCH_CHECK();
+    helm_apply(s, s->dmask, b, 0, H);                    // (1-m) B m = -(1-m) l Lap m
+    k_helm_rhs<<<g, kBlock, 0, s->stream>>>(b, H, s->mask, s->pid, s->mat, N);
+    LAUNCH_CHECK();
+    const int it = cg(s, [&](const double* x, double* y) { helm_apply(s, x, y, 1, H); }, b, u, w, N, rtol,
+                      maxit, nullptr);
+    k_phi0<<<g, kBlock, 0, s->stream>>>(phi, u, s->mask, N);
+    LAUNCH_CHECK();
+    return it;
+  }
+
+  // max |x_i| over n entries (device slot SC_CG + 1, host copy after sync)
+  static double absmax(pff_solver* s, const double* x, long long n) {
+    const int nb = red_blocks(n);
+    k_absmax<<<nb, kBlock, 0, s->stream>>>(x, n, s->part0);
+    k_max_final<<<1, kBlock, 0, s->stream>>>(s->part0, nb, s->scal + SC_CG + 1);
+    LAUNCH_CHECK();
+    sync_scal(s);
+    return s->hscal[SC_CG + 1];
+  }
+
+  // Mechanical sub-problem of the staggered scheme at fixed phi and E (device
+  // Edev[0]): Newton on G[sigma(f E + eps~, phi)] = 0, each step solving
+  // G[C_i : d] = -G[sigma_i] by CG with the FP64 tangent restricted to the
+  // strain rows; stops when max|d| / (|E| ||f||) < tol.  Returns the Newton
+  // count (0: no convergence); CG iterations are added to *cg_total.
+  static int mechanical(pff_solver* s, const pff_stagger_params& sp, double nf, long long* cg_total) {
+    const long long N = s->N, M = s->M;
+    double* rhs = vec(s, RHS);
+    double* d = vec(s, SOL);
+    double* w[3] = {vec(s, R), vec(s, P), vec(s, V)};
+    for (int it = 1; it <= sp.max_newton; ++it) {
+      residual(s, 0.0, nullptr);
+      k_fill<double><<<grid1(N + 1), kBlock, 0, s->stream>>>(rhs + (long long)C * N, 0.0, N + 1);
+      LAUNCH_CHECK();
+      const int k = cg(s, [&](const double* x, double* y) { apply(s, x, y, 1); }, rhs, d, w, M, sp.cg_rtol,
+                       sp.cg_maxit, nullptr);
+      *cg_total += k;
+      s->kiters += k;
+      project_strain(s, d);
+      k_axpy<<<grid1((long long)C * N), kBlock, 0, s->stream>>>(s->eps_t, 1.0, d, (long long)C * N);
+      LAUNCH_CHECK();
+      s->ts_valid = false;
+      if (nf == 0.0) return it;
+      const double dm = absmax(s, d, (long long)C * N);
+      if (!std::isfinite(dm)) return 0;
+      if (dm / nf < sp.tol_mech) return it;
+    }
+    return 0;
+  }
+
+  // One strain-controlled increment (Algorithm 1) from the committed state at
+  // load E (device Edev[0]): stagger iterations of the mechanical and the
+  // Helmholtz sub-problem until both fields settle.  Leaves the final state in
+  // eps_t / phi and its residual pass (sigma, Gamma, history) in the scalars.
+  static int stagger(pff_solver* s, const pff_stagger_params& sp, double E, pff_stagger_result* out) {
+    const long long N = s->N;
+    double* eps_prev = vec(s, X1);
+    double* phi_prev = vec(s, X2);
+    double fn = 0.0;
+    for (int k = 0; k < C; ++k) fn += s->fm[k] * s->fm[k];
+    const double nf = std::sqrt(fn) * std::fabs(E);
+    Vec16 fm{};
+    for (int k = 0; k < 6; ++k) fm.v[k] = s->fm[k];
+    long long cgm = 0, cgh = 0;
+    int newton = 0, st = 0, conv = 0;
+    double err = 0.0;
+    for (st = 1; st <= sp.max_stagger; ++st) {
+      HC(hipMemcpyAsync(eps_prev, s->eps_t, C * N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+      HC(hipMemcpyAsync(phi_prev, s->phi, N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+      const int it = mechanical(s, sp, nf, &cgm);
+      if (it == 0) break;
+      newton += it;
+      residual(s, 0.0, nullptr);                 // history H = max(psi+(eps), Hn) of the new strain
+      cgh += helm_solve(s, s->Hcur, s->phi, sp.cg_rtol, sp.cg_maxit);
+      const int nb = red_blocks(N);
+      k_stagger_norms<C><<<nb, kBlock, 0, s->stream>>>(s->eps_t, eps_prev, s->phi, phi_prev, fm, s->Edev, N,
+                                                      s->part0);
+      FinStore::Args fs{s->scal + SC_CG + 2, 4};
+      k_reduce<FinStore><<<1, kBlock, 0, s->stream>>>(s->part0, nb, 4, fs);
+      LAUNCH_CHECK();
+      sync_scal(s);
+      const double* h = s->hscal + SC_CG + 2;
+      // a relative change of zero is zero, also over a zero norm (E = 0)
+      auto rel = [](double num, double den) {
+        return num == 0.0 ? 0.0 : (den > 0.0 ? num / den : HUGE_VAL);
+      };
+      err = std::max(rel(std::sqrt(h[0]), std::sqrt(h[1])), rel(std::sqrt(h[2]), std::sqrt(h[3])));
+      if (s->trace)
+        std::fprintf(stderr, "[pff] stagger %d newton %d err %.3e\n", st, it, err);
+      if (std::isnan(err)) break;
+      if (err < sp.tol_sta) {
+        conv = 1;
+        break;
+      }
+    }
+    if (st > sp.max_stagger) st = sp.max_stagger;
+    if (conv) residual(s, 0.0, nullptr);         // sigma and Gamma at the final fields
+    if (out) {
+      out->stagger_iters = st;
+      out->newton_iters = newton;
+      out->cg_mech = cgm;
+      out->cg_helm = cgh;
+      out->err = err;
+      out->converged = conv;
+    }
+    return conv;
   }
 
   // phi0: masked damage-free Helmholtz problem by CG (rtol 1e-14)
@@ -1200,6 +1434,7 @@ pff_status pff_bootstrap(pff_solver* s, double* a0, double* E_s) {
       I::initial_damage(s, s->phi);
       // a0 = Gamma(phi0): a residual pass at eps = 0, E = 0, H = 0
       HC(hipMemsetAsync(s->eps_t, 0, s->C * s->N * sizeof(double), s->stream));
+      HC(hipMemsetAsync(s->eps_c, 0, s->C * s->N * sizeof(double), s->stream));
       HC(hipMemsetAsync(s->Hn, 0, s->N * sizeof(double), s->stream));
       HC(hipMemsetAsync(s->Edev, 0, 4 * sizeof(double), s->stream));
       I::residual(s, 0.0, nullptr);
@@ -1354,6 +1589,72 @@ pff_status pff_step(pff_solver* s, pff_increment_result* out) {
     if (out) {
       for (int q = 0; q < 6; ++q) out->sigma_M[q] = s->hscal[SC_SIG + q] / double(N);
       out->load_factor = Ecur;
+      out->crack_length = s->hscal[SC_GAMMA];
+      out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return PFF_OK;
+  });
+}
+
+pff_status pff_stagger_defaults(pff_stagger_params* p) {
+  if (!p) return PFF_ERR_ARG;
+  p->tol_mech = 1e-9;
+  p->tol_sta = 1e-8;
+  p->cg_rtol = 1e-11;
+  p->max_stagger = 500;
+  p->max_newton = 50;
+  p->cg_maxit = 20000;
+  return PFF_OK;
+}
+
+pff_status pff_stagger_step(pff_solver* s, double dE, const pff_stagger_params* params, pff_stagger_result* out) {
+  return guarded(s, [&]() -> pff_status {
+    if (!s->bootstrapped) throw Fail("pff_stagger_step before pff_bootstrap/pff_set_state", PFF_ERR_STATE);
+    pff_stagger_params sp;
+    pff_stagger_defaults(&sp);
+    if (params) sp = *params;
+    if (!(sp.tol_mech > 0.0) || !(sp.tol_sta > 0.0) || !(sp.cg_rtol > 0.0) || sp.max_stagger < 1 ||
+        sp.max_newton < 1 || sp.cg_maxit < 1 || !std::isfinite(dE))
+      throw Fail("pff_stagger_step: invalid parameters", PFF_ERR_ARG);
+    const auto t0 = std::chrono::steady_clock::now();
+    const long long N = s->N;
+    const int C = s->C;
+    const double E = s->E + dE;
+    HC(hipMemcpyAsync(s->eps_t, s->eps_c, C * N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    HC(hipMemcpyAsync(s->phi, s->phi_c, N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    HC(hipStreamSynchronize(s->stream));
+    s->hstage[0] = E;
+    HC(hipMemcpyAsync(s->Edev, s->hstage, sizeof(double), hipMemcpyHostToDevice, s->stream));
+    if (out) std::memset(out, 0, sizeof(*out));
+    int conv = 0;
+    dispatch_dim(s, [&](auto dimc) {
+      constexpr int DIM = decltype(dimc)::value;
+      conv = Impl<DIM, double>::stagger(s, sp, E, out);
+    });
+    if (out) {
+      out->increment = s->n + 1;
+      out->E = E;
+    }
+    if (!conv) {
+      HC(hipMemcpyAsync(s->eps_t, s->eps_c, C * N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+      HC(hipMemcpyAsync(s->phi, s->phi_c, N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+      HC(hipStreamSynchronize(s->stream));
+      s->ts_valid = false;
+      if (out) out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      return PFF_NOT_CONVERGED;
+    }
+    const int g = grid1(N);
+    k_commit_history<<<g, kBlock, 0, s->stream>>>(s->Hn, s->Hcur, N);
+    LAUNCH_CHECK();
+    HC(hipMemcpyAsync(s->eps_c, s->eps_t, C * N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    HC(hipMemcpyAsync(s->phi_c, s->phi, N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    HC(hipStreamSynchronize(s->stream));
+    s->E = E;
+    s->a = s->hscal[SC_GAMMA];
+    s->n += 1;
+    s->ts_valid = false;
+    if (out) {
+      for (int q = 0; q < 6; ++q) out->sigma_M[q] = s->hscal[SC_SIG + q] / double(N);
       out->crack_length = s->hscal[SC_GAMMA];
       out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }

@@ -62,6 +62,7 @@ struct TangentPipe {
     SpecTables<T> tab;
     int mode;
     int pro;
+    int mech;        // 1: the damage rows of J are zero (mechanical operator G[C:d eps~])
     const T* r;
     const T* w;
     T* vout;
@@ -148,7 +149,7 @@ struct TangentPipe {
     for (int k = 0; k < C; ++k) A.Jv[k * N + i] = in[k];
     const bool m = A.mask[i] != 0;
     const T Gc = T(A.mat.Gc[A.pid[i]]);
-    const T j2 = A.aux[i] - (m ? T(0) : Gc * A.l * in[C]);
+    const T j2 = A.mech ? T(0) : A.aux[i] - (m ? T(0) : Gc * A.l * in[C]);
     A.Jv[C * N + i] = j2;
     if (A.mode == 1) {
 #pragma unroll
@@ -298,6 +299,9 @@ struct ResidualPipe {
   }
 };
 
+// (1-m) B u with B u = (1/l + 2H/Gc) u - l Lap u: the damage equation
+// divided by Gc (symmetric positive definite); H = 0 (null H) for the
+// damage-free bootstrap.  H holds the signed history of the residual pass.
 struct HelmPipe {
   using real = double;
   static constexpr int NF = 1;
@@ -311,6 +315,9 @@ struct HelmPipe {
     int mask_input;          // 1: operator (1-m) B (1-m); 0: (1-m) B
     const uint8_t* mask;
     SpecTables<double> tab;
+    const double* H;         // history (|H| used), or null
+    const uint8_t* pid;
+    Material mat;
   };
   __device__ static void prologue(const Args& A, long long i, double* out, double*) {
     const bool m = A.mask[i] != 0;
@@ -323,7 +330,8 @@ struct HelmPipe {
   __device__ static void epilogue(const Args& A, long long i, const double* in, double*) {
     const bool m = A.mask[i] != 0;
     const double u = (A.mask_input && m) ? 0.0 : A.u[i];
-    A.out[i] = m ? 0.0 : u / A.l - A.l * in[0];
+    const double a = 1.0 / A.l + (A.H ? 2.0 * fabs(A.H[i]) / A.mat.Gc[A.pid[i]] : 0.0);
+    A.out[i] = m ? 0.0 : a * u - A.l * in[0];
   }
 };
 

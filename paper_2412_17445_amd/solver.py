@@ -137,6 +137,24 @@ class Solver:
         out["status"] = st
         return out
 
+    def stagger_step(self, dE, **params):
+        """One strain-controlled increment of the staggered scheme (load E += dE).
+        Keyword overrides of the defaults: tol_mech, tol_sta, cg_rtol,
+        max_stagger, max_newton, cg_maxit."""
+        p = L.pff_stagger_params()
+        self._check(self.lib.pff_stagger_defaults(C.byref(p)), "pff_stagger_defaults")
+        for k, v in params.items():
+            if not hasattr(p, k):
+                raise TypeError(f"unknown staggered-scheme parameter {k}")
+            setattr(p, k, v)
+        r = L.pff_stagger_result()
+        st = self._check(self.lib.pff_stagger_step(self.h, float(dE), C.byref(p), C.byref(r)),
+                         "pff_stagger_step")
+        return dict(increment=r.increment, converged=bool(r.converged), stagger_iters=r.stagger_iters,
+                    newton_iters=r.newton_iters, cg_mech=r.cg_mech, cg_helm=r.cg_helm, E=r.E,
+                    Gamma=r.crack_length, sigma_M=list(r.sigma_M), err=r.err, seconds=r.seconds,
+                    status=st)
+
     def device_bytes(self):
         b = C.c_size_t()
         self._check(self.lib.pff_solver_bytes(self.h, C.byref(b)), "pff_solver_bytes")

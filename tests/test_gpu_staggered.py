@@ -1,0 +1,156 @@
+"""GPU parity of the strain-controlled staggered scheme (paper Algorithm 1)
+through the C ABI (pff_stagger_step).
+
+* Homogeneous cell: every increment matches the closed form (uniform strain
+  f E, phi = 2H / (Gc/l + 2H), H = (lambda/2 + mu) E^2).
+* Seeded cases against the staggered oracle's stored increments
+  (tests/golden/stagger_<case>.json, written by make_stagger_runs.py from
+  oracle/ only): load, crack length, mean stress, sampled damage, and the
+  stagger / Newton counts.
+* At the load factor of a crack-length-controlled increment both schemes
+  reach the same root, and crack-length increments continue from the
+  staggered state.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+# FP64 bar.  The two implementations run the same iterations; both stop on a
+# stagger error below 1e-8, so where round-off moves a stopping decision the
+# fields differ by the last correction, bounded by that tolerance.
+TOL = 1e-9
+
+
+def _solver(prob, precision="fp64"):
+    from paper_2412_17445_amd import Solver
+    s = Solver.from_problem(prob, precision=precision)
+    s.bootstrap()
+    return s
+
+
+def _gold(case):
+    with open(os.path.join(GOLD, f"stagger_{case}.json")) as fh:
+        return json.load(fh)
+
+
+@pytest.mark.gpu
+def test_homogeneous_uniaxial_closed_form():
+    from synth.configs import Problem, _dyad
+    n = 8
+    Ey, nu, Gc, l, k = 1.0, 0.3, 1e-3, 2.0, 1e-6
+    prob = Problem(name="hom", shape=(1, n, n), phases=[(Ey, nu, Gc)],
+                   phase_id=np.zeros((1, n, n), np.uint8), mask=None, f=_dyad(1, 1), l=l, k=k)
+    lam = Ey * nu / ((1 + nu) * (1 - 2 * nu))
+    mu = Ey / (2 * (1 + nu))
+    s = _solver(prob)
+    for i in range(4):
+        out = s.stagger_step(0.02)
+        assert out["converged"] and out["status"] == 0
+        E = out["E"]
+        assert E == pytest.approx(0.02 * (i + 1), rel=1e-15)
+        H = (0.5 * lam + mu) * E * E
+        phi = 2 * H / (Gc / l + 2 * H)
+        g = (1 - phi) ** 2 + k
+        _, ph, Hn, Es, _ = s.get_state()
+        assert np.abs(ph - phi).max() <= 1e-9 * phi
+        assert np.abs(Hn - H).max() <= 1e-12 * H
+        sig = out["sigma_M"]
+        ref = [g * lam * E, g * (lam + 2 * mu) * E, g * lam * E]
+        for q in range(3):
+            assert abs(sig[q] - ref[q]) <= 1e-9 * abs(ref[q]), (q, sig[q], ref[q])
+        assert max(abs(v) for v in sig[3:]) <= 1e-12
+    s.close()
+
+
+def _check_increment(out, ref, tol):
+    assert out["converged"], out
+    assert out["E"] == pytest.approx(ref["E"], rel=1e-14)
+    assert abs(out["Gamma"] - ref["Gamma"]) <= tol * abs(ref["Gamma"]), (out["Gamma"], ref["Gamma"])
+    sig, sref = np.array(out["sigma_M"]), np.array(ref["sigma_M"])
+    assert np.abs(sig - sref).max() <= tol * np.abs(sref).max(), (sig, sref)
+    assert out["newton_iters"] == ref["newton_iters"], (out, ref)
+    assert out["stagger_iters"] == ref["stagger_iters"], (out, ref)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case,precision", [("tiny16", "fp64"), ("gc16", "fp64"), ("gc16", "mixed"),
+                                            ("crack2d_64", "fp64"), ("pore24", "fp64")])
+def test_matches_the_staggered_oracle(case, precision):
+    from synth import problem_config
+    g = _gold(case)
+    s = _solver(problem_config(case), precision)
+    idx = np.array(g["sample_index"])
+    for ref in g["increments"]:
+        out = s.stagger_step(ref["dE"], **g["params"])
+        print(case, precision, {k: v for k, v in out.items() if k != "sigma_M"}, flush=True)
+        _check_increment(out, ref, TOL)
+        _, phi, _, E, a = s.get_state()
+        assert E == pytest.approx(ref["E"], rel=1e-14)
+        assert a == pytest.approx(out["Gamma"], rel=1e-15)
+        assert np.abs(phi.ravel()[idx] - np.array(ref["phi_samples"])).max() <= TOL
+        assert abs(np.linalg.norm(phi) - ref["phi_norm"]) <= TOL * ref["phi_norm"]
+    s.close()
+
+
+@pytest.mark.gpu
+def test_unloading_keeps_the_damage():
+    from synth import problem_config
+    s = _solver(problem_config("gc16"))
+    s.stagger_step(3e-3)
+    s.stagger_step(3e-3)
+    _, phi_peak, H_peak, _, _ = s.get_state()
+    out = s.stagger_step(-2e-3)
+    assert out["converged"] and out["E"] == pytest.approx(4e-3)
+    _, phi, H, _, _ = s.get_state()
+    assert np.abs(phi - phi_peak).max() <= 1e-9
+    assert (H >= H_peak).all() and np.abs(H - H_peak).max() <= 1e-12 * H_peak.max()
+    s.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", ["tiny16", "gc16"])
+def test_shares_the_root_of_crack_length_control_and_hands_over(case):
+    """Staggered increment at E1 = monolithic increment 1; pff_step then
+    continues from it to monolithic increment 2."""
+    from synth import problem_config
+    with open(os.path.join(GOLD, f"oracle_{case}.json")) as fh:
+        mono = json.load(fh)
+    r1, r2 = mono["increments"][0], mono["increments"][1]
+    s = _solver(problem_config(case))
+    out = s.stagger_step(r1["E"])
+    # the staggered stopping rule (1e-8) bounds the distance to the root
+    assert abs(out["Gamma"] - r1["Gamma"]) <= 1e-8 * r1["Gamma"]
+    sig, sref = np.array(out["sigma_M"]), np.array(r1["sigma_M"])
+    assert np.abs(sig - sref).max() <= 1e-7 * np.abs(sref).max()
+    nxt = s.step()
+    assert nxt["converged"]
+    assert abs(nxt["a"] - out["Gamma"] - (r2["a"] - r1["a"])) <= 1e-12 * r2["a"]
+    assert abs(nxt["E"] - r2["E"]) <= 1e-6 * r2["E"]
+    assert abs(nxt["Gamma"] - r2["Gamma"]) <= 1e-7 * r2["Gamma"]
+    s.close()
+
+
+@pytest.mark.gpu
+def test_argument_and_state_errors():
+    from paper_2412_17445_amd import PffError, Solver
+    from synth import problem_config
+    prob = problem_config("tiny16")
+    s = Solver.from_problem(prob)
+    with pytest.raises(PffError):
+        s.stagger_step(1e-3)                  # before bootstrap
+    s.bootstrap()
+    with pytest.raises(PffError):
+        s.stagger_step(1e-3, tol_sta=0.0)
+    with pytest.raises(PffError):
+        s.stagger_step(float("nan"))
+    with pytest.raises(TypeError):
+        s.stagger_step(1e-3, tolerance=1.0)
+    out = s.stagger_step(0.0)                 # zero load: the bootstrap state is the solution
+    assert out["converged"] and out["E"] == 0.0
+    assert out["stagger_iters"] == 1 and max(abs(v) for v in out["sigma_M"]) == 0.0
+    s.close()
