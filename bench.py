@@ -169,7 +169,35 @@ def compare_fp64(prob, args, mixed_outs, mixed_s_per_step):
     return {"increments": len(mixed_outs), "fp64_ms_per_step": round(fp64_s * 1e3, 2),
             "mixed_ms_per_step": round(mixed_s_per_step * 1e3, 2),
             "fp64_time_over_mixed_time": round(fp64_s / mixed_s_per_step, 3),
+            "fp64_first_increment_s": round(t[0], 3),
             "max_rel_diff": {k: float("%.3e" % v) for k, v in d.items()}}
+
+
+def staggered_leg(prob, first):
+    """The strain-controlled staggered scheme (Algorithm 1, FP64) from the
+    bootstrap state to the load factor E1 of the first crack-length increment
+    `first`: both schemes reach the same root there, so time and tangent
+    applies compare the two controls on equal work."""
+    import numpy as np
+
+    from paper_2412_17445_amd import Solver
+
+    s = Solver.from_problem(prob, precision="fp64")
+    s.bootstrap()
+    a0, _ = s.counters()
+    o = s.stagger_step(first["E"])
+    a1, _ = s.counters()
+    s.close()
+    log(f"staggered increment to E1: converged={o['converged']} stagger={o['stagger_iters']} "
+        f"newton={o['newton_iters']} cg={o['cg_mech']}+{o['cg_helm']} {o['seconds']:.2f}s")
+    sm, so = np.array(o["sigma_M"]), np.array(first["sigma_M"])
+    return {"E": first["E"], "converged": o["converged"], "seconds": round(o["seconds"], 3),
+            "stagger_iters": o["stagger_iters"], "newton_iters": o["newton_iters"],
+            "cg_mech": o["cg_mech"], "cg_helm": o["cg_helm"], "tangent_applies": a1 - a0,
+            "crack_control_applies": first["applies"],
+            "crack_control_seconds": round(first["seconds"], 3),
+            "rel_diff_Gamma": float("%.3e" % (abs(o["Gamma"] - first["Gamma"]) / abs(first["Gamma"]))),
+            "rel_diff_sigma_M": float("%.3e" % (np.abs(sm - so).max() / np.abs(so).max()))}
 
 
 def serve_stream(args):
@@ -267,6 +295,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="mixed workloads: skip the plain-FP64 solve of the same increments")
     ap.add_argument("--no-serve", action="store_true", help="skip the served request stream")
+    ap.add_argument("--no-stagger", action="store_true",
+                    help="skip the staggered strain-controlled increment")
     ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrivals per second")
     ap.add_argument("--serve-inc-scale", type=float, default=0.1,
@@ -400,6 +430,12 @@ def main():
     if prob.precision == "mixed" and not args.no_compare:
         s.close()
         line["mixed_vs_fp64"] = compare_fp64(prob, args, warm + outs, elapsed / args.steps)
+    if not args.no_stagger:
+        first = (warm + outs)[0]
+        line["staggered_vs_crack_control"] = staggered_leg(prob, first)
+        if "mixed_vs_fp64" in line:
+            line["staggered_vs_crack_control"]["crack_control_fp64_seconds"] = \
+                line["mixed_vs_fp64"]["fp64_first_increment_s"]
     if not args.no_serve:
         line["serving"] = serve_stream(args)
     if not args.no_cpu_baseline:

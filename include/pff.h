@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define PFF_ABI_VERSION 1
+#define PFF_ABI_VERSION 2
 
 typedef int pff_status;
 enum {
@@ -99,6 +99,7 @@ typedef struct {
   double load_factor, crack_length, target_a;
   double err[3];
   double seconds;
+  double dissipation;      /* D = sum over voxels of Gc gamma_f (eq. JaviGc, middle form), h = 1 */
 } pff_increment_result;
 
 int pff_abi_version(void);
@@ -148,7 +149,23 @@ typedef struct {
   double sigma_M[6];       /* Mandel */
   double err;              /* last stagger error */
   double seconds;
+  double dissipation;      /* as in pff_increment_result */
 } pff_stagger_result;
+
+/* Effective toughness from a macroscopic path (eq. JaviGc, right-hand form),
+ * host only, no device needed: work = integral of Sigma_M : f dE along the n
+ * path points (E[k], sigma_M[6k..6k+5] in the order 11, 22, 33, 23, 13, 12,
+ * as pff_increment_result reports them) by the trapezoidal rule, starting
+ * from the unloaded state (0, 0) and following the path order (segments with
+ * decreasing E, the snap-backs of crack-length control, count negative);
+ * gceff = volume * work / L_g, with volume the cell volume (N voxels of unit
+ * size) and L_g the crack length over which the toughness is measured (the
+ * cell length across the crack path, less the initial crack where one is
+ * given).  f: 3x3 row-major symmetric.  Outputs may be NULL.  Errors:
+ * PFF_ERR_ARG (n < 0, NULL path with n > 0, NULL f, non-positive volume or
+ * L_g, non-finite result). */
+pff_status pff_effective_toughness(int n, const double* E, const double* sigma_M, const double* f,
+                                   double volume, double L_g, double* work, double* gceff);
 
 /* Fill *p with the defaults above.  Errors: PFF_ERR_ARG (p NULL). */
 pff_status pff_stagger_defaults(pff_stagger_params* p);
@@ -182,9 +199,11 @@ pff_status pff_set_state(pff_solver* s, const double* eps_tilde, const double* p
 /* Hot path, step (a1)+(a8): constitutive update at the current state and
  * the FP64 residual F = (F1, F2, F3) for target crack length `a`
  * (eq. System_CrackLength); F_dev receives (C+1)*N+1 doubles or may be
- * NULL.  Host outputs (may be NULL): gamma = Gamma(phi), sigma_M[6]. */
+ * NULL.  Host outputs (may be NULL): gamma = Gamma(phi), sigma_M[6], and
+ * dissipation = sum of Gc gamma_f (the Gc-weighted crack functional, eq.
+ * JaviGc middle form). */
 pff_status pff_residual(pff_solver* s, double a, double* F_dev, double* gamma,
-                        double* sigma_M);
+                        double* sigma_M, double* dissipation);
 
 /* Hot path, steps (a2)-(a6): Jv = dF(q; v) at the state of the last
  * pff_residual call (eq. CrackLength_linearization). v_dev, Jv_dev: Krylov

@@ -63,6 +63,12 @@ class System:
         l = self.l
         return float(np.sum(phi * phi / (2.0 * l) - 0.5 * l * phi * fo.laplacian(phi)))
 
+    def dissipation(self, phi):
+        """D = integral of Gc gamma_f (eq. `JaviGc`, middle form; unit voxels),
+        gamma_f in the spectral form of `gamma`."""
+        l = self.l
+        return float(np.sum(self.Gc * (phi * phi / (2.0 * l) - 0.5 * l * phi * fo.laplacian(phi))))
+
     # -- residual (eq. System_CrackLength) ---------------------------------
     def residual(self, eps_t, phi, E, Hn, a):
         eps = eps_t + self.fE(E)

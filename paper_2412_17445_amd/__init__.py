@@ -5,6 +5,8 @@ this package only builds it and marshals arguments to it.
 """
 
 from ._lib import load as load_library  # noqa: F401
-from .solver import PffError, Server, Solver, footprint_bytes, problem_kwargs  # noqa: F401
+from .solver import (PffError, Server, Solver, effective_toughness, footprint_bytes,  # noqa: F401
+                     problem_kwargs)
 
-__all__ = ["Solver", "Server", "PffError", "footprint_bytes", "problem_kwargs", "load_library"]
+__all__ = ["Solver", "Server", "PffError", "effective_toughness", "footprint_bytes", "problem_kwargs",
+           "load_library"]

@@ -37,7 +37,8 @@ class pff_increment_result(C.Structure):
                 ("converged", C.c_int), ("applies", C.c_longlong), ("applies_fp64", C.c_longlong),
                 ("fp64_fallbacks", C.c_int), ("refinements", C.c_int), ("sigma_M", C.c_double * 6),
                 ("load_factor", C.c_double), ("crack_length", C.c_double),
-                ("target_a", C.c_double), ("err", C.c_double * 3), ("seconds", C.c_double)]
+                ("target_a", C.c_double), ("err", C.c_double * 3), ("seconds", C.c_double),
+                ("dissipation", C.c_double)]
 
 
 class pff_stagger_params(C.Structure):
@@ -49,7 +50,7 @@ class pff_stagger_result(C.Structure):
     _fields_ = [("increment", C.c_int), ("converged", C.c_int), ("stagger_iters", C.c_int),
                 ("newton_iters", C.c_int), ("cg_mech", C.c_longlong), ("cg_helm", C.c_longlong),
                 ("E", C.c_double), ("crack_length", C.c_double), ("sigma_M", C.c_double * 6),
-                ("err", C.c_double), ("seconds", C.c_double)]
+                ("err", C.c_double), ("seconds", C.c_double), ("dissipation", C.c_double)]
 
 
 class pff_request_info(C.Structure):
@@ -73,6 +74,8 @@ EXPORTS = {
                              C.c_void_p, C.POINTER(pff_params), C.c_void_p, C.POINTER(C.c_void_p)]),
     "pff_bootstrap": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pff_step": (C.c_int, [C.c_void_p, C.POINTER(pff_increment_result)]),
+    "pff_effective_toughness": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                          C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pff_stagger_defaults": (C.c_int, [C.POINTER(pff_stagger_params)]),
     "pff_stagger_step": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(pff_stagger_params),
                                    C.POINTER(pff_stagger_result)]),
@@ -81,7 +84,7 @@ EXPORTS = {
     "pff_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                 C.c_double, C.c_int]),
     "pff_residual": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.POINTER(C.c_double),
-                               C.c_void_p]),
+                               C.c_void_p, C.POINTER(C.c_double)]),
     "pff_apply_tangent": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pff_project": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "pff_krylov_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,

@@ -59,6 +59,7 @@ enum {
   SC_GAMMA = 6, SC_F1 = 7, SC_F2 = 8,
   SC_NW = 9, SC_NEPS = 10, SC_NDPHI = 11, SC_NPHI = 12,
   SC_ETA = 13,     // 2 slots: ||b - J x||^2, ||b||^2 of the FP64 check
+  SC_DISS = 15,    // dissipation: sum of Gc gamma_f
   SC_CG = 16,      // CG scratch; staggered scheme: [17] max |d eps~|, [18..21] stagger norms
   SC_KS = 32,      // Krylov scalars
   SC_COUNT = 64
@@ -532,6 +533,7 @@ struct FinResid {
     F.scal[SC_GAMMA] = tot[0];
     F.scal[SC_F1] = tot[1];
     F.scal[SC_F2] = tot[2];
+    F.scal[SC_DISS] = tot[3];
     F.rhs_last[0] = F.a - tot[0];
     if (F.rhs32_last) F.rhs32_last[0] = float(F.a - tot[0]);
     if (F.F_last) F.F_last[0] = tot[0] - F.a;
@@ -652,7 +654,7 @@ struct Impl {
     const long long last = (long long)(C + 1) * s->N;
     FinResid::Args fr{s->scal, a, vecs<double>(s, RHS) + last,
                       s->kv32[RHS] ? s->kv32[RHS] + last : nullptr, F_dev ? F_dev + last : nullptr};
-    k_reduce<FinResid><<<1, kBlock, 0, s->stream>>>(s->part1, nblk, 3, fr);
+    k_reduce<FinResid><<<1, kBlock, 0, s->stream>>>(s->part1, nblk, 4, fr);
     LAUNCH_CHECK();
     s->ts_valid = true;
   }
@@ -1590,10 +1592,31 @@ pff_status pff_step(pff_solver* s, pff_increment_result* out) {
       for (int q = 0; q < 6; ++q) out->sigma_M[q] = s->hscal[SC_SIG + q] / double(N);
       out->load_factor = Ecur;
       out->crack_length = s->hscal[SC_GAMMA];
+      out->dissipation = s->hscal[SC_DISS];
       out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return PFF_OK;
   });
+}
+
+pff_status pff_effective_toughness(int n, const double* E, const double* sigma_M, const double* f,
+                                   double volume, double L_g, double* work, double* gceff) {
+  if (n < 0 || (n > 0 && (!E || !sigma_M)) || !f || !(volume > 0.0) || !(L_g > 0.0)) return PFF_ERR_ARG;
+  // Sigma : f with sigma_M = (11, 22, 33, 23, 13, 12) and f a symmetric 3x3 tensor
+  auto sf = [&](int k) {
+    const double* q = sigma_M + 6 * (long long)k;
+    return q[0] * f[0] + q[1] * f[4] + q[2] * f[8] + 2.0 * (q[3] * f[5] + q[4] * f[2] + q[5] * f[1]);
+  };
+  double W = 0.0, E0 = 0.0, S0 = 0.0;   // the path starts unloaded
+  for (int k = 0; k < n; ++k) {
+    const double S1 = sf(k);
+    W += 0.5 * (S0 + S1) * (E[k] - E0);
+    E0 = E[k];
+    S0 = S1;
+  }
+  if (work) *work = W;
+  if (gceff) *gceff = volume * W / L_g;
+  return std::isfinite(W) ? PFF_OK : PFF_ERR_ARG;
 }
 
 pff_status pff_stagger_defaults(pff_stagger_params* p) {
@@ -1656,6 +1679,7 @@ pff_status pff_stagger_step(pff_solver* s, double dE, const pff_stagger_params* 
     if (out) {
       for (int q = 0; q < 6; ++q) out->sigma_M[q] = s->hscal[SC_SIG + q] / double(N);
       out->crack_length = s->hscal[SC_GAMMA];
+      out->dissipation = s->hscal[SC_DISS];
       out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return PFF_OK;
@@ -1704,7 +1728,8 @@ pff_status pff_set_state(pff_solver* s, const double* eps_tilde, const double* p
   });
 }
 
-pff_status pff_residual(pff_solver* s, double a, double* F_dev, double* gamma, double* sigma_M) {
+pff_status pff_residual(pff_solver* s, double a, double* F_dev, double* gamma, double* sigma_M,
+                        double* dissipation) {
   return guarded(s, [&]() -> pff_status {
     dispatch(s, [&](auto impl) {
       using I = decltype(impl);
@@ -1712,6 +1737,7 @@ pff_status pff_residual(pff_solver* s, double a, double* F_dev, double* gamma, d
     });
     sync_scal(s);
     if (gamma) *gamma = s->hscal[SC_GAMMA];
+    if (dissipation) *dissipation = s->hscal[SC_DISS];
     if (sigma_M)
       for (int q = 0; q < 6; ++q) sigma_M[q] = s->hscal[SC_SIG + q] / double(s->N);
     return PFF_OK;

@@ -175,7 +175,7 @@ struct ResidualPipe {
   static constexpr int D = DIM == 2 ? 2 : 3;
   static constexpr int NF = C + 1;
   static constexpr int NRED_PRO = 6;   // sum of sigma: 11, 22, 33, 23, 13, 12
-  static constexpr int NRED_EPI = 3;   // Gamma, ||F1||^2, ||F2||^2
+  static constexpr int NRED_EPI = 4;   // Gamma, ||F1||^2, ||F2||^2, dissipation
   struct Args {
     GridDesc g;
     Material mat;
@@ -293,9 +293,12 @@ struct ResidualPipe {
     A.rhs[C * N + i] = -F2;
     if (A.rhs32) A.rhs32[C * N + i] = float(-F2);
     if (A.F) A.F[C * N + i] = F2;
-    red[0] += phi * phi / (2.0 * l) - 0.5 * l * phi * lap;
+    const double gam = phi * phi / (2.0 * l) - 0.5 * l * phi * lap;
+    red[0] += gam;
     red[1] += f1;
     red[2] += F2 * F2;
+    red[3] += Gc * gam;                      // Gc-weighted crack functional
+
   }
 };
 

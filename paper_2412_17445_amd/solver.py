@@ -65,7 +65,7 @@ def _result_dict(r):
                 converged=bool(r.converged), applies=r.applies, applies_fp64=r.applies_fp64,
                 fp64_fallbacks=r.fp64_fallbacks, refinements=r.refinements,
                 sigma_M=list(r.sigma_M), E=r.load_factor, Gamma=r.crack_length,
-                a=r.target_a, err=list(r.err), seconds=r.seconds)
+                a=r.target_a, err=list(r.err), seconds=r.seconds, dissipation=r.dissipation)
 
 
 class Solver:
@@ -153,7 +153,7 @@ class Solver:
         return dict(increment=r.increment, converged=bool(r.converged), stagger_iters=r.stagger_iters,
                     newton_iters=r.newton_iters, cg_mech=r.cg_mech, cg_helm=r.cg_helm, E=r.E,
                     Gamma=r.crack_length, sigma_M=list(r.sigma_M), err=r.err, seconds=r.seconds,
-                    status=st)
+                    dissipation=r.dissipation, status=st)
 
     def device_bytes(self):
         b = C.c_size_t()
@@ -180,13 +180,14 @@ class Solver:
                                            float(E), float(a), int(n)), "pff_set_state")
 
     def residual(self, a, want_F=True):
+        """(F on the device or None, Gamma, Sigma_M, dissipation) at the current state."""
         torch = _torch()
         F = torch.empty(self.M, dtype=torch.float64, device="cuda") if want_F else None
-        gam = C.c_double()
+        gam, dis = C.c_double(), C.c_double()
         sig = (C.c_double * 6)()
         self._check(self.lib.pff_residual(self.h, float(a), None if F is None else F.data_ptr(),
-                                          C.byref(gam), sig), "pff_residual")
-        return F, gam.value, list(sig)
+                                          C.byref(gam), sig, C.byref(dis)), "pff_residual")
+        return F, gam.value, list(sig), dis.value
 
     def apply(self, v, out=None):
         torch = _torch()
@@ -247,6 +248,23 @@ class Solver:
     def load(self, data):
         buf = (C.c_ubyte * len(data)).from_buffer_copy(data)
         self._check(self.lib.pff_load(self.h, buf, len(data)), "pff_load")
+
+
+def effective_toughness(E, sigma_M, f, volume, L_g):
+    """(work, G_Ceff) of a macroscopic path: E[k] and sigma_M[k] (11, 22, 33,
+    23, 13, 12) per increment in path order, f the 3x3 loading tensor
+    (pff_effective_toughness, host only)."""
+    E = np.ascontiguousarray(E, dtype=np.float64).reshape(-1)
+    S = np.ascontiguousarray(sigma_M, dtype=np.float64).reshape(-1)
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+    if S.size != 6 * E.size or f.size != 9:
+        raise ValueError("sigma_M must hold 6 values per path point and f 9 values")
+    w, g = C.c_double(), C.c_double()
+    st = L.load().pff_effective_toughness(E.size, E.ctypes.data, S.ctypes.data, f.ctypes.data,
+                                          float(volume), float(L_g), C.byref(w), C.byref(g))
+    if st != L.PFF_OK:
+        raise PffError(st, "pff_effective_toughness: invalid arguments")
+    return w.value, g.value
 
 
 def footprint_bytes(shape, precision):

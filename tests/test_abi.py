@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
     lib = L.load()
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert lib.pff_abi_version() == 1
+    assert lib.pff_abi_version() == 2
 
 
 def test_struct_layouts():
@@ -42,7 +42,38 @@ def test_struct_layouts():
     assert C.sizeof(L.pff_phase) == 24
     # 4 doubles + f[9] + 3 doubles, then 3 ints (+ padding)
     assert C.sizeof(L.pff_params) == 8 * (2 + 9 + 4) + 4 * 3 + 4
-    assert C.sizeof(L.pff_increment_result) == 4 * 4 + 8 * 2 + 4 * 2 + 8 * (6 + 3 + 3 + 1)
+    assert C.sizeof(L.pff_increment_result) == 4 * 4 + 8 * 2 + 4 * 2 + 8 * (6 + 3 + 3 + 2)
+
+
+STRUCTS = ["pff_grid", "pff_phase", "pff_params", "pff_increment_result", "pff_stagger_params",
+           "pff_stagger_result", "pff_request_info", "pff_server_stats"]
+
+
+def test_ctypes_layouts_match_the_c_compiler(tmp_path):
+    """sizeof and every field offset of the header's structs, as gcc lays
+    them out, equal the ctypes mirrors of the binding."""
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pff.h"', "int main(void) {"]
+    want = []
+    for name in STRUCTS:
+        cls = getattr(L, name)
+        lines.append(f'  printf("%zu\\n", sizeof({name}));')
+        want.append(C.sizeof(cls))
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({name}, {fname}));')
+            want.append(getattr(cls, fname).offset)
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got == want
 
 
 def _params(**kw):

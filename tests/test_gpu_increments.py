@@ -86,6 +86,9 @@ def test_fp64_increments_match_oracle(case):
         out = s.step()
         assert out["converged"], out
         errs.append(max(_errors(out, ref)))
+        if len(prob.phases) == 1 or len({ph[2] for ph in prob.phases}) == 1:
+            Gc = prob.phases[0][2]           # uniform toughness: D = Gc Gamma
+            assert abs(out["dissipation"] - Gc * out["Gamma"]) <= 1e-13 * Gc * out["Gamma"]
         print(case, "fp64 increment", ref["increment"], "max rel err %.2e" % errs[-1], flush=True)
     s.close()
     assert max(errs) <= tol, (max(errs), tol)

@@ -111,7 +111,7 @@ def test_newton_solve_on_own_residual_near_root():
     s = gpu_solver(prob, precision="fp64")
     s.bootstrap()
     s.set_state(eps_t, phi, o.Hn, E, o.a, 0)
-    F, _, _ = s.residual(a_new)
+    F, _, _, _ = s.residual(a_new)
     assert float(F.abs().max()) < 1e-9          # close to the root
     x, it, rr, ok = s.krylov_solve(F.neg(), rtol=1e-10, maxit=2000)
     assert ok and rr <= 1e-10, (it, rr)
@@ -137,7 +137,7 @@ def test_residual_and_tangent(name, shape, precision):
     a = 2.5
     s = gpu_solver(prob)
     s.set_state(eps_t, phi, Hn, E, a - 1.0, n=1)
-    F, gam, sig = s.residual(a)
+    F, gam, sig, dis = s.residual(a)
     R = sysm.residual(eps_t, phi, E, Hn, a)
     F = F.cpu().numpy()
     c, N = sysm.ncomp, sysm.N
@@ -145,6 +145,8 @@ def test_residual_and_tangent(name, shape, precision):
     assert rel(F[c * N:(c + 1) * N], R["F2"].ravel()) < 1e-11
     assert abs(F[-1] - R["F3"]) <= 1e-12 * abs(R["Gamma"])
     assert abs(gam - R["Gamma"]) <= 1e-12 * abs(R["Gamma"])
+    D = sysm.dissipation(phi)
+    assert abs(dis - D) <= 1e-12 * abs(D)
     sM = R["sigma_M"]
     ref_sig = [sM[0, 0], sM[1, 1], sM[2, 2], sM[1, 2], sM[0, 2], sM[0, 1]]
     assert rel(sig, ref_sig) < 1e-12
@@ -170,7 +172,7 @@ def test_krylov_solve(name):
     eps_t, phi, E, Hn = _frozen_state(sysm, 4)
     s = gpu_solver(prob)
     s.set_state(eps_t, phi, Hn, E, 1.0, n=1)
-    F, _, _ = s.residual(2.0)
+    F, _, _, _ = s.residual(2.0)
     b = -F
     x, it, rr, ok = s.krylov_solve(b, rtol=1e-10, maxit=3000)
     assert ok and rr <= 1e-10

@@ -64,6 +64,46 @@ def test_homogeneous_uniaxial_closed_form():
         for q in range(3):
             assert abs(sig[q] - ref[q]) <= 1e-9 * abs(ref[q]), (q, sig[q], ref[q])
         assert max(abs(v) for v in sig[3:]) <= 1e-12
+        D = n * n * Gc * phi * phi / (2 * l)         # uniform damage: no gradient term
+        assert abs(out["dissipation"] - D) <= 1e-9 * D
+    s.close()
+
+
+@pytest.mark.gpu
+def test_homogeneous_work_equals_energy_plus_dissipation():
+    """Along the strain-controlled homogeneous path the damage minimises
+    g psi0+ + Gc phi^2/(2l) at every load, so the area under the macroscopic
+    curve (pff_effective_toughness) equals the elastic energy plus the
+    dissipation the GPU reports, up to the trapezoidal rule's O(dE^2)."""
+    from paper_2412_17445_amd import effective_toughness
+    from synth.configs import Problem, _dyad
+    n, Ey, nu, Gc, l, k = 8, 1.0, 0.3, 1e-3, 2.0, 1e-6
+    prob = Problem(name="hom", shape=(1, n, n), phases=[(Ey, nu, Gc)],
+                   phase_id=np.zeros((1, n, n), np.uint8), mask=None, f=_dyad(1, 1), l=l, k=k)
+    lam = Ey * nu / ((1 + nu) * (1 - 2 * nu))
+    mu = Ey / (2 * (1 + nu))
+    s = _solver(prob)
+    Es, sig = [], []
+    for _ in range(200):
+        o = s.stagger_step(2.5e-4)
+        assert o["converged"]
+        Es.append(o["E"])
+        sig.append(o["sigma_M"])
+    E = Es[-1]
+    H = (0.5 * lam + mu) * E * E
+    phi = 2 * H / (Gc / l + 2 * H)
+    elastic = n * n * ((1 - phi) ** 2 + k) * H
+    work, gceff = effective_toughness(Es, sig, prob.f, n * n, n)
+    # the same trapezoidal rule over the closed-form path at the same loads
+    Ea = np.array(Es)
+    Ha = (0.5 * lam + mu) * Ea * Ea
+    ga = (1 - 2 * Ha / (Gc / l + 2 * Ha)) ** 2 + k
+    sf = ga * (lam + 2 * mu) * Ea
+    exact_trap = float(np.sum(0.5 * (sf + np.concatenate([[0.0], sf[:-1]])) * np.diff(np.concatenate([[0.0], Ea]))))
+    assert abs(work - exact_trap) <= 1e-8 * exact_trap
+    # trapezoidal error of 200 equal steps on this path: 3.4e-5 (oracle pin)
+    assert abs(work * n * n - (elastic + o["dissipation"])) <= 5e-5 * (elastic + o["dissipation"])
+    assert gceff == pytest.approx(work * n * n / n, rel=1e-14)
     s.close()
 
 
