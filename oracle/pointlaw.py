@@ -24,6 +24,12 @@ Paper Sec. 2.1 (eqs. `Emec`, `PlusNegPsi`, `gFunct`), Sec. 2.3 (eq.
   reaches the damage rows while the constraint row still asks for damage.)
 Theta(x) = 1 for x > 0 and 0 otherwise.  Plane strain (2D) is the 3x3
 problem with zero out-of-plane strain.
+
+Isotropic variant (`iso=True`, Sec. 5.4: no split, the whole elastic energy
+psi0 = psi0(+) + psi0(-) is degraded): sigma = g sigma0, C = g C0, and
+psi0 takes the place of psi0(+) as the history driver (H = max(psi0, Hn))
+and sigma0 the place of sigma0(+) in d sigma / d phi.  The returned keys keep
+their names: psi_p is the driving energy and sigma0p the degraded stress part.
 """
 
 from __future__ import annotations
@@ -41,7 +47,7 @@ def heaviside(x):
     return (x > 0.0).astype(np.float64)
 
 
-def evaluate(eps_t, phi, Hn, lam, mu, k):
+def evaluate(eps_t, phi, Hn, lam, mu, k, iso=False):
     """Point law on a tensor field eps_t (3, 3, ...) with per-voxel lam, mu.
 
     Returns a dict with sigma, sigma0p, psi_p, psi_m, H, chi, g and the
@@ -61,6 +67,9 @@ def evaluate(eps_t, phi, Hn, lam, mu, k):
     s0p = (lam * trp)[..., None, None] * I + 2.0 * mu[..., None, None] * epsp
     s0m = (lam * trm)[..., None, None] * I + 2.0 * mu[..., None, None] * epsm
     g = (1.0 - phi) ** 2 + k
+    if iso:                                  # the whole energy is degraded
+        psi_p, psi_m = psi_p + psi_m, np.zeros_like(psi_m)
+        s0p, s0m = s0p + s0m, np.zeros_like(s0m)
     sigma = g[..., None, None] * s0p + s0m
     H = np.maximum(psi_p, Hn)
     chi = (psi_p >= Hn).astype(np.float64)
@@ -72,9 +81,13 @@ def evaluate(eps_t, phi, Hn, lam, mu, k):
     denom = np.where(differ, za - zb, 1.0)
     theta = np.where(differ, (pa - pb) / denom,
                      np.broadcast_to(ta[..., :, None], differ.shape))
+    trflag = heaviside(tr)
+    if iso:                                  # P(+) = identity, Theta(tr) = 1: C = g C0
+        theta = np.ones_like(theta)
+        trflag = np.ones_like(trflag)
     back = lambda t: np.moveaxis(t, (-2, -1), (0, 1))   # noqa: E731
     return dict(sigma=back(sigma), sigma0p=back(s0p), sigma0m=back(s0m),
-                psi_p=psi_p, psi_m=psi_m, H=H, chi=chi, g=g, tr=tr,
+                psi_p=psi_p, psi_m=psi_m, H=H, chi=chi, g=g, tr=tr, trflag=trflag,
                 vec=vec, theta=theta, lam=lam, mu=mu)
 
 
@@ -87,7 +100,7 @@ def tangent_apply(st, w_t):
     PpW = vec @ (theta * Wp) @ vecT
     g, lam, mu = st["g"], st["lam"], st["mu"]
     trw = np.trace(W, axis1=-2, axis2=-1)
-    coef = lam * ((g - 1.0) * heaviside(st["tr"]) + 1.0) * trw
+    coef = lam * ((g - 1.0) * st["trflag"] + 1.0) * trw
     out = coef[..., None, None] * np.eye(3) + 2.0 * mu[..., None, None] * (
         W + (g - 1.0)[..., None, None] * PpW)
     return np.moveaxis(out, (-2, -1), (0, 1))

@@ -48,6 +48,7 @@ class System:
                   else np.asarray(prob.mask, dtype=np.float64).reshape(self.shape))
         self.l = float(prob.l)
         self.k = float(prob.k)
+        self.iso = getattr(prob, "split", "spectral") == "none"
         self.f = fo.to_mandel(np.asarray(prob.f, dtype=np.float64)[:, :, None, None, None],
                               self.ncomp)[:, 0, 0, 0]
 
@@ -56,7 +57,7 @@ class System:
         return self.f.reshape((self.ncomp, 1, 1, 1)) * E
 
     def point(self, eps, phi, Hn):
-        return pl.evaluate(fo.to_tensor(eps), phi, Hn, self.lam, self.mu, self.k)
+        return pl.evaluate(fo.to_tensor(eps), phi, Hn, self.lam, self.mu, self.k, iso=self.iso)
 
     def gamma(self, phi):
         """Crack length/area Gamma(phi) (eq. `CrackLenght`, spectral form)."""

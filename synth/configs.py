@@ -49,6 +49,7 @@ class Problem:
     krylov_rtol: float = 1e-10
     krylov_maxit: int = 5000
     precision: str = "fp64"              # "fp64" or "mixed"
+    split: str = "spectral"              # "spectral" (Miehe split) or "none" (isotropic degradation)
     notes: str = ""
     extra: dict = field(default_factory=dict)
 

@@ -28,34 +28,36 @@ def material(rng, n):
     return pl.lame(E, nu)
 
 
-def ev(eps, phi, Hn, lam, mu, k=1e-6):
-    return pl.evaluate(eps, phi, Hn, lam, mu, k)
+def ev(eps, phi, Hn, lam, mu, k=1e-6, iso=False):
+    return pl.evaluate(eps, phi, Hn, lam, mu, k, iso=iso)
 
 
+@pytest.mark.parametrize("iso", [False, True])
 @pytest.mark.parametrize("plane", [False, True])
-def test_euler_identity(plane):
+def test_euler_identity(plane, iso):
     rng = np.random.default_rng(0)
     n = 500
     eps = rand_sym(rng, n, plane=plane)
     lam, mu = material(rng, n)
     phi = rng.uniform(0, 1, n)
-    st = ev(eps, phi, np.zeros(n), lam, mu)
+    st = ev(eps, phi, np.zeros(n), lam, mu, iso=iso)
     Ce = pl.tangent_apply(st, eps)
     assert np.allclose(Ce, st["sigma"], atol=1e-15, rtol=1e-12)
 
 
+@pytest.mark.parametrize("iso", [False, True])
 @pytest.mark.parametrize("plane", [False, True])
-def test_tangent_against_stress_differences(plane):
+def test_tangent_against_stress_differences(plane, iso):
     rng = np.random.default_rng(1)
     n = 400
     eps = rand_sym(rng, n, plane=plane)
     w = rand_sym(rng, n, plane=plane)
     lam, mu = material(rng, n)
     phi = rng.uniform(0, 1, n)
-    st = ev(eps, phi, np.zeros(n), lam, mu)
+    st = ev(eps, phi, np.zeros(n), lam, mu, iso=iso)
     h = 1e-7
-    sp = ev(eps + h * w, phi, np.zeros(n), lam, mu)["sigma"]
-    sm = ev(eps - h * w, phi, np.zeros(n), lam, mu)["sigma"]
+    sp = ev(eps + h * w, phi, np.zeros(n), lam, mu, iso=iso)["sigma"]
+    sm = ev(eps - h * w, phi, np.zeros(n), lam, mu, iso=iso)["sigma"]
     fd = (sp - sm) / (2 * h)
     Cw = pl.tangent_apply(st, w)
     err = np.abs(fd - Cw).max(axis=(0, 1)) / np.abs(Cw).max(axis=(0, 1))
@@ -161,3 +163,26 @@ def test_history_flag():
     st = ev(eps, np.zeros(3), Hn, lam, mu)
     assert list(st["chi"]) == [1.0, 1.0, 0.0]        # ties count as loading
     assert np.allclose(st["H"], [psi, psi, 2 * psi])
+
+
+def test_isotropic_variant_is_degraded_linear_elasticity():
+    """No split: sigma = g (lambda tr eps I + 2 mu eps) for any strain, and
+    the driving energy is the whole psi0 = eps : C0 : eps / 2, also in
+    compression, where the split model has no driving energy."""
+    rng = np.random.default_rng(7)
+    n = 300
+    eps = rand_sym(rng, n)
+    lam, mu = material(rng, n)
+    phi = rng.uniform(0, 1, n)
+    st = ev(eps, phi, np.zeros(n), lam, mu, iso=True)
+    g = (1 - phi) ** 2 + 1e-6
+    tr = np.einsum("ii...->...", eps)
+    s0 = lam * tr * np.eye(3)[:, :, None] + 2 * mu * eps
+    assert np.allclose(st["sigma"], g * s0, rtol=1e-12, atol=1e-17)
+    psi0 = 0.5 * np.einsum("ij...,ij...->...", s0, eps)
+    assert np.allclose(st["psi_p"], psi0, rtol=1e-12, atol=1e-20)
+    comp = -np.abs(rand_sym(rng, 1))[:, :, 0]
+    comp = np.diag(np.diag(comp))[:, :, None]                # all eigenvalues negative
+    l1, m1 = np.array([1.0]), np.array([0.7])
+    assert ev(comp, np.zeros(1), np.zeros(1), l1, m1)["psi_p"][0] == 0.0
+    assert ev(comp, np.zeros(1), np.zeros(1), l1, m1, iso=True)["psi_p"][0] > 0.0

@@ -44,6 +44,31 @@ def test_homogeneous_uniaxial_closed_form():
         assert abs(sig[0, 1]) <= 1e-12
 
 
+def test_homogeneous_compression_damages_only_without_split():
+    """Uniaxial plane-strain compression: the spectral split leaves no
+    driving energy (all strain eigenvalues and the trace are <= 0), the
+    isotropic model is driven by the whole psi0 = (lambda/2 + mu) E^2."""
+    n = 8
+    Ey, nu, Gc, l, k = 1.0, 0.3, 1e-3, 2.0, 1e-6
+    lam = Ey * nu / ((1 + nu) * (1 - 2 * nu))
+    mu = Ey / (2 * (1 + nu))
+    for split in ("spectral", "none"):
+        prob = Problem(name="hom", shape=(1, n, n), phases=[(Ey, nu, Gc)],
+                       phase_id=np.zeros((1, n, n), np.uint8), mask=None, f=_dyad(1, 1), l=l, k=k,
+                       split=split)
+        st = StaggeredSolver(prob, dE=-0.02)
+        out = st.step()
+        E = out["E"]
+        H = (0.5 * lam + mu) * E * E if split == "none" else 0.0
+        phi = 2 * H / (Gc / l + 2 * H)
+        g = (1 - phi) ** 2 + k
+        assert np.abs(st.phi - phi).max() <= 1e-9 * max(phi, 1e-300)
+        sig = out["sigma_M"]
+        gs = g if split == "none" else 1.0
+        assert abs(sig[1, 1] - gs * (lam + 2 * mu) * E) <= 1e-9 * abs((lam + 2 * mu) * E)
+        assert abs(sig[0, 0] - gs * lam * E) <= 1e-9 * abs(lam * E)
+
+
 @pytest.mark.parametrize("case", ["tiny16", "gc16"])
 def test_reaches_the_crack_length_controlled_root(case):
     prob = problem_config(case)

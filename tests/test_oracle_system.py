@@ -32,9 +32,12 @@ def _state(sys, seed):
     return eps_t, phi, E, Hn
 
 
-@pytest.mark.parametrize("name", ["tiny16", "fib64", "pore24", "part24"])
-def test_tangent_is_residual_derivative(name):
+@pytest.mark.parametrize("name,split", [("tiny16", "spectral"), ("fib64", "spectral"),
+                                        ("pore24", "spectral"), ("part24", "spectral"),
+                                        ("tiny16", "none"), ("part24", "none")])
+def test_tangent_is_residual_derivative(name, split):
     prob = problem_config(name)
+    prob.split = split
     if name == "fib64":
         prob.shape = (1, 32, 32)
         prob.phase_id = prob.phase_id[:, :32, :32]
