@@ -18,6 +18,12 @@ Readings taken here (the paper leaves them open):
   (q = 0 and modes with two or more Nyquist axes).  At an even axis' Nyquist
   index cos(q/2) is taken as exactly 0.
 * Laplacian symbol -|q|^2 with q_j = 2 pi m_j / N_j and the Nyquist mode kept.
+* Standard-frequency projection (the paper's eq. `GFourier` without the
+  rotated scheme, `scheme="standard"`): n = xi/|xi| with xi_j = q_j, except
+  that an even axis' Nyquist index contributes xi_j = 0.  The sign of the
+  Nyquist frequency is undefined (m = N/2 and -N/2 alias), and taking either
+  one would make the projected field complex; with xi_j = 0 the symbol is
+  even in every m_j and the projection maps real fields to real fields.
 Arrays are [z, y, x]; tensor index 0 <-> x, 1 <-> y, 2 <-> z.
 """
 
@@ -99,6 +105,33 @@ def rotated_direction(shape):
     return n, zero
 
 
+def standard_direction(shape):
+    """Unit vectors n = xi/|xi| of the standard scheme and the mask of xi == 0."""
+    nz, ny, nx = shape
+
+    def axis(n_):
+        q = 2.0 * np.pi * np.fft.fftfreq(n_)
+        if n_ % 2 == 0:
+            q[n_ // 2] = 0.0                # Nyquist: no signed frequency
+        return q
+
+    rx = np.broadcast_to(axis(nx)[None, None, :], shape)
+    ry = np.broadcast_to(axis(ny)[None, :, None], shape)
+    rz = np.broadcast_to(axis(nz)[:, None, None], shape)
+    r2 = rx * rx + ry * ry + rz * rz
+    zero = r2 == 0.0
+    inv = np.where(zero, 0.0, 1.0 / np.sqrt(np.where(zero, 1.0, r2)))
+    return np.stack([rx * inv, ry * inv, rz * inv]), zero
+
+
+def direction(shape, scheme="rotated"):
+    if scheme == "rotated":
+        return rotated_direction(shape)
+    if scheme == "standard":
+        return standard_direction(shape)
+    raise ValueError(scheme)
+
+
 def project_hat(A_hat, n, zero):
     """P(A) = (A n) (x) n + n (x) (A n) - (n . A n) n (x) n, zero where r = 0."""
     An = np.einsum("ij...,j...->i...", A_hat, n)
@@ -118,17 +151,17 @@ def ifftn(a):
     return np.fft.ifftn(a, axes=(-3, -2, -1))
 
 
-def G_tensor(A):
+def G_tensor(A, scheme="rotated"):
     """Projection of a real symmetric tensor field A (3, 3, nz, ny, nx)."""
     shape = A.shape[2:]
-    n, zero = rotated_direction(shape)
+    n, zero = direction(shape, scheme)
     out = project_hat(fftn(A), n, zero)
     return ifftn(out).real
 
 
-def G_mandel(m):
+def G_mandel(m, scheme="rotated"):
     """Projection acting on a Mandel field (c, nz, ny, nx)."""
-    return to_mandel(G_tensor(to_tensor(m)), m.shape[0])
+    return to_mandel(G_tensor(to_tensor(m), scheme), m.shape[0])
 
 
 def laplacian(phi):

@@ -49,6 +49,7 @@ class System:
         self.l = float(prob.l)
         self.k = float(prob.k)
         self.iso = getattr(prob, "split", "spectral") == "none"
+        self.scheme = getattr(prob, "projection", "rotated")
         self.f = fo.to_mandel(np.asarray(prob.f, dtype=np.float64)[:, :, None, None, None],
                               self.ncomp)[:, 0, 0, 0]
 
@@ -74,7 +75,7 @@ class System:
     def residual(self, eps_t, phi, E, Hn, a):
         eps = eps_t + self.fE(E)
         st = self.point(eps, phi, Hn)
-        F1 = fo.to_mandel(fo.G_tensor(st["sigma"]), self.ncomp)
+        F1 = fo.to_mandel(fo.G_tensor(st["sigma"], self.scheme), self.ncomp)
         lap = fo.laplacian(phi)
         l, Gc, H = self.l, self.Gc, st["H"]
         F2 = (1.0 - self.m) * ((Gc / l + 2.0 * H) * phi - Gc * l * lap - 2.0 * H)
@@ -102,7 +103,7 @@ class System:
             w = fo.to_tensor(d_eps + self.fE(dE))
             dphi_f = (1.0 - m) * d_phi
             tau = pl.tangent_apply(st, w) + b * dphi_f
-            J1 = fo.to_mandel(fo.G_tensor(tau), c)
+            J1 = fo.to_mandel(fo.G_tensor(tau, self.scheme), c)
             bw = np.einsum("ij...,ij...->...", b, w)
             J2 = (1.0 - m) * (st["chi"] * bw + A * dphi_f
                               - Gc * l * fo.laplacian(dphi_f)) + m * d_phi

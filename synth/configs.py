@@ -50,6 +50,7 @@ class Problem:
     krylov_maxit: int = 5000
     precision: str = "fp64"              # "fp64" or "mixed"
     split: str = "spectral"              # "spectral" (Miehe split) or "none" (isotropic degradation)
+    projection: str = "rotated"          # "rotated" (Willot) or "standard" frequencies in G
     notes: str = ""
     extra: dict = field(default_factory=dict)
 
@@ -67,7 +68,19 @@ CONFIG_NAMES = ("crack2d_64", "fibres2d_256", "pores3d_64",
 
 
 def problem_config(name: str) -> Problem:
-    """Return the seeded problem called `name` (benchmark or parity case)."""
+    """Return the seeded problem called `name` (benchmark or parity case).
+    A suffix "_iso" gives the same problem with the isotropic (no split)
+    degradation of Sec. 5.4."""
+    if name.endswith("_std"):
+        prob = problem_config(name[:-4])
+        prob.name, prob.projection = name, "standard"
+        prob.notes = (prob.notes + "; " if prob.notes else "") + "standard-frequency projection"
+        return prob
+    if name.endswith("_iso"):
+        prob = problem_config(name[:-4])
+        prob.name, prob.split = name, "none"
+        prob.notes = (prob.notes + "; " if prob.notes else "") + "isotropic degradation (no split)"
+        return prob
     if name == "crack2d_64":
         n = 64
         return Problem(

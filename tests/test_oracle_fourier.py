@@ -38,9 +38,10 @@ def random_compatible(shape, rng):
     return eps
 
 
+@pytest.mark.parametrize("scheme", ["rotated", "standard"])
 @pytest.mark.parametrize("shape", SHAPES)
-def test_projection_idempotent_symmetric(shape):
-    n, zero = fo.rotated_direction(shape)
+def test_projection_idempotent_symmetric(shape, scheme):
+    n, zero = fo.direction(shape, scheme)
     c = 3 if shape[0] == 1 else 6
     basis = np.eye(c)
     cols = []
@@ -131,3 +132,74 @@ def test_nyquist_rotated_zero_modes():
     assert zero[0, 0, 0] and zero[0, 4, 4]
     assert not zero[0, 0, 4] and not zero[0, 4, 0]
     assert np.allclose(np.abs(n[:, 0, 0, 4]), [1, 0, 0])
+
+
+# ---- standard-frequency projection (eq. GFourier without the rotated scheme) ----
+
+def plane_waves(shape, rng, nwave=4):
+    """Random sums of plane waves below the Nyquist index, with their exact
+    real-space derivatives (closed form, no FFT): returns (value, grad,
+    hessian) callables over the voxel grid."""
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    pos = (x, y, z)
+    waves = []
+    for _ in range(nwave):
+        k = [int(rng.integers(-((n - 1) // 2), (n - 1) // 2 + 1)) if n > 2 else 0 for n in (nx, ny, nz)]
+        q = np.array([2 * np.pi * k[0] / nx, 2 * np.pi * k[1] / ny, 2 * np.pi * k[2] / nz])
+        waves.append((q, rng.standard_normal(), rng.uniform(0, 2 * np.pi)))
+
+    def phase(q, th):
+        return q[0] * pos[0] + q[1] * pos[1] + q[2] * pos[2] + th
+
+    def val():
+        return sum(a * np.cos(phase(q, th)) for q, a, th in waves)
+
+    def grad(i):
+        return sum(-a * q[i] * np.sin(phase(q, th)) for q, a, th in waves)
+
+    def hess(i, j):
+        return sum(-a * q[i] * q[j] * np.cos(phase(q, th)) for q, a, th in waves)
+
+    return val, grad, hess
+
+
+@pytest.mark.parametrize("shape", [(1, 16, 16), (1, 12, 18), (1, 15, 9), (6, 8, 10), (5, 7, 9)])
+def test_standard_projection_keeps_exact_symmetric_gradients(shape):
+    rng = np.random.default_rng(11)
+    dim = 2 if shape[0] == 1 else 3
+    us = [plane_waves(shape, rng) for _ in range(3)]
+    eps = np.zeros((3, 3) + shape)
+    for i in range(dim):
+        for j in range(dim):
+            eps[i, j] = 0.5 * (us[i][1](j) + us[j][1](i))
+    out = fo.G_tensor(eps, "standard")
+    assert np.abs(out - eps).max() <= 1e-12 * np.abs(eps).max()
+    # the rotated scheme does not keep them: the two schemes differ
+    assert np.abs(fo.G_tensor(eps, "rotated") - eps).max() > 1e-3 * np.abs(eps).max()
+
+
+@pytest.mark.parametrize("shape", [(1, 16, 16), (1, 15, 9), (6, 8, 10)])
+def test_standard_projection_annihilates_exact_airy_stress(shape):
+    rng = np.random.default_rng(12)
+    _, _, H = plane_waves(shape, rng)
+    sig = np.zeros((3, 3) + shape)
+    sig[0, 0] = H(1, 1)
+    sig[1, 1] = H(0, 0)
+    sig[0, 1] = sig[1, 0] = -H(0, 1)
+    assert np.abs(fo.G_tensor(sig, "standard")).max() <= 1e-12 * np.abs(sig).max()
+
+
+def test_standard_projection_of_real_field_with_nyquist_content_is_real():
+    """Reading: xi_j = 0 at an even axis' Nyquist index keeps the projected
+    field real (either signed frequency there would not)."""
+    rng = np.random.default_rng(13)
+    shape = (4, 6, 8)
+    A = rng.standard_normal((3, 3) + shape)
+    A = 0.5 * (A + np.swapaxes(A, 0, 1))
+    n, zero = fo.direction(shape, "standard")
+    out = fo.ifftn(fo.project_hat(fo.fftn(A), n, zero))
+    assert np.abs(out.imag).max() <= 1e-14 * np.abs(A).max()
+    # modes whose non-zero indices are all Nyquist indices have xi = 0 and
+    # are projected to 0, like the DC mode
+    assert zero[0, 0, 4] and zero[2, 3, 4] and not zero[0, 1, 4]

@@ -34,7 +34,8 @@ def _state(sys, seed):
 
 @pytest.mark.parametrize("name,split", [("tiny16", "spectral"), ("fib64", "spectral"),
                                         ("pore24", "spectral"), ("part24", "spectral"),
-                                        ("tiny16", "none"), ("part24", "none")])
+                                        ("tiny16", "none"), ("part24", "none"),
+                                        ("tiny16_std", "spectral"), ("part24_std", "spectral")])
 def test_tangent_is_residual_derivative(name, split):
     prob = problem_config(name)
     prob.split = split
@@ -120,9 +121,14 @@ def _laminate_closed_form(phases, frac, E):
     return S, exx
 
 
-@pytest.mark.parametrize("shape", [(1, 8, 24), (1, 6, 21)])
-def test_laminate_closed_form(shape):
+@pytest.mark.parametrize("shape,scheme", [((1, 8, 24), "rotated"), ((1, 6, 21), "rotated"),
+                                          ((1, 6, 21), "standard")])
+def test_laminate_closed_form(shape, scheme):
+    """Exact laminate solution.  With standard frequencies only on an odd grid:
+    on an even one the Nyquist mode of the strain step is outside the range
+    of the projection (xi = 0 there)."""
     prob = problem_config("tiny16")
+    prob.projection = scheme
     prob.shape = shape
     prob.phases = [(1.0, 0.3, 1e-3), (5.0, 0.2, 1e-3)]
     prob.phase_id = laminate_x(shape[2], shape[1], shape[0], width=7, period=shape[2])
