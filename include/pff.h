@@ -78,11 +78,22 @@ typedef struct {
  *  krylov_rtol  BiCGSTAB stop ||r|| <= rtol ||b||
  *  precision    PFF_PREC_FP64 or PFF_PREC_MIXED (FP32 tangent/FFT/Krylov
  *               vectors, FP64 residual, inner products, constraint and
- *               load-factor update) */
+ *               load-factor update)
+ *  split        PFF_SPLIT_SPECTRAL (0): Miehe spectral split, g degrades
+ *               psi0(+) (eq. PlusNegPsi); PFF_SPLIT_NONE (1): isotropic
+ *               model of Sec. 5.4, g degrades the whole psi0, which also
+ *               drives the history
+ *  projection   PFF_PROJ_ROTATED (0): G built with Willot's rotated
+ *               frequencies (Sec. 3.1); PFF_PROJ_STANDARD (1): the plain
+ *               Fourier frequencies of eq. GFourier, with xi_j = 0 at an
+ *               even axis' Nyquist index (its sign is undefined) */
 typedef struct {
   double l, k_resid, f[9], delta_a, alpha, newton_tol, krylov_rtol;
-  int newton_maxit, krylov_maxit, precision;
+  int newton_maxit, krylov_maxit, precision, split, projection;
 } pff_params;
+
+enum { PFF_SPLIT_SPECTRAL = 0, PFF_SPLIT_NONE = 1 };
+enum { PFF_PROJ_ROTATED = 0, PFF_PROJ_STANDARD = 1 };
 
 /* Per-increment outputs (Algorithm 2): macroscopic stress Sigma_M = <sigma>
  * as tensor components [11, 22, 33, 23, 13, 12] (sigma_33 of plane strain

@@ -15,6 +15,8 @@ LIB_PATH = os.path.join(HERE, "libpff.so")
 PFF_OK, PFF_NOT_CONVERGED, PFF_QUEUED = 0, 1, 2
 PFF_ERR_ARG, PFF_ERR_OOM, PFF_ERR_DEVICE, PFF_ERR_STATE = -1, -2, -3, -4
 PFF_PREC_FP64, PFF_PREC_MIXED = 0, 1
+PFF_SPLIT_SPECTRAL, PFF_SPLIT_NONE = 0, 1
+PFF_PROJ_ROTATED, PFF_PROJ_STANDARD = 0, 1
 
 
 class pff_grid(C.Structure):
@@ -29,7 +31,8 @@ class pff_params(C.Structure):
     _fields_ = [("l", C.c_double), ("k_resid", C.c_double), ("f", C.c_double * 9),
                 ("delta_a", C.c_double), ("alpha", C.c_double), ("newton_tol", C.c_double),
                 ("krylov_rtol", C.c_double), ("newton_maxit", C.c_int),
-                ("krylov_maxit", C.c_int), ("precision", C.c_int)]
+                ("krylov_maxit", C.c_int), ("precision", C.c_int), ("split", C.c_int),
+                ("projection", C.c_int)]
 
 
 class pff_increment_result(C.Structure):

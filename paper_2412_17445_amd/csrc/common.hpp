@@ -50,6 +50,7 @@ struct AxisPlan {
 // Per-phase material constants (Lame lambda, mu and toughness Gc).
 struct Material {
   int nphase;
+  int iso;       // 1: isotropic degradation (no split): sigma = g sigma0, C = g C0, psi0 drives H
   double lam[kMaxPhases], mu[kMaxPhases], Gc[kMaxPhases];
 };
 

@@ -25,8 +25,8 @@
 namespace pff {
 
 template <typename T> struct SpecTables {
-  const T* hs[3];   // sin(q/2) per axis (x, y, z), indexed by mode index
-  const T* hc[3];   // cos(q/2), exactly 0 at an even axis' Nyquist index
+  const T* hs[3];   // sin(q/2) per axis (x, y, z), indexed by mode index (standard scheme: q)
+  const T* hc[3];   // cos(q/2), exactly 0 at an even axis' Nyquist index (standard scheme: 1)
   const T* q2[3];   // q^2 (standard frequencies, Nyquist kept)
   T invN;
 };

@@ -1123,7 +1123,9 @@ template <typename F> void dispatch_dim(pff_solver* s, F&& fn) {
 // ---- host-side predictor --------------------------------------------------------
 
 // psi0(+) of a symmetric tensor (3x3, or its in-plane 2x2 block in 2D)
-double psi_plus_host(const double f[9], double lam, double mu, int dim) {
+// history driver of the homogeneous strain f (E = 1): psi0(+) of the split
+// model, or the whole psi0 of the isotropic one
+double psi_plus_host(const double f[9], double lam, double mu, int dim, int iso) {
   double A[3][3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) A[i][j] = 0.5 * (f[3 * i + j] + f[3 * j + i]);
@@ -1151,10 +1153,10 @@ double psi_plus_host(const double f[9], double lam, double mu, int dim) {
   double tr = 0.0, sq = 0.0;
   for (int a = 0; a < D; ++a) {
     tr += A[a][a];
-    const double zp = A[a][a] > 0.0 ? A[a][a] : 0.0;
+    const double zp = (iso || A[a][a] > 0.0) ? A[a][a] : 0.0;
     sq += zp * zp;
   }
-  const double trp = tr > 0.0 ? tr : 0.0;
+  const double trp = (iso || tr > 0.0) ? tr : 0.0;
   return 0.5 * lam * trp * trp + mu * sq;
 }
 
@@ -1198,9 +1200,17 @@ void upload_tables(pff_solver* s, DevTables<T>& t) {
       tw[j] = cpx<T>{T(cosl(ang)), T(sinl(ang))};
       const int m = (2 * j < n) ? j : j - n;      // signed frequency, Nyquist reads -n/2
       const long double half = 3.14159265358979323846264338327950288L * (long double)m / n;
-      hs[j] = T(sinl(half));
-      hc[j] = (n % 2 == 0 && 2 * j == n) ? T(0) : T(cosl(half));
       const long double q = 2.0L * half;
+      const bool nyq = n % 2 == 0 && 2 * j == n;
+      if (s->prm.projection == PFF_PROJ_STANDARD) {
+        // r_j = xi_j: the plain frequency, 0 at the Nyquist index (no sign)
+        hs[j] = nyq ? T(0) : T(q);
+        hc[j] = T(1);
+      } else {
+        // rotated scheme: r_j = sin(q_j/2) prod_{m != j} cos(q_m/2)
+        hs[j] = T(sinl(half));
+        hc[j] = nyq ? T(0) : T(cosl(half));
+      }
       q2[j] = T(q * q);
     }
     t.tw[a] = s->alloc<cpx<T>>(n);
@@ -1311,7 +1321,9 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     const pff_params& p = s->prm;
     if (!(p.l > 0) || !(p.k_resid >= 0) || !(p.delta_a > 0) || !(p.alpha > 0) || p.alpha > 1 ||
         !(p.newton_tol > 0) || !(p.krylov_rtol > 0) || p.newton_maxit < 1 || p.krylov_maxit < 1 ||
-        (p.precision != PFF_PREC_FP64 && p.precision != PFF_PREC_MIXED))
+        (p.precision != PFF_PREC_FP64 && p.precision != PFF_PREC_MIXED) ||
+        (p.split != PFF_SPLIT_SPECTRAL && p.split != PFF_SPLIT_NONE) ||
+        (p.projection != PFF_PROJ_ROTATED && p.projection != PFF_PROJ_STANDARD))
       throw Fail("invalid solver parameters", PFF_ERR_ARG);
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j)
@@ -1326,6 +1338,7 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
       s->fm[3] = r2 * p.f[5]; s->fm[4] = r2 * p.f[2]; s->fm[5] = r2 * p.f[1];
     }
     s->mat.nphase = n_phases;
+    s->mat.iso = p.split == PFF_SPLIT_NONE ? 1 : 0;
     s->phases.assign(phases, phases + n_phases);
     for (int k = 0; k < n_phases; ++k) {
       const double E = phases[k].E, nu = phases[k].nu;
@@ -1445,7 +1458,7 @@ pff_status pff_bootstrap(pff_solver* s, double* a0, double* E_s) {
     s->a = s->hscal[SC_GAMMA];
     // predictor: bisection on the gradient-free homogeneous damage
     std::vector<double> psif(s->mat.nphase), cnt(s->mat.nphase, 0.0);
-    for (int k = 0; k < s->mat.nphase; ++k) psif[k] = psi_plus_host(s->prm.f, s->mat.lam[k], s->mat.mu[k], s->dim);
+    for (int k = 0; k < s->mat.nphase; ++k) psif[k] = psi_plus_host(s->prm.f, s->mat.lam[k], s->mat.mu[k], s->dim, s->mat.iso);
     for (long long i = 0; i < s->N; ++i)
       if (!s->h_mask[i]) cnt[s->h_pid[i]] += 1.0;
     const double l = s->prm.l, da = s->prm.delta_a;

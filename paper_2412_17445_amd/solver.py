@@ -29,8 +29,14 @@ def _torch():
 
 def marshal_problem(shape, phases, phase_id, mask, f, l, k=1e-6, delta_a=1.0, alpha=1.0,
                     newton_tol=1e-8, krylov_rtol=1e-10, newton_maxit=50, krylov_maxit=5000,
-                    precision="fp64"):
-    """C structs and host arrays of one RVE problem (pff_create's inputs)."""
+                    precision="fp64", split="spectral", projection="rotated"):
+    """C structs and host arrays of one RVE problem (pff_create's inputs).
+    split: "spectral" (Miehe split) or "none" (isotropic degradation);
+    projection: "rotated" (Willot) or "standard" frequencies in G."""
+    if split not in ("spectral", "none"):
+        raise ValueError("split must be 'spectral' or 'none'")
+    if projection not in ("rotated", "standard"):
+        raise ValueError("projection must be 'rotated' or 'standard'")
     nz, ny, nx = shape
     grid = L.pff_grid(nx, ny, nz)
     ph = (L.pff_phase * len(phases))(*[L.pff_phase(*map(float, p)) for p in phases])
@@ -47,6 +53,8 @@ def marshal_problem(shape, phases, phase_id, mask, f, l, k=1e-6, delta_a=1.0, al
     prm.newton_tol, prm.krylov_rtol = float(newton_tol), float(krylov_rtol)
     prm.newton_maxit, prm.krylov_maxit = int(newton_maxit), int(krylov_maxit)
     prm.precision = L.PFF_PREC_MIXED if precision == "mixed" else L.PFF_PREC_FP64
+    prm.split = L.PFF_SPLIT_NONE if split == "none" else L.PFF_SPLIT_SPECTRAL
+    prm.projection = L.PFF_PROJ_STANDARD if projection == "standard" else L.PFF_PROJ_ROTATED
     return grid, ph, pid, msk, prm
 
 
@@ -55,7 +63,8 @@ def problem_kwargs(prob, **over):
               f=prob.f, l=prob.l, k=prob.k, delta_a=prob.delta_a, alpha=prob.alpha,
               newton_tol=prob.newton_tol, krylov_rtol=prob.krylov_rtol,
               newton_maxit=prob.newton_maxit, krylov_maxit=prob.krylov_maxit,
-              precision=prob.precision)
+              precision=prob.precision, split=getattr(prob, "split", "spectral"),
+              projection=getattr(prob, "projection", "rotated"))
     kw.update(over)
     return kw
 
@@ -73,7 +82,7 @@ class Solver:
 
     def __init__(self, shape, phases, phase_id, mask, f, l, k=1e-6, delta_a=1.0, alpha=1.0,
                  newton_tol=1e-8, krylov_rtol=1e-10, newton_maxit=50, krylov_maxit=5000,
-                 precision="fp64", stream=None):
+                 precision="fp64", split="spectral", projection="rotated", stream=None):
         torch = _torch()
         self.lib = L.load()
         nz, ny, nx = shape
@@ -86,7 +95,7 @@ class Solver:
         grid, ph, pid, msk, prm = marshal_problem(
             shape, phases, phase_id, mask, f, l, k=k, delta_a=delta_a, alpha=alpha,
             newton_tol=newton_tol, krylov_rtol=krylov_rtol, newton_maxit=newton_maxit,
-            krylov_maxit=krylov_maxit, precision=precision)
+            krylov_maxit=krylov_maxit, precision=precision, split=split, projection=projection)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self._stream = stream
@@ -102,7 +111,9 @@ class Solver:
     def from_problem(cls, prob, **over):
         kw = dict(k=prob.k, delta_a=prob.delta_a, alpha=prob.alpha, newton_tol=prob.newton_tol,
                   krylov_rtol=prob.krylov_rtol, newton_maxit=prob.newton_maxit,
-                  krylov_maxit=prob.krylov_maxit, precision=prob.precision)
+                  krylov_maxit=prob.krylov_maxit, precision=prob.precision,
+                  split=getattr(prob, "split", "spectral"),
+                  projection=getattr(prob, "projection", "rotated"))
         kw.update(over)
         return cls(prob.shape, prob.phases, prob.phase_id, prob.mask, prob.f, prob.l, **kw)
 

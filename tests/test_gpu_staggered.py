@@ -107,6 +107,37 @@ def test_homogeneous_work_equals_energy_plus_dissipation():
     s.close()
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("split", ["spectral", "none"])
+def test_homogeneous_compression(split):
+    """Uniaxial plane-strain compression: no driving energy under the split,
+    psi0 = (lambda/2 + mu) E^2 without it (isotropic model, closed form)."""
+    from synth.configs import Problem, _dyad
+    n = 8
+    Ey, nu, Gc, l, k = 1.0, 0.3, 1e-3, 2.0, 1e-6
+    prob = Problem(name="hom", shape=(1, n, n), phases=[(Ey, nu, Gc)],
+                   phase_id=np.zeros((1, n, n), np.uint8), mask=None, f=_dyad(1, 1), l=l, k=k,
+                   split=split)
+    lam = Ey * nu / ((1 + nu) * (1 - 2 * nu))
+    mu = Ey / (2 * (1 + nu))
+    s = _solver(prob)
+    for _ in range(3):
+        out = s.stagger_step(-0.02)
+        assert out["converged"]
+        E = out["E"]
+        H = (0.5 * lam + mu) * E * E if split == "none" else 0.0
+        phi = 2 * H / (Gc / l + 2 * H)
+        g = (1 - phi) ** 2 + k if split == "none" else 1.0
+        _, ph, Hn, _, _ = s.get_state()
+        assert np.abs(ph - phi).max() <= 1e-9 * max(phi, 1e-9)      # round-off of a zero field
+        assert np.abs(Hn - H).max() <= 1e-12 * max(H, 1e-12)
+        sig = out["sigma_M"]
+        ref = [g * lam * E, g * (lam + 2 * mu) * E, g * lam * E]
+        for q in range(3):
+            assert abs(sig[q] - ref[q]) <= 1e-9 * abs(ref[q]), (split, q, sig[q], ref[q])
+    s.close()
+
+
 def _check_increment(out, ref, tol):
     assert out["converged"], out
     assert out["E"] == pytest.approx(ref["E"], rel=1e-14)
