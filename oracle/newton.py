@@ -21,6 +21,12 @@ Readings (see also `system`):
   with phi_loc = 2 psi0(+)(f E) / (Gc/l + 2 psi0(+)(f E)), using
   psi0(+)(f E) = E^2 psi0(+)(f); the guess is eps = f E_s,
   phi = max(phi0, (1-m) phi_loc(E_s)), E = E_s > 0.
+* Weighted control (FFT analogue of eq. `FEMweights`): the constraint is
+  w_a Gamma + w_E E = tau with tau raised by `delta_a` per increment; the
+  weights (1, 0) give crack-length control, (0, 1) monolithic strain
+  control, which can start an uncracked cell from phi = 0.  tau0 =
+  w_a Gamma(phi0), the convergence measure is |w_a Gamma + w_E E - tau| /
+  |tau|, and the predictor solves w_a S(E) + w_E E = delta_a.
 """
 
 from __future__ import annotations
@@ -79,7 +85,8 @@ class Solver:
     def predictor(self, delta_a):
         s = self.sys
         psif = self.psi_f()
-        S = lambda E: float(np.sum((1 - s.m) * self.local_damage(E, psif) ** 2)) / (2 * s.l)  # noqa: E731
+        S0 = lambda E: float(np.sum((1 - s.m) * self.local_damage(E, psif) ** 2)) / (2 * s.l)  # noqa: E731
+        S = lambda E: s.wa * S0(E) + s.wE * E                                   # noqa: E731
         lo, hi = 0.0, 1.0
         while S(hi) < delta_a:
             hi *= 2.0
@@ -97,7 +104,7 @@ class Solver:
         s = self.sys
         phi0, _ = self.initial_damage()
         self.phi = phi0
-        self.a = s.gamma(phi0)
+        self.a = s.wa * s.gamma(phi0)
         Es, psif = self.predictor(self.delta_a)
         self.guess = (np.zeros_like(self.eps_t),
                       np.maximum(phi0, (1 - s.m) * self.local_damage(Es, psif)), Es)
@@ -127,7 +134,7 @@ class Solver:
             gam = s.gamma(phi)
             errs = (np.linalg.norm(w) / np.linalg.norm(eps),
                     np.linalg.norm(d_phi) / np.linalg.norm(phi),
-                    abs(gam - a) / abs(a))
+                    abs(s.wa * gam + s.wE * E - a) / abs(a))
             err = max(errs)
             if err <= self.tol:
                 return eps_t, phi, E, dict(converged=True, newton_iters=it,

@@ -50,6 +50,9 @@ class System:
         self.k = float(prob.k)
         self.iso = getattr(prob, "split", "spectral") == "none"
         self.scheme = getattr(prob, "projection", "rotated")
+        # control F3 = w_a Gamma + w_E E - tau (eq. `FEMweights`, FFT analogue);
+        # (1, 0) is the crack-length control of eq. `System_CrackLength`
+        self.wa, self.wE = (float(w) for w in getattr(prob, "control_weights", (1.0, 0.0)))
         self.f = fo.to_mandel(np.asarray(prob.f, dtype=np.float64)[:, :, None, None, None],
                               self.ncomp)[:, 0, 0, 0]
 
@@ -80,7 +83,7 @@ class System:
         l, Gc, H = self.l, self.Gc, st["H"]
         F2 = (1.0 - self.m) * ((Gc / l + 2.0 * H) * phi - Gc * l * lap - 2.0 * H)
         gam = float(np.sum(phi * phi / (2.0 * l) - 0.5 * l * phi * lap))
-        F3 = gam - a
+        F3 = self.wa * gam + self.wE * E - a
         sig_mean = st["sigma"].reshape(3, 3, -1).mean(axis=-1)
         return dict(F1=F1, F2=F2, F3=F3, Gamma=gam, sigma_M=sig_mean, state=st,
                     r=phi / l - l * lap)
@@ -107,7 +110,7 @@ class System:
             bw = np.einsum("ij...,ij...->...", b, w)
             J2 = (1.0 - m) * (st["chi"] * bw + A * dphi_f
                               - Gc * l * fo.laplacian(dphi_f)) + m * d_phi
-            J3 = np.sum(r * dphi_f)
+            J3 = self.wa * np.sum(r * dphi_f) + self.wE * dE
             return np.concatenate([J1.ravel(), J2.ravel(), [J3]])
 
         return apply

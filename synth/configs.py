@@ -51,6 +51,7 @@ class Problem:
     precision: str = "fp64"              # "fp64" or "mixed"
     split: str = "spectral"              # "spectral" (Miehe split) or "none" (isotropic degradation)
     projection: str = "rotated"          # "rotated" (Willot) or "standard" frequencies in G
+    control_weights: Tuple[float, float] = (1.0, 0.0)   # (w_a, w_E): F3 = w_a Gamma + w_E E - tau
     notes: str = ""
     extra: dict = field(default_factory=dict)
 
