@@ -86,10 +86,17 @@ typedef struct {
  *  projection   PFF_PROJ_ROTATED (0): G built with Willot's rotated
  *               frequencies (Sec. 3.1); PFF_PROJ_STANDARD (1): the plain
  *               Fourier frequencies of eq. GFourier, with xi_j = 0 at an
- *               even axis' Nyquist index (its sign is undefined) */
+ *               even axis' Nyquist index (its sign is undefined)
+ *  w_gamma,     weights of the controlled quantity tau = w_gamma Gamma +
+ *  w_load       w_load E (an FFT analogue of eq. FEMweights): F3 = tau(phi,
+ *               E) - tau_n, raised by delta_a per increment.  (1, 0) is the
+ *               crack-length control of eq. System_CrackLength and is taken
+ *               when both are 0; (0, 1) is monolithic strain control, which
+ *               can start an uncracked cell.  Both >= 0. */
 typedef struct {
   double l, k_resid, f[9], delta_a, alpha, newton_tol, krylov_rtol;
   int newton_maxit, krylov_maxit, precision, split, projection;
+  double w_gamma, w_load;
 } pff_params;
 
 enum { PFF_SPLIT_SPECTRAL = 0, PFF_SPLIT_NONE = 1 };
@@ -124,8 +131,11 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
                       const pff_params* params, void* hip_stream, pff_solver** out);
 
 /* Bootstrap (the paper is silent on the start of the path): damage-free Helmholtz
- * solution phi0 with phi = 1 on the crack mask, a0 = Gamma(phi0), and the
- * homogeneous-solution predictor E_s for the first increment.
+ * solution phi0 with phi = 1 on the crack mask, the control value a0 =
+ * w_gamma Gamma(phi0) (= Gamma(phi0) for crack-length control), and the
+ * homogeneous-solution predictor E_s for the first increment (root of
+ * w_gamma S(E) + w_load E = delta_a, S the crack length of the
+ * gradient-free homogeneous damage).
  * Outputs (host, may be NULL): a0, E_s. */
 pff_status pff_bootstrap(pff_solver* s, double* a0, double* E_s);
 

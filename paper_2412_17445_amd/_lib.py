@@ -32,7 +32,7 @@ class pff_params(C.Structure):
                 ("delta_a", C.c_double), ("alpha", C.c_double), ("newton_tol", C.c_double),
                 ("krylov_rtol", C.c_double), ("newton_maxit", C.c_int),
                 ("krylov_maxit", C.c_int), ("precision", C.c_int), ("split", C.c_int),
-                ("projection", C.c_int)]
+                ("projection", C.c_int), ("w_gamma", C.c_double), ("w_load", C.c_double)]
 
 
 class pff_increment_result(C.Structure):

@@ -271,12 +271,13 @@ struct FinRR {      // ||r||^2 and the next rho, beta
 // voxel part of the inner products); writes J u and the updated vector at
 // their trailing entries, adds the trailing terms to the inner products and
 // forms alpha (mode 1) or omega (mode 2) with the breakdown flags.
-// vout_last and dv_last are the same entry in mode 2 (no __restrict__).
+// vout_last and dv_last are the same entry in mode 2, and in_last may be
+// either of them (no __restrict__).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fin_fused(const double* __restrict__ part0,
                                                       const double* __restrict__ part1, int nblk, int mode,
                                                       int pro, T* Jv_last, T* vout_last, const T* dv_last,
-                                                      double* ks) {
+                                                      const T* in_last, double wa, double wE, double* ks) {
   __shared__ double lds[kBlock];
   __shared__ double tot[3];
   const double* src[3] = {part0, part1, part1 + nblk};
@@ -293,7 +294,9 @@ __global__ void __launch_bounds__(kBlock) k_fin_fused(const double* __restrict__
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
-  const T j3 = T(tot[0]);
+  // border row J3 = w_a (r, d phi) + w_E dE, dE the trailing entry of the input
+  const double din = pro ? ks[KS_ULAST] : double(*in_last);
+  const T j3 = T(wa * tot[0] + wE * din);
   // mode 1 pairs J u with r_hat; mode 2 with u itself, whose trailing entry
   // the prologue formed (pro) or the caller holds in dv
   T dlast;
@@ -329,9 +332,11 @@ __global__ void __launch_bounds__(kBlock) k_fin_fused(const double* __restrict__
 }
 
 template <typename T>
-struct FinLast {    // write the reduced total into the trailing entry of a vector
-  struct Args { T* dst; };
-  __device__ static void run(const Args& F, const double* tot) { *F.dst = T(tot[0]); }
+struct FinLast {    // border row: J3 = w_a (r, d phi) + w_E dE into the trailing entry
+  struct Args { T* dst; double wa, wE; const T* vlast; };
+  __device__ static void run(const Args& F, const double* tot) {
+    *F.dst = T(F.wa * tot[0] + F.wE * double(*F.vlast));
+  }
 };
 
 }  // namespace pff

@@ -60,7 +60,8 @@ enum {
   SC_NW = 9, SC_NEPS = 10, SC_NDPHI = 11, SC_NPHI = 12,
   SC_ETA = 13,     // 2 slots: ||b - J x||^2, ||b||^2 of the FP64 check
   SC_DISS = 15,    // dissipation: sum of Gc gamma_f
-  SC_CG = 16,      // CG scratch; staggered scheme: [17] max |d eps~|, [18..21] stagger norms
+  SC_F3 = 24,      // constraint residual F3 = w_a Gamma + w_E E - tau
+  SC_CG = 16,      // CG scratch (16..23); staggered scheme: [17] max |d eps~|, [18..21] stagger norms
   SC_KS = 32,      // Krylov scalars
   SC_COUNT = 64
 };
@@ -156,7 +157,8 @@ struct pff_solver {
   double tim_ms[kTimSlots] = {};
   long long tim_n[kTimSlots] = {};
   int n = 0;
-  double a = 0.0, E = 0.0, E_s = 0.0;
+  double a = 0.0, E = 0.0, E_s = 0.0;   // a: control value tau
+  double wa = 1.0, wE = 0.0;              // control weights (tau = wa Gamma + wE E)
   long long applies = 0, kiters = 0;
   std::string err;
 
@@ -528,15 +530,25 @@ struct FinNewton {
 };
 
 struct FinResid {
-  struct Args { double* scal; double a; double* rhs_last; float* rhs32_last; double* F_last; };
+  struct Args {
+    double* scal;
+    double a;              // control value tau
+    double wa, wE;         // F3 = w_a Gamma + w_E E - tau
+    const double* E;
+    double* rhs_last;
+    float* rhs32_last;
+    double* F_last;
+  };
   __device__ static void run(const Args& F, const double* tot) {
+    const double f3 = F.wa * tot[0] + F.wE * F.E[0] - F.a;
     F.scal[SC_GAMMA] = tot[0];
     F.scal[SC_F1] = tot[1];
     F.scal[SC_F2] = tot[2];
     F.scal[SC_DISS] = tot[3];
-    F.rhs_last[0] = F.a - tot[0];
-    if (F.rhs32_last) F.rhs32_last[0] = float(F.a - tot[0]);
-    if (F.F_last) F.F_last[0] = tot[0] - F.a;
+    F.scal[SC_F3] = f3;
+    F.rhs_last[0] = -f3;
+    if (F.rhs32_last) F.rhs32_last[0] = float(-f3);
+    if (F.F_last) F.F_last[0] = f3;
   }
 };
 
@@ -585,7 +597,8 @@ struct Impl {
     run_pipeline<TangentPipe<TW, DIM>>(s, A, nblk, ev);
     const long long last = (long long)(C + 1) * s->N;
     k_fin_fused<TW><<<1, kBlock, 0, s->stream>>>(s->part0, s->part1, nblk, mode, pro, Jv + last,
-                                                 pro ? vout + last : nullptr, dv + last, s->scal + SC_KS);
+                                                 pro ? vout + last : nullptr, dv + last, v + last, s->wa,
+                                                 s->wE, s->scal + SC_KS);
     LAUNCH_CHECK();
     s->applies++;
     if (std::is_same<TW, double>::value) s->applies64++;
@@ -606,7 +619,8 @@ struct Impl {
     const int grp = 5 * (std::is_same<TW, float>::value ? 1 : 0);
     hipEvent_t* ev = (s->tim_every > 0 && s->applies % s->tim_every == 0) ? timing_acquire(s, grp) : nullptr;
     run_pipeline<TangentPipe<TW, DIM>>(s, A, nblk, ev);
-    typename FinLast<TW>::Args F{Jv + (long long)(C + 1) * s->N};
+    const long long last = (long long)(C + 1) * s->N;
+    typename FinLast<TW>::Args F{Jv + last, s->wa, s->wE, v + last};
     k_reduce<FinLast<TW>><<<1, kBlock, 0, s->stream>>>(s->part0, nblk, 1, F);
     LAUNCH_CHECK();
     s->applies++;
@@ -652,7 +666,7 @@ struct Impl {
     k_reduce<FinStore><<<1, kBlock, 0, s->stream>>>(s->part0, nblk, 6, fs);
     LAUNCH_CHECK();
     const long long last = (long long)(C + 1) * s->N;
-    FinResid::Args fr{s->scal, a, vecs<double>(s, RHS) + last,
+    FinResid::Args fr{s->scal, a, s->wa, s->wE, s->Edev, vecs<double>(s, RHS) + last,
                       s->kv32[RHS] ? s->kv32[RHS] + last : nullptr, F_dev ? F_dev + last : nullptr};
     k_reduce<FinResid><<<1, kBlock, 0, s->stream>>>(s->part1, nblk, 4, fr);
     LAUNCH_CHECK();
@@ -1323,8 +1337,16 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
         !(p.newton_tol > 0) || !(p.krylov_rtol > 0) || p.newton_maxit < 1 || p.krylov_maxit < 1 ||
         (p.precision != PFF_PREC_FP64 && p.precision != PFF_PREC_MIXED) ||
         (p.split != PFF_SPLIT_SPECTRAL && p.split != PFF_SPLIT_NONE) ||
-        (p.projection != PFF_PROJ_ROTATED && p.projection != PFF_PROJ_STANDARD))
+        (p.projection != PFF_PROJ_ROTATED && p.projection != PFF_PROJ_STANDARD) ||
+        !(p.w_gamma >= 0) || !(p.w_load >= 0) || !std::isfinite(p.w_gamma) || !std::isfinite(p.w_load))
       throw Fail("invalid solver parameters", PFF_ERR_ARG);
+    if (p.w_gamma == 0.0 && p.w_load == 0.0) {
+      s->wa = 1.0;                                    // crack-length control
+      s->wE = 0.0;
+    } else {
+      s->wa = p.w_gamma;
+      s->wE = p.w_load;
+    }
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j)
         if (p.f[3 * i + j] != p.f[3 * j + i]) throw Fail("f must be symmetric", PFF_ERR_ARG);
@@ -1455,7 +1477,7 @@ pff_status pff_bootstrap(pff_solver* s, double* a0, double* E_s) {
       I::residual(s, 0.0, nullptr);
       sync_scal(s);
     });
-    s->a = s->hscal[SC_GAMMA];
+    s->a = s->wa * s->hscal[SC_GAMMA];          // tau0 (E = 0)
     // predictor: bisection on the gradient-free homogeneous damage
     std::vector<double> psif(s->mat.nphase), cnt(s->mat.nphase, 0.0);
     for (int k = 0; k < s->mat.nphase; ++k) psif[k] = psi_plus_host(s->prm.f, s->mat.lam[k], s->mat.mu[k], s->dim, s->mat.iso);
@@ -1466,13 +1488,13 @@ pff_status pff_bootstrap(pff_solver* s, double* a0, double* E_s) {
       const double h = 2.0 * E * E * psif[k];
       return h / (s->mat.Gc[k] / l + h);
     };
-    auto S = [&](double E) {
+    auto S = [&](double E) {      // control value gained by the homogeneous solution at E
       double acc = 0.0;
       for (int k = 0; k < s->mat.nphase; ++k) {
         const double p = loc(E, k);
         acc += cnt[k] * p * p;
       }
-      return acc / (2.0 * l);
+      return s->wa * acc / (2.0 * l) + s->wE * E;
     };
     double lo = 0.0, hi = 1.0;
     while (S(hi) < da) {
@@ -1537,7 +1559,7 @@ pff_status pff_step(pff_solver* s, pff_increment_result* out) {
       if (trace) {
         sync_scal(s);
         std::fprintf(stderr, "[pff] inc %d start |F1|=%.6e |F2|=%.6e F3=%.6e\n", s->n + 1,
-                     std::sqrt(s->hscal[SC_F1]), std::sqrt(s->hscal[SC_F2]), s->hscal[SC_GAMMA] - a_new);
+                     std::sqrt(s->hscal[SC_F1]), std::sqrt(s->hscal[SC_F2]), s->hscal[SC_F3]);
       }
       for (it = 1; it <= s->prm.newton_maxit; ++it) {
         int kit = 0;
@@ -1553,11 +1575,11 @@ pff_status pff_step(pff_solver* s, pff_increment_result* out) {
                        "[pff] inc %d it %d krylov %d relres %.2e | E=%.12e |F1|=%.6e |F2|=%.6e F3=%.6e "
                        "|w|/|eps|=%.2e |dphi|/|phi|=%.2e\n",
                        s->n + 1, it, kit, rr, s->hstage[0], std::sqrt(h[SC_F1]), std::sqrt(h[SC_F2]),
-                       h[SC_GAMMA] - a_new, std::sqrt(h[SC_NW] / h[SC_NEPS]), std::sqrt(h[SC_NDPHI] / h[SC_NPHI]));
+                       h[SC_F3], std::sqrt(h[SC_NW] / h[SC_NEPS]), std::sqrt(h[SC_NDPHI] / h[SC_NPHI]));
         }
         err[0] = std::sqrt(h[SC_NW]) / std::sqrt(h[SC_NEPS]);
         err[1] = std::sqrt(h[SC_NDPHI]) / std::sqrt(h[SC_NPHI]);
-        err[2] = std::fabs(h[SC_GAMMA] - a_new) / std::fabs(a_new);
+        err[2] = std::fabs(h[SC_F3]) / std::fabs(a_new);
         const double e = std::max(err[0], std::max(err[1], err[2]));
         if (e <= s->prm.newton_tol) {
           conv = 1;
@@ -1686,7 +1708,7 @@ pff_status pff_stagger_step(pff_solver* s, double dE, const pff_stagger_params* 
     HC(hipMemcpyAsync(s->phi_c, s->phi, N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
     HC(hipStreamSynchronize(s->stream));
     s->E = E;
-    s->a = s->hscal[SC_GAMMA];
+    s->a = s->wa * s->hscal[SC_GAMMA] + s->wE * E;   // the control value of this state
     s->n += 1;
     s->ts_valid = false;
     if (out) {

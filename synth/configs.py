@@ -70,8 +70,14 @@ CONFIG_NAMES = ("crack2d_64", "fibres2d_256", "pores3d_64",
 
 def problem_config(name: str) -> Problem:
     """Return the seeded problem called `name` (benchmark or parity case).
-    A suffix "_iso" gives the same problem with the isotropic (no split)
-    degradation of Sec. 5.4."""
+    Suffixes: "_iso" gives the same problem with the isotropic (no split)
+    degradation of Sec. 5.4, "_std" with the standard-frequency projection,
+    "_w" with the weighted control 0.7 Gamma + 3 E."""
+    if name.endswith("_w"):
+        prob = problem_config(name[:-2])
+        prob.name, prob.control_weights = name, (0.7, 3.0)
+        prob.notes = (prob.notes + "; " if prob.notes else "") + "weighted control 0.7 Gamma + 3 E"
+        return prob
     if name.endswith("_std"):
         prob = problem_config(name[:-4])
         prob.name, prob.projection = name, "standard"

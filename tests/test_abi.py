@@ -40,8 +40,8 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts():
     assert C.sizeof(L.pff_grid) == 12
     assert C.sizeof(L.pff_phase) == 24
-    # 2 doubles + f[9] + 4 doubles, then 5 ints (+ padding)
-    assert C.sizeof(L.pff_params) == 8 * (2 + 9 + 4) + 4 * 5 + 4
+    # 2 doubles + f[9] + 4 doubles, 5 ints (+ padding), 2 doubles
+    assert C.sizeof(L.pff_params) == 8 * (2 + 9 + 4) + 4 * 5 + 4 + 8 * 2
     assert C.sizeof(L.pff_increment_result) == 4 * 4 + 8 * 2 + 4 * 2 + 8 * (6 + 3 + 3 + 2)
 
 

@@ -136,7 +136,8 @@ def _frozen_state(sysm, seed):
 
 
 @pytest.mark.parametrize("name,shape", SHAPES + [("gc16_iso", None), ("part24_iso", (12, 18, 16)),
-                                              ("tiny16_std", (1, 12, 18)), ("part24_std", (12, 18, 16))])
+                                              ("tiny16_std", (1, 12, 18)), ("part24_std", (12, 18, 16)),
+                                              ("gc16_w", None), ("part24_w", (9, 8, 6))])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_residual_and_tangent(name, shape, precision):
     prob = small_problem(name, shape, precision)
@@ -168,7 +169,8 @@ def test_residual_and_tangent(name, shape, precision):
     for blk in (slice(0, c * N), slice(c * N, (c + 1) * N)):
         assert rel(Jv[blk], ref[blk]) < tol
     r = phi / sysm.l - sysm.l * fo.laplacian(phi)
-    scale = np.sum(np.abs(r * (1 - sysm.m) * v[c * N:(c + 1) * N].reshape(sysm.shape)))
+    scale = sysm.wa * np.sum(np.abs(r * (1 - sysm.m) * v[c * N:(c + 1) * N].reshape(sysm.shape))) \
+        + sysm.wE * abs(v[-1])
     assert abs(Jv[-1] - ref[-1]) <= tol * scale
     s.close()
 
