@@ -57,8 +57,9 @@ enum { PFF_PREC_FP64 = 0, PFF_PREC_MIXED = 1 };
 
 typedef struct pff_solver pff_solver;
 
-/* Voxel grid. nx, ny >= 2 and nz >= 1; each size a product of 2s and 3s,
- * at most 512 (x) / 512 (y, z). */
+/* Voxel grid. nx, ny >= 2 and nz >= 1, each at most 512.  Lengths with
+ * prime factors other than 2 and 3 are allowed: such a factor p takes a
+ * generic-radix FFT stage with O(p) work per element. */
 typedef struct {
   int nx, ny, nz;
 } pff_grid;

@@ -4,7 +4,10 @@
 // product of the radices already applied, butterfly j of a radix-R stage
 // reads the R inputs j + r*n/R, multiplies input r by w_{Ns*R}^{r*(j mod Ns)},
 // applies an R-point DFT and writes output r to (j div Ns)*Ns*R + j mod Ns +
-// r*Ns.  Radices 2, 3, 4 and 8 cover every length 2^a 3^b.  S = -1 is the
+// r*Ns.  Radices 2, 3, 4 and 8 have unrolled butterflies; every other
+// prime factor p of the length runs a stage of radix p in which each item
+// computes one output element from its p inputs (O(p) work per element), so
+// any length up to the tile limit is covered.  S = -1 is the
 // forward transform (exp(-2 pi i jk/n), the numpy convention), S = +1 the
 // unnormalised inverse.  The caller scales by 1/N elsewhere.
 //
@@ -128,6 +131,57 @@ __device__ __forceinline__ void stockham_stage(cpx<T>* buf, int n, int Ns, int n
   __syncthreads();
 }
 
+// Stage of any radix R, one output element per item: output o of the stage
+// (o = (j div Ns) Ns R + j mod Ns + r Ns) sums its R inputs j + m n/R times
+// w_{Ns R}^{m (j mod Ns)} w_R^{m r}, one table lookup per term (both factors
+// are powers of w_n: tw[(m (j mod Ns) n/(Ns R) + (m r mod R) n/R) mod n]).
+// All items read before the barrier and write their own element after it.
+template <typename T, int S, int MAXE>
+__device__ __forceinline__ void stockham_stage_any(cpx<T>* buf, int n, int R, int Ns, int nseq, int ltx,
+                                                const cpx<T>* tw) {
+  const int TX = 1 << ltx;
+  const int total = (n * nseq) << ltx;
+  const int nb = n / R;
+  const int twstep = n / (Ns * R);
+  cpx<T> out[MAXE];
+#pragma unroll
+  for (int q = 0; q < MAXE; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    if (idx < total) {
+      const int t = idx & (TX - 1);
+      const int rest = idx >> ltx;
+      const int sq = rest / n;
+      const int o = rest - sq * n;                  // output position in the sequence
+      const int kk = o % Ns;
+      const int r = (o / Ns) % R;
+      const int j = (o / (Ns * R)) * Ns + kk;       // butterfly index
+      const cpx<T>* in = buf + (sq * n + j) * TX + t;
+      const int d1 = kk * twstep;                   // m kk twstep < n for every m < R
+      const int d2 = r * nb;                        // (m r mod R) nb = m r nb mod n
+      int e1 = 0, e2 = 0;
+      cpx<T> acc = {T(0), T(0)};
+      for (int m = 0; m < R; ++m) {
+        int e = e1 + e2;
+        if (e >= n) e -= n;
+        cpx<T> w = tw[e];
+        if (S > 0) w.y = -w.y;
+        acc = cadd(acc, cmul(in[m * nb * TX], w));
+        e1 += d1;
+        e2 += d2;
+        if (e2 >= n) e2 -= n;
+      }
+      out[q] = acc;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXE; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    if (idx < total) buf[idx] = out[q];           // element idx is the item's own output
+  }
+  __syncthreads();
+}
+
 // ---- lengths known at compile time ----------------------------------------
 // The radix sequence of factor23 (8s, then one 4 or 2, then 3s), as constexpr.
 constexpr int c_pow2(int n) { return n % 2 == 0 ? 1 + c_pow2(n / 2) : 0; }
@@ -203,9 +257,12 @@ __device__ __forceinline__ void fft_c(cpx<T>* buf, int nseq, int ltx, const cpx<
 // In-place transform of nseq sequences (times TX = 2^ltx interleaved
 // columns) of length pl.n held in buf; tw is the LDS twiddle table
 // exp(-2 pi i k/n).  Lengths 32..512 (powers of two) take the compile-time
-// path, every other 3-smooth length the generic one.
+// path, every other length the generic one.
 // Must be called by every thread of the block; ends with a barrier.
-template <typename T, int S, int MAXE>
+// ANY: the kernel may meet radices other than 2, 3, 4 and 8 (generic stage
+// compiled in).  Kernels of 2^a 3^b grids are instantiated without it, so the
+// generic stage's registers do not count against their occupancy.
+template <typename T, int S, int MAXE, bool ANY = false>
 __device__ void fft_lds(cpx<T>* buf, int nseq, int ltx, const AxisPlan& pl, const cpx<T>* tw) {
   switch (pl.n) {
     case 32: fft_c<T, S, 32, 0, 1, MAXE>(buf, nseq, ltx, tw); return;
@@ -223,7 +280,8 @@ __device__ void fft_lds(cpx<T>* buf, int nseq, int ltx, const AxisPlan& pl, cons
     if (R == 8) stockham_stage<T, S, 8, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
     else if (R == 4) stockham_stage<T, S, 4, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
     else if (R == 3) stockham_stage<T, S, 3, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
-    else stockham_stage<T, S, 2, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
+    else if (R == 2) stockham_stage<T, S, 2, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
+    else if constexpr (ANY) stockham_stage_any<T, S, MAXE>(buf, pl.n, R, Ns, nseq, ltx, tw);
     Ns *= R;
   }
 }

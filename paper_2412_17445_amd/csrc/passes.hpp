@@ -34,7 +34,7 @@ template <typename T> struct SpecTables {
 // Max LDS elements per thread of the in-place FFT (64 KB per block).
 template <typename T> struct FftCap { static constexpr int MAXE = 8; };
 
-template <class P>
+template <class P, bool ANY>
 __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xfwd(const typename P::Args A, const AxisPlan pl,
                                                  const cpx<typename P::real>* __restrict__ tw_g,
                                                  cpx<typename P::real>* __restrict__ spec,
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xfwd(co
     for (int p = 0; p < NP; ++p) bufa[(r * NP + p) * nx + x] = cpx<T>{vals[2 * p], vals[2 * p + 1]};
   }
   __syncthreads();
-  fft_lds<T, -1, FftCap<T>::MAXE>(bufa, RB * NP, 0, pl, tw);
+  fft_lds<T, -1, FftCap<T>::MAXE, ANY>(bufa, RB * NP, 0, pl, tw);
   const cpx<T>* res = bufa;
   const long long Nh = A.g.Nh;
   const int nxm = A.g.nxm;
@@ -118,7 +118,7 @@ constexpr int kXcds = 8;   // MI355X: workgroups are dispatched round-robin over
 // transform along the same axis follow.  With remap, consecutive tiles are
 // given to workgroups on the same XCD, so that two tiles sharing 128-byte
 // lines meet in that XCD's L2.
-template <class P, int S, bool SPECTRAL>
+template <class P, int S, bool SPECTRAL, bool ANY>
 __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_axis(const typename P::Args A, const AxisPlan pl,
                                                  const cpx<typename P::real>* __restrict__ tw_g,
                                                  cpx<typename P::real>* __restrict__ spec, int axis,
@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_axis(co
     }
   }
   __syncthreads();
-  fft_lds<T, S, MAXE>(buf, nfb, ltx, pl, tw);
+  fft_lds<T, S, MAXE, ANY>(buf, nfb, ltx, pl, tw);
   if constexpr (SPECTRAL) {
     for (int idx = threadIdx.x; idx < per_field; idx += blockDim.x) {
       const int t = idx & (TX - 1), j = idx >> ltx;
@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_axis(co
       for (int f = 0; f < NF; ++f) buf[f * per_field + idx] = v[f];
     }
     __syncthreads();
-    fft_lds<T, -S, MAXE>(buf, nfb, ltx, pl, tw);
+    fft_lds<T, -S, MAXE, ANY>(buf, nfb, ltx, pl, tw);
   }
   for (int f = 0; f < nfb; ++f) {
     cpx<T>* dst = spec + (long long)(f0 + f) * g.Nh + off0;
@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_axis(co
   }
 }
 
-template <class P>
+template <class P, bool ANY>
 __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xinv(const typename P::Args A, const AxisPlan pl,
                                                  const cpx<typename P::real>* __restrict__ tw_g,
                                                  const cpx<typename P::real>* __restrict__ spec,
@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xinv(co
     }
   }
   __syncthreads();
-  fft_lds<T, 1, FftCap<T>::MAXE>(bufa, RB * NP, 0, pl, tw);
+  fft_lds<T, 1, FftCap<T>::MAXE, ANY>(bufa, RB * NP, 0, pl, tw);
   const cpx<T>* res = bufa;
   double red[NR > 0 ? NR : 1];
 #pragma unroll

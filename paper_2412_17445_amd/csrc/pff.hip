@@ -66,17 +66,27 @@ enum {
   SC_COUNT = 64
 };
 
-bool factor23(int n, AxisPlan& pl) {
+// Stage plan of one axis: radix 8 stages, then one 4 or 2, then 3s (all with
+// unrolled butterflies), then every other prime factor in ascending order
+// (generic radix stage).
+bool make_plan(int n, AxisPlan& pl) {
+  if (n < 1 || n > 512) return false;
   pl.n = n;
   pl.nstage = 0;
   int a = 0, b = 0, m = n;
   while (m % 2 == 0) { m /= 2; ++a; }
   while (m % 3 == 0) { m /= 3; ++b; }
-  if (m != 1) return false;
   while (a >= 3) { pl.radix[pl.nstage++] = 8; a -= 3; }
   if (a == 2) pl.radix[pl.nstage++] = 4;
   else if (a == 1) pl.radix[pl.nstage++] = 2;
   for (int i = 0; i < b; ++i) pl.radix[pl.nstage++] = 3;
+  for (int p = 5; m > 1; p += 2) {
+    while (m % p == 0) {
+      if (pl.nstage >= kMaxStages) return false;
+      pl.radix[pl.nstage++] = p;
+      m /= p;
+    }
+  }
   if (pl.nstage > kMaxStages) return false;
   pl.dn = make_fastdiv((uint32_t)n);
   int Ns = 1;
@@ -110,6 +120,7 @@ struct pff_solver {
   hipStream_t stream = nullptr;
   GridDesc g{};
   AxisPlan plan[3]{};
+  bool plan_any = false;    // some axis has a prime factor above 3 (generic FFT stages)
   DevTables<double> td;
   DevTables<float> tf;
   // device memory
@@ -258,8 +269,8 @@ size_t lds_axis(int n, int nfb, int tx, size_t csz) { return (size_t(nfb) * n * 
 
 // Runs the FFT round trip of pipe P: forward passes with its prologue, the
 // spectral stage, inverse passes with its epilogue.
-template <class P>
-void run_pipeline(pff_solver* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev = nullptr) {
+template <class P, bool ANY>
+void run_passes(pff_solver* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev) {
   using T = typename P::real;
   constexpr int NF = P::NF;
   constexpr int NP = (NF + 1) / 2;
@@ -276,7 +287,7 @@ void run_pipeline(pff_solver* s, const typename P::Args& A, int& nblk_x, hipEven
   nblk_x = (int)((nrows + rb - 1) / rb);
   if ((size_t)nblk_x > s->part_len) throw Fail("partial buffer too small", PFF_ERR_STATE);
   if (ev) HC(hipEventRecord(ev[0], s->stream));
-  k_xfwd<P><<<nblk_x, nthr, ldsx, s->stream>>>(A, s->plan[0], tb.tw[0], spec, rb, s->part0);
+  k_xfwd<P, ANY><<<nblk_x, nthr, ldsx, s->stream>>>(A, s->plan[0], tb.tw[0], spec, rb, s->part0);
   LAUNCH_CHECK();
   if (ev) HC(hipEventRecord(ev[1], s->stream));
   // the spectral pass holds all NF fields of a tile
@@ -289,7 +300,8 @@ void run_pipeline(pff_solver* s, const typename P::Args& A, int& nblk_x, hipEven
     throw Fail("axis too long for the LDS budget", PFF_ERR_ARG);
   const dim3 gs((s->g.nxm + txs - 1) / txs + s->g.nyq, last == 1 ? s->nz : s->ny, 1);
   if (s->dim == 2) {
-    k_axis<P, -1, true><<<gs, sthr, ldss, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txs), NF, 0);
+    k_axis<P, -1, true, ANY><<<gs, sthr, ldss, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txs), NF,
+                                                            0);
     LAUNCH_CHECK();
     if (ev) {
       HC(hipEventRecord(ev[2], s->stream));
@@ -303,20 +315,30 @@ void run_pipeline(pff_solver* s, const typename P::Args& A, int& nblk_x, hipEven
     const int txy = choose_tx(s->ny, 1, csz, s->g.nxm, athr, s->axis_tx);
     const size_t ldsy = lds_axis(s->ny, 1, txy, csz);
     const dim3 gy((s->g.nxm + txy - 1) / txy + s->g.nyq, s->nz, NF);
-    k_axis<P, -1, false><<<gy, athr, ldsy, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txy), 1, 0);
+    k_axis<P, -1, false, ANY><<<gy, athr, ldsy, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txy), 1,
+                                                             0);
     LAUNCH_CHECK();
     if (ev) HC(hipEventRecord(ev[2], s->stream));
-    k_axis<P, -1, true><<<gs, sthr, ldss, s->stream>>>(A, s->plan[2], tb.tw[2], spec, 2, log2i(txs), NF,
-                                                       s->xcd_remap);
+    k_axis<P, -1, true, ANY><<<gs, sthr, ldss, s->stream>>>(A, s->plan[2], tb.tw[2], spec, 2, log2i(txs), NF,
+                                                            s->xcd_remap);
     LAUNCH_CHECK();
     if (ev) HC(hipEventRecord(ev[3], s->stream));
-    k_axis<P, 1, false><<<gy, athr, ldsy, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txy), 1, 0);
+    k_axis<P, 1, false, ANY><<<gy, athr, ldsy, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txy), 1,
+                                                            0);
     LAUNCH_CHECK();
     if (ev) HC(hipEventRecord(ev[4], s->stream));
   }
-  k_xinv<P><<<nblk_x, nthr, ldsx, s->stream>>>(A, s->plan[0], tb.tw[0], spec, rb, s->part1);
+  k_xinv<P, ANY><<<nblk_x, nthr, ldsx, s->stream>>>(A, s->plan[0], tb.tw[0], spec, rb, s->part1);
   LAUNCH_CHECK();
   if (ev) HC(hipEventRecord(ev[5], s->stream));
+}
+
+// The kernels with the generic-radix FFT stage run only where a grid length
+// has a prime factor above 3.
+template <class P>
+void run_pipeline(pff_solver* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev = nullptr) {
+  if (s->plan_any) run_passes<P, true>(s, A, nblk_x, ev);
+  else run_passes<P, false>(s, A, nblk_x, ev);
 }
 
 // ---- live kernel timing (sampled event pairs on the solver stream) -------------
@@ -1317,8 +1339,13 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     s->nz = grid->nz;
     if (s->nx < 2 || s->ny < 2 || s->nz < 1 || s->nx > 512 || s->ny > 512 || s->nz > 512)
       throw Fail("grid sizes out of range", PFF_ERR_ARG);
-    if (!factor23(s->nx, s->plan[0]) || !factor23(s->ny, s->plan[1]) || !factor23(s->nz, s->plan[2]))
-      throw Fail("grid sizes must be products of 2 and 3", PFF_ERR_ARG);
+    if (!make_plan(s->nx, s->plan[0]) || !make_plan(s->ny, s->plan[1]) || !make_plan(s->nz, s->plan[2]))
+      throw Fail("grid sizes must be between 1 and 512", PFF_ERR_ARG);
+    for (int a = 0; a < 3; ++a)
+      for (int st = 0; st < s->plan[a].nstage; ++st) {
+        const int R = s->plan[a].radix[st];
+        if (R != 2 && R != 3 && R != 4 && R != 8) s->plan_any = true;
+      }
     s->dim = s->nz == 1 ? 2 : 3;
     s->C = s->dim == 2 ? 3 : 6;
     s->nxh = s->nx / 2 + 1;

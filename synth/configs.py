@@ -131,6 +131,24 @@ def problem_config(name: str) -> Problem:
             phase_id=np.zeros((1, n, n), np.uint8),
             mask=line_crack_mask(n, n, 8, 6, 10), f=_dyad(1, 1), l=1.5,
             delta_a=0.5, n_increments=4)
+    if name == "crack2d_39":
+        # one of the paper's grid sizes (Sec. 5.1 uses 39^2, 77^2, 155^2):
+        # 39 = 3 * 13 takes a generic radix-13 FFT stage
+        n = 39
+        return Problem(
+            name=name, shape=(1, n, n), phases=[(1.0, 0.3, 1e-3)],
+            phase_id=np.zeros((1, n, n), np.uint8),
+            mask=line_crack_mask(n, n, 19, 14, 25), f=_dyad(1, 1), l=2.0,
+            delta_a=1.0, n_increments=4,
+            notes="homogeneous 39^2, centred 11-voxel crack, uniaxial yy")
+    if name == "pore35":
+        # 35 = 5 * 7: radix-5 and radix-7 stages on all three axes
+        n = 35
+        pid, _ = spheres_random(n, 3.0, 4.5, 0.12, seed=14, gap=1.0)
+        return Problem(
+            name=name, shape=(n, n, n),
+            phases=[(1.0, 0.3, 1e-3), (1e-6, 0.3, 1e-3)], phase_id=pid, mask=None,
+            f=_dyad(2, 2), l=1.5, delta_a=2.0, n_increments=2, alpha=0.9)
     if name == "gc16":
         n = 16
         pid = np.zeros((1, n, n), np.uint8)

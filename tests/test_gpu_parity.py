@@ -46,11 +46,17 @@ def rel(a, b):
     return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
 
 
+# lengths with prime factors above 3 (generic-radix FFT stages): 5, 7, 11,
+# 13, 17, 31, and the paper's 39 = 3 * 13 and 77 = 7 * 11
+ODD_SHAPES = [("tiny16", (1, 15, 20)), ("tiny16", (1, 13, 11)), ("tiny16", (1, 39, 39)),
+              ("tiny16", (1, 31, 17)), ("tiny16", (1, 14, 77)), ("part24", (5, 7, 10)),
+              ("part24", (7, 11, 13)), ("pore24", (10, 14, 35))]
+
 STD_SHAPES = [("tiny16_std", None), ("tiny16_std", (1, 12, 18)), ("tiny16_std", (1, 18, 9)),
               ("part24_std", (12, 18, 16)), ("part24_std", (9, 8, 6))]
 
 
-@pytest.mark.parametrize("name,shape", SHAPES + STD_SHAPES)
+@pytest.mark.parametrize("name,shape", SHAPES + STD_SHAPES + ODD_SHAPES)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_projection_and_laplacian(name, shape, prec):
     prob = small_problem(name, shape)
@@ -137,7 +143,9 @@ def _frozen_state(sysm, seed):
 
 @pytest.mark.parametrize("name,shape", SHAPES + [("gc16_iso", None), ("part24_iso", (12, 18, 16)),
                                               ("tiny16_std", (1, 12, 18)), ("part24_std", (12, 18, 16)),
-                                              ("gc16_w", None), ("part24_w", (9, 8, 6))])
+                                              ("gc16_w", None), ("part24_w", (9, 8, 6)),
+                                              ("tiny16", (1, 15, 20)), ("tiny16", (1, 39, 39)),
+                                              ("part24", (5, 7, 10)), ("part24", (7, 11, 13))])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_residual_and_tangent(name, shape, precision):
     prob = small_problem(name, shape, precision)
