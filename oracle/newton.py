@@ -27,6 +27,9 @@ Readings (see also `system`):
   control, which can start an uncracked cell from phi = 0.  tau0 =
   w_a Gamma(phi0), the convergence measure is |w_a Gamma + w_E E - tau| /
   |tau|, and the predictor solves w_a S(E) + w_E E = delta_a.
+* Dissipation control (eq. `SystemDis`, last line): Gamma is replaced by
+  D = integral of Gc gamma_f in the constraint, its row (r -> Gc r), tau0
+  and the predictor (S weighted by Gc).
 """
 
 from __future__ import annotations
@@ -85,7 +88,8 @@ class Solver:
     def predictor(self, delta_a):
         s = self.sys
         psif = self.psi_f()
-        S0 = lambda E: float(np.sum((1 - s.m) * self.local_damage(E, psif) ** 2)) / (2 * s.l)  # noqa: E731
+        gw = s.Gc if s.dctl else 1.0
+        S0 = lambda E: float(np.sum(gw * (1 - s.m) * self.local_damage(E, psif) ** 2)) / (2 * s.l)  # noqa: E731
         S = lambda E: s.wa * S0(E) + s.wE * E                                   # noqa: E731
         lo, hi = 0.0, 1.0
         while S(hi) < delta_a:
@@ -104,7 +108,7 @@ class Solver:
         s = self.sys
         phi0, _ = self.initial_damage()
         self.phi = phi0
-        self.a = s.wa * s.gamma(phi0)
+        self.a = s.wa * s.controlled(phi0)
         Es, psif = self.predictor(self.delta_a)
         self.guess = (np.zeros_like(self.eps_t),
                       np.maximum(phi0, (1 - s.m) * self.local_damage(Es, psif)), Es)
@@ -131,10 +135,10 @@ class Solver:
             phi = phi + self.alpha * d_phi
             E = E + self.alpha * dE
             eps = eps_t + s.fE(E)
-            gam = s.gamma(phi)
+            q = s.controlled(phi)
             errs = (np.linalg.norm(w) / np.linalg.norm(eps),
                     np.linalg.norm(d_phi) / np.linalg.norm(phi),
-                    abs(s.wa * gam + s.wE * E - a) / abs(a))
+                    abs(s.wa * q + s.wE * E - a) / abs(a))
             err = max(errs)
             if err <= self.tol:
                 return eps_t, phi, E, dict(converged=True, newton_iters=it,
@@ -160,7 +164,7 @@ class Solver:
         self.eps_t, self.phi, self.E, self.a = eps_t, phi, E, a_new
         self.n += 1
         out = dict(info)
-        out.update(increment=self.n, E=E, Gamma=s.gamma(phi), a=a_new,
+        out.update(increment=self.n, E=E, Gamma=s.gamma(phi), a=a_new, D=s.dissipation(phi),
                    sigma_M=st["sigma"].reshape(3, 3, -1).mean(axis=-1),
                    phi_norm=float(np.linalg.norm(phi)))
         self.history.append(out)

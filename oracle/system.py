@@ -53,6 +53,10 @@ class System:
         # control F3 = w_a Gamma + w_E E - tau (eq. `FEMweights`, FFT analogue);
         # (1, 0) is the crack-length control of eq. `System_CrackLength`
         self.wa, self.wE = (float(w) for w in getattr(prob, "control_weights", (1.0, 0.0)))
+        # controlled quantity: the crack length Gamma (eq. `System_CrackLength`) or
+        # the dissipation D = integral of Gc gamma_f (eq. `SystemDis`, last line);
+        # the two coincide up to the factor Gc for homogeneous toughness
+        self.dctl = getattr(prob, "control", "length") == "dissipation"
         self.f = fo.to_mandel(np.asarray(prob.f, dtype=np.float64)[:, :, None, None, None],
                               self.ncomp)[:, 0, 0, 0]
 
@@ -68,6 +72,10 @@ class System:
         l = self.l
         return float(np.sum(phi * phi / (2.0 * l) - 0.5 * l * phi * fo.laplacian(phi)))
 
+    def controlled(self, phi):
+        """The controlled quantity: Gamma, or D for dissipation control."""
+        return self.dissipation(phi) if self.dctl else self.gamma(phi)
+
     def dissipation(self, phi):
         """D = integral of Gc gamma_f (eq. `JaviGc`, middle form; unit voxels),
         gamma_f in the spectral form of `gamma`."""
@@ -82,8 +90,10 @@ class System:
         lap = fo.laplacian(phi)
         l, Gc, H = self.l, self.Gc, st["H"]
         F2 = (1.0 - self.m) * ((Gc / l + 2.0 * H) * phi - Gc * l * lap - 2.0 * H)
-        gam = float(np.sum(phi * phi / (2.0 * l) - 0.5 * l * phi * lap))
-        F3 = self.wa * gam + self.wE * E - a
+        dens = phi * phi / (2.0 * l) - 0.5 * l * phi * lap
+        gam = float(np.sum(dens))
+        Q = float(np.sum(Gc * dens)) if self.dctl else gam
+        F3 = self.wa * Q + self.wE * E - a
         sig_mean = st["sigma"].reshape(3, 3, -1).mean(axis=-1)
         return dict(F1=F1, F2=F2, F3=F3, Gamma=gam, sigma_M=sig_mean, state=st,
                     r=phi / l - l * lap)
@@ -97,6 +107,11 @@ class System:
         b = -2.0 * (1.0 - phi) * st["sigma0p"]          # d sigma / d phi
         A = Gc / l + 2.0 * st["H"]
         r = phi / l - l * fo.laplacian(phi)
+        # gradient of the controlled quantity: dGamma/dphi = r; with dissipation
+        # control dD/dphi = Gc phi/l - (l/2) (Gc Lap phi + Lap(Gc phi)) (the
+        # Laplacian is symmetric, Gc is not constant)
+        rq = (Gc * phi / l - 0.5 * l * (Gc * fo.laplacian(phi) + fo.laplacian(Gc * phi))
+              if self.dctl else r)
         c, shp = self.ncomp, self.shape
 
         def apply(v):
@@ -110,7 +125,7 @@ class System:
             bw = np.einsum("ij...,ij...->...", b, w)
             J2 = (1.0 - m) * (st["chi"] * bw + A * dphi_f
                               - Gc * l * fo.laplacian(dphi_f)) + m * d_phi
-            J3 = self.wa * np.sum(r * dphi_f) + self.wE * dE
+            J3 = self.wa * np.sum(rq * dphi_f) + self.wE * dE
             return np.concatenate([J1.ravel(), J2.ravel(), [J3]])
 
         return apply

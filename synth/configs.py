@@ -52,6 +52,7 @@ class Problem:
     split: str = "spectral"              # "spectral" (Miehe split) or "none" (isotropic degradation)
     projection: str = "rotated"          # "rotated" (Willot) or "standard" frequencies in G
     control_weights: Tuple[float, float] = (1.0, 0.0)   # (w_a, w_E): F3 = w_a Gamma + w_E E - tau
+    control: str = "length"              # controlled quantity: "length" (Gamma) or "dissipation" (D)
     notes: str = ""
     extra: dict = field(default_factory=dict)
 
@@ -72,7 +73,14 @@ def problem_config(name: str) -> Problem:
     """Return the seeded problem called `name` (benchmark or parity case).
     Suffixes: "_iso" gives the same problem with the isotropic (no split)
     degradation of Sec. 5.4, "_std" with the standard-frequency projection,
-    "_w" with the weighted control 0.7 Gamma + 3 E."""
+    "_w" with the weighted control 0.7 Gamma + 3 E, "_d" with dissipation
+    control (increment delta_a times the smallest Gc)."""
+    if name.endswith("_d"):
+        prob = problem_config(name[:-2])
+        prob.name, prob.control = name, "dissipation"
+        prob.delta_a = prob.delta_a * min(ph[2] for ph in prob.phases)
+        prob.notes = (prob.notes + "; " if prob.notes else "") + "dissipation control"
+        return prob
     if name.endswith("_w"):
         prob = problem_config(name[:-2])
         prob.name, prob.control_weights = name, (0.7, 3.0)

@@ -5,7 +5,8 @@ tests.  Calls only `oracle/` and `synth/` (the seeded problem definitions).
 
 Each CASE writes tests/golden/oracle_<CASE>.json with the bootstrap values
 (a0, E_s) and, per increment: E, Gamma, a, Sigma_M (11, 22, 33, 23, 13, 12),
-||phi||, Newton and Krylov iteration counts.
+||phi||, the dissipation D (runs written after it was added), Newton and
+Krylov iteration counts.
 """
 
 import json
@@ -21,7 +22,7 @@ from synth import problem_config  # noqa: E402
 
 CASES = {"tiny16": 4, "gc16": 4, "fib64": 4, "pore24": 3, "part24": 3, "crack2d_64": 30,
          "gc16_iso": 4, "part24_iso": 3, "gc16_std": 4, "gc16_w": 4,
-         "crack2d_39": 4, "pore35": 2}
+         "crack2d_39": 4, "pore35": 2, "gc16_d": 4}
 
 
 def run(case, n_inc):
@@ -37,7 +38,7 @@ def run(case, n_inc):
         sm = o["sigma_M"]
         incs.append(dict(increment=o["increment"], E=o["E"], Gamma=o["Gamma"], a=o["a"],
                          sigma_M=[sm[0, 0], sm[1, 1], sm[2, 2], sm[1, 2], sm[0, 2], sm[0, 1]],
-                         phi_norm=o["phi_norm"], newton_iters=o["newton_iters"],
+                         phi_norm=o["phi_norm"], dissipation=o["D"], newton_iters=o["newton_iters"],
                          krylov_iters=o["krylov_iters"]))
         print(case, incs[-1], f"{time.time() - t0:.0f}s", flush=True)
         with open(os.path.join(HERE, f"oracle_{case}.json"), "w") as fh:

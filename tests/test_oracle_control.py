@@ -10,6 +10,9 @@ System_CrackLength).
   constraint with the closed-form damage phi(E) (root found by bisection of
   the scalar constraint, written out here).
 * J v against central differences of the residual with mixed weights.
+* Dissipation control (eq. SystemDis, last line): with homogeneous Gc it is
+  crack-length control with the increment scaled by Gc; with two
+  toughnesses every increment raises D = sum Gc gamma_f by exactly delta.
 """
 
 import numpy as np
@@ -110,3 +113,57 @@ def test_tangent_is_residual_derivative_with_weights(weights):
     fd = (F(h) - F(-h)) / (2 * h)
     assert abs(Jv[-1] - fd[-1]) <= 1e-7 * abs(fd[-1])
     assert np.abs(Jv[:-1] - fd[:-1]).max() <= 2e-5 * np.abs(fd[:-1]).max()
+
+
+def test_dissipation_control_with_uniform_toughness_is_length_control():
+    a = problem_config("tiny16")
+    d = problem_config("tiny16_d")
+    Gc = a.phases[0][2]
+    assert d.delta_a == pytest.approx(Gc * a.delta_a)
+    sa, sd = Solver(a), Solver(d)
+    ba, bd = sa.bootstrap(), sd.bootstrap()
+    assert bd["a0"] == pytest.approx(Gc * ba["a0"], rel=1e-13)
+    assert bd["E_s"] == pytest.approx(ba["E_s"], rel=1e-12)
+    for _ in range(2):
+        oa, od = sa.step(), sd.step()
+        assert od["E"] == pytest.approx(oa["E"], rel=1e-9)
+        assert od["Gamma"] == pytest.approx(oa["Gamma"], rel=1e-9)
+        assert od["D"] == pytest.approx(Gc * od["Gamma"], rel=1e-13)
+
+
+def test_dissipation_control_with_two_toughnesses():
+    prob = problem_config("gc16_d")
+    s = Solver(prob)
+    b = s.bootstrap()
+    sy = s.sys
+    D0 = b["a0"]
+    assert D0 == pytest.approx(sy.dissipation(s.phi), rel=1e-13)
+    length = Solver(problem_config("gc16"))
+    length.bootstrap()
+    for i in range(1, 3):
+        o = s.step()
+        assert o["converged"]
+        assert o["D"] == pytest.approx(D0 + i * prob.delta_a, rel=1e-8)
+        ol = length.step()
+        assert abs(o["E"] - ol["E"]) > 1e-6 * ol["E"]          # a different control
+
+
+def test_tangent_is_residual_derivative_under_dissipation_control():
+    from oracle import fourier as fo
+    prob = problem_config("gc16_d")
+    sy = System(prob)
+    rng = np.random.default_rng(6)
+    eps_t = fo.G_mandel(rng.standard_normal((sy.ncomp,) + sy.shape) * 1e-3)
+    phi = np.clip(rng.uniform(0, 0.6, sy.shape) + sy.m, 0, 1)
+    E = 5e-3
+    Hn = sy.point(eps_t + sy.fE(E), phi, np.zeros(sy.shape))["psi_p"] * 0.8
+    J = sy.tangent(eps_t, phi, E, Hn)
+    d_phi = rng.standard_normal(sy.shape) * 1e-2 * (1 - sy.m)
+    Jv = J(sy.pack(np.zeros_like(eps_t), d_phi, 0.0))
+    h = 1e-6
+
+    def F3(t):
+        return sy.residual(eps_t, phi + t * d_phi, E, Hn, 1.0)["F3"]
+
+    fd = (F3(h) - F3(-h)) / (2 * h)
+    assert abs(Jv[-1] - fd) <= 1e-7 * abs(fd)     # the row with Gc r instead is 2.5e-2 off
