@@ -93,12 +93,19 @@ typedef struct {
  *               E) - tau_n, raised by delta_a per increment.  (1, 0) is the
  *               crack-length control of eq. System_CrackLength and is taken
  *               when both are 0; (0, 1) is monolithic strain control, which
- *               can start an uncracked cell.  Both >= 0. */
+ *               can start an uncracked cell.  Both >= 0.
+ *  control      PFF_CONTROL_LENGTH (0): Gamma as above; PFF_CONTROL_DISSIPATION
+ *               (1): the dissipation D = sum of Gc gamma_f takes its place
+ *               (eq. SystemDis, last line), with the border row dD/dphi =
+ *               Gc phi/l - (l/2)(Gc Lap phi + Lap(Gc phi)).  Equal up to the
+ *               factor Gc for homogeneous toughness. */
 typedef struct {
   double l, k_resid, f[9], delta_a, alpha, newton_tol, krylov_rtol;
-  int newton_maxit, krylov_maxit, precision, split, projection;
+  int newton_maxit, krylov_maxit, precision, split, projection, control;
   double w_gamma, w_load;
 } pff_params;
+
+enum { PFF_CONTROL_LENGTH = 0, PFF_CONTROL_DISSIPATION = 1 };
 
 enum { PFF_SPLIT_SPECTRAL = 0, PFF_SPLIT_NONE = 1 };
 enum { PFF_PROJ_ROTATED = 0, PFF_PROJ_STANDARD = 1 };

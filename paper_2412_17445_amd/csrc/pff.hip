@@ -169,7 +169,8 @@ struct pff_solver {
   long long tim_n[kTimSlots] = {};
   int n = 0;
   double a = 0.0, E = 0.0, E_s = 0.0;   // a: control value tau
-  double wa = 1.0, wE = 0.0;              // control weights (tau = wa Gamma + wE E)
+  double wa = 1.0, wE = 0.0;              // control weights (tau = wa Q + wE E)
+  bool dctl = false;                      // Q = D (dissipation) instead of Gamma
   long long applies = 0, kiters = 0;
   std::string err;
 
@@ -555,14 +556,15 @@ struct FinResid {
   struct Args {
     double* scal;
     double a;              // control value tau
-    double wa, wE;         // F3 = w_a Gamma + w_E E - tau
+    double wa, wE;         // F3 = w_a Q + w_E E - tau, Q = Gamma or D
+    int dctl;              // 1: Q = D (dissipation control)
     const double* E;
     double* rhs_last;
     float* rhs32_last;
     double* F_last;
   };
   __device__ static void run(const Args& F, const double* tot) {
-    const double f3 = F.wa * tot[0] + F.wE * F.E[0] - F.a;
+    const double f3 = F.wa * (F.dctl ? tot[3] : tot[0]) + F.wE * F.E[0] - F.a;
     F.scal[SC_GAMMA] = tot[0];
     F.scal[SC_F1] = tot[1];
     F.scal[SC_F2] = tot[2];
@@ -672,15 +674,32 @@ struct Impl {
     A.mask = s->mask;
     A.tab = spec_tables<double>(s);
     A.lap_ext = nullptr;
+    A.lapg = nullptr;
     if (DIM == 2) {
       LapPipe::Args LA;
       LA.g = s->g;
       LA.u = s->phi;
       LA.out = s->lap64;
       LA.tab = A.tab;
+      LA.pid = nullptr;
+      LA.mat = s->mat;
       int nb = 0;
       run_pipeline<LapPipe>(s, LA, nb);
       A.lap_ext = s->lap64;
+    }
+    if (s->dctl) {
+      // Lap(Gc phi) into a CG work vector (free outside the CG solves of the
+      // bootstrap and of the staggered Helmholtz problem)
+      LapPipe::Args LA;
+      LA.g = s->g;
+      LA.u = s->phi;
+      LA.out = s->cgv[3];
+      LA.tab = A.tab;
+      LA.pid = s->pid;
+      LA.mat = s->mat;
+      int nb = 0;
+      run_pipeline<LapPipe>(s, LA, nb);
+      A.lapg = s->cgv[3];
     }
     int nblk = 0;
     run_pipeline<ResidualPipe<DIM>>(s, A, nblk);
@@ -688,7 +707,7 @@ struct Impl {
     k_reduce<FinStore><<<1, kBlock, 0, s->stream>>>(s->part0, nblk, 6, fs);
     LAUNCH_CHECK();
     const long long last = (long long)(C + 1) * s->N;
-    FinResid::Args fr{s->scal, a, s->wa, s->wE, s->Edev, vecs<double>(s, RHS) + last,
+    FinResid::Args fr{s->scal, a, s->wa, s->wE, s->dctl ? 1 : 0, s->Edev, vecs<double>(s, RHS) + last,
                       s->kv32[RHS] ? s->kv32[RHS] + last : nullptr, F_dev ? F_dev + last : nullptr};
     k_reduce<FinResid><<<1, kBlock, 0, s->stream>>>(s->part1, nblk, 4, fr);
     LAUNCH_CHECK();
@@ -1367,6 +1386,9 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
         (p.projection != PFF_PROJ_ROTATED && p.projection != PFF_PROJ_STANDARD) ||
         !(p.w_gamma >= 0) || !(p.w_load >= 0) || !std::isfinite(p.w_gamma) || !std::isfinite(p.w_load))
       throw Fail("invalid solver parameters", PFF_ERR_ARG);
+    if (p.control != PFF_CONTROL_LENGTH && p.control != PFF_CONTROL_DISSIPATION)
+      throw Fail("invalid solver parameters", PFF_ERR_ARG);
+    s->dctl = p.control == PFF_CONTROL_DISSIPATION;
     if (p.w_gamma == 0.0 && p.w_load == 0.0) {
       s->wa = 1.0;                                    // crack-length control
       s->wE = 0.0;
@@ -1504,7 +1526,7 @@ pff_status pff_bootstrap(pff_solver* s, double* a0, double* E_s) {
       I::residual(s, 0.0, nullptr);
       sync_scal(s);
     });
-    s->a = s->wa * s->hscal[SC_GAMMA];          // tau0 (E = 0)
+    s->a = s->wa * s->hscal[s->dctl ? SC_DISS : SC_GAMMA];   // tau0 (E = 0)
     // predictor: bisection on the gradient-free homogeneous damage
     std::vector<double> psif(s->mat.nphase), cnt(s->mat.nphase, 0.0);
     for (int k = 0; k < s->mat.nphase; ++k) psif[k] = psi_plus_host(s->prm.f, s->mat.lam[k], s->mat.mu[k], s->dim, s->mat.iso);
@@ -1519,7 +1541,7 @@ pff_status pff_bootstrap(pff_solver* s, double* a0, double* E_s) {
       double acc = 0.0;
       for (int k = 0; k < s->mat.nphase; ++k) {
         const double p = loc(E, k);
-        acc += cnt[k] * p * p;
+        acc += cnt[k] * p * p * (s->dctl ? s->mat.Gc[k] : 1.0);
       }
       return s->wa * acc / (2.0 * l) + s->wE * E;
     };
@@ -1735,7 +1757,7 @@ pff_status pff_stagger_step(pff_solver* s, double dE, const pff_stagger_params* 
     HC(hipMemcpyAsync(s->phi_c, s->phi, N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
     HC(hipStreamSynchronize(s->stream));
     s->E = E;
-    s->a = s->wa * s->hscal[SC_GAMMA] + s->wE * E;   // the control value of this state
+    s->a = s->wa * s->hscal[s->dctl ? SC_DISS : SC_GAMMA] + s->wE * E;   // control value of this state
     s->n += 1;
     s->ts_valid = false;
     if (out) {

@@ -216,6 +216,9 @@ struct ResidualPipe {
     // near a root, where G[sigma] is tiny, the 12 component would carry
     // errors of eps * |Lap phi| outside the range of the projection.
     const double* lap_ext;
+    // dissipation control: Lap(Gc phi), for the border row dD/dphi =
+    // Gc phi/l - (l/2) (Gc Lap phi + Lap(Gc phi)); null for crack-length control
+    const double* lapg;
   };
 
   __device__ static void prologue(const Args& A, long long i, double* out, double* red) {
@@ -307,7 +310,7 @@ struct ResidualPipe {
     const double lap = A.lap_ext ? A.lap_ext[i] : in[C];
     const double l = A.l;
     const double F2 = m ? 0.0 : (Gc / l + 2.0 * H) * phi - Gc * l * lap - 2.0 * H;
-    const double r = phi / l - l * lap;
+    const double r = A.lapg ? Gc * phi / l - 0.5 * l * (Gc * lap + A.lapg[i]) : phi / l - l * lap;
     A.ts[L::R * N + i] = r;
     if (A.ts32) A.ts32[L::R * N + i] = float(r);
     double f1 = 0.0;
@@ -377,8 +380,12 @@ struct LapPipe {
     const double* u;
     double* out;
     SpecTables<double> tab;
+    const uint8_t* pid;      // non-null: the input is Gc u (per-phase toughness of mat)
+    Material mat;
   };
-  __device__ static void prologue(const Args& A, long long i, double* out, double*) { out[0] = A.u[i]; }
+  __device__ static void prologue(const Args& A, long long i, double* out, double*) {
+    out[0] = A.pid ? A.mat.Gc[A.pid[i]] * A.u[i] : A.u[i];
+  }
   __device__ static void spectral(const Args& A, int kx, int ky, int kz, cpx<double>* v) {
     if (A.g.nz == 1) spectral_proj_lap<double, 2, 0, true>(A.tab, kx, ky, kz, v);
     else spectral_proj_lap<double, 3, 0, true>(A.tab, kx, ky, kz, v);

@@ -30,11 +30,14 @@ def _torch():
 def marshal_problem(shape, phases, phase_id, mask, f, l, k=1e-6, delta_a=1.0, alpha=1.0,
                     newton_tol=1e-8, krylov_rtol=1e-10, newton_maxit=50, krylov_maxit=5000,
                     precision="fp64", split="spectral", projection="rotated",
-                    control_weights=(1.0, 0.0)):
+                    control_weights=(1.0, 0.0), control="length"):
     """C structs and host arrays of one RVE problem (pff_create's inputs).
     split: "spectral" (Miehe split) or "none" (isotropic degradation);
     projection: "rotated" (Willot) or "standard" frequencies in G;
-    control_weights: (w_a, w_E) of the controlled quantity w_a Gamma + w_E E."""
+    control_weights: (w_a, w_E) of the controlled quantity w_a Q + w_E E;
+    control: Q is "length" (Gamma) or "dissipation" (sum of Gc gamma_f)."""
+    if control not in ("length", "dissipation"):
+        raise ValueError("control must be 'length' or 'dissipation'")
     if split not in ("spectral", "none"):
         raise ValueError("split must be 'spectral' or 'none'")
     if projection not in ("rotated", "standard"):
@@ -58,6 +61,7 @@ def marshal_problem(shape, phases, phase_id, mask, f, l, k=1e-6, delta_a=1.0, al
     prm.split = L.PFF_SPLIT_NONE if split == "none" else L.PFF_SPLIT_SPECTRAL
     prm.projection = L.PFF_PROJ_STANDARD if projection == "standard" else L.PFF_PROJ_ROTATED
     prm.w_gamma, prm.w_load = (float(w) for w in control_weights)
+    prm.control = L.PFF_CONTROL_DISSIPATION if control == "dissipation" else L.PFF_CONTROL_LENGTH
     return grid, ph, pid, msk, prm
 
 
@@ -68,7 +72,8 @@ def problem_kwargs(prob, **over):
               newton_maxit=prob.newton_maxit, krylov_maxit=prob.krylov_maxit,
               precision=prob.precision, split=getattr(prob, "split", "spectral"),
               projection=getattr(prob, "projection", "rotated"),
-              control_weights=getattr(prob, "control_weights", (1.0, 0.0)))
+              control_weights=getattr(prob, "control_weights", (1.0, 0.0)),
+              control=getattr(prob, "control", "length"))
     kw.update(over)
     return kw
 
@@ -87,7 +92,7 @@ class Solver:
     def __init__(self, shape, phases, phase_id, mask, f, l, k=1e-6, delta_a=1.0, alpha=1.0,
                  newton_tol=1e-8, krylov_rtol=1e-10, newton_maxit=50, krylov_maxit=5000,
                  precision="fp64", split="spectral", projection="rotated",
-                 control_weights=(1.0, 0.0), stream=None):
+                 control_weights=(1.0, 0.0), control="length", stream=None):
         torch = _torch()
         self.lib = L.load()
         nz, ny, nx = shape
@@ -101,7 +106,7 @@ class Solver:
             shape, phases, phase_id, mask, f, l, k=k, delta_a=delta_a, alpha=alpha,
             newton_tol=newton_tol, krylov_rtol=krylov_rtol, newton_maxit=newton_maxit,
             krylov_maxit=krylov_maxit, precision=precision, split=split, projection=projection,
-            control_weights=control_weights)
+            control_weights=control_weights, control=control)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self._stream = stream
@@ -120,7 +125,8 @@ class Solver:
                   krylov_maxit=prob.krylov_maxit, precision=prob.precision,
                   split=getattr(prob, "split", "spectral"),
                   projection=getattr(prob, "projection", "rotated"),
-                  control_weights=getattr(prob, "control_weights", (1.0, 0.0)))
+                  control_weights=getattr(prob, "control_weights", (1.0, 0.0)),
+                  control=getattr(prob, "control", "length"))
         kw.update(over)
         return cls(prob.shape, prob.phases, prob.phase_id, prob.mask, prob.f, prob.l, **kw)
 

@@ -145,7 +145,8 @@ def _frozen_state(sysm, seed):
                                               ("tiny16_std", (1, 12, 18)), ("part24_std", (12, 18, 16)),
                                               ("gc16_w", None), ("part24_w", (9, 8, 6)),
                                               ("tiny16", (1, 15, 20)), ("tiny16", (1, 39, 39)),
-                                              ("part24", (5, 7, 10)), ("part24", (7, 11, 13))])
+                                              ("part24", (5, 7, 10)), ("part24", (7, 11, 13)),
+                                              ("gc16_d", None), ("part24_d", (9, 8, 6))])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_residual_and_tangent(name, shape, precision):
     prob = small_problem(name, shape, precision)
@@ -177,6 +178,9 @@ def test_residual_and_tangent(name, shape, precision):
     for blk in (slice(0, c * N), slice(c * N, (c + 1) * N)):
         assert rel(Jv[blk], ref[blk]) < tol
     r = phi / sysm.l - sysm.l * fo.laplacian(phi)
+    if sysm.dctl:
+        Gc = sysm.Gc
+        r = Gc * phi / sysm.l - 0.5 * sysm.l * (Gc * fo.laplacian(phi) + fo.laplacian(Gc * phi))
     scale = sysm.wa * np.sum(np.abs(r * (1 - sysm.m) * v[c * N:(c + 1) * N].reshape(sysm.shape))) \
         + sysm.wE * abs(v[-1])
     assert abs(Jv[-1] - ref[-1]) <= tol * scale
