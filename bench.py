@@ -200,6 +200,41 @@ def staggered_leg(prob, first):
             "rel_diff_sigma_M": float("%.3e" % (np.abs(sm - so).max() / np.abs(so).max()))}
 
 
+def odd_grid_leg(args):
+    """One crack-length increment on a grid whose length has prime factors
+    above 3 (105 = 3 * 5 * 7, the paper's 3D grid): the pass kernels with
+    generic-radix FFT stages.  Reports the in-solve apply time per voxel."""
+    import torch
+
+    from paper_2412_17445_amd import Solver
+    from synth import problem_config
+
+    prob = problem_config(args.odd_workload)
+    s = Solver.from_problem(prob)
+    s.bootstrap()
+    w = s.step()
+    log(f"{args.odd_workload} warm-up increment: converged={w['converged']} {w['seconds']:.2f}s")
+    s.timing(args.timing_every)
+    a0, _ = s.counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    o = s.step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    a1, _ = s.counters()
+    tim = s.timing_read()
+    whole = [v for sl, v in tim.items() if sl % 6 == 5]
+    n_ap, ms_ap = sum(v[0] for v in whole), sum(v[1] for v in whole)
+    s.close()
+    log(f"{args.odd_workload} timed increment: converged={o['converged']} {dt:.2f}s")
+    return {"workload": args.odd_workload, "grid": list(prob.shape[::-1]), "precision": prob.precision,
+            "converged": o["converged"], "ms_per_increment": round(dt * 1e3, 2),
+            "tangent_applies": a1 - a0,
+            "mvoxel_applies_per_s": round((a1 - a0) * prob.nvox / dt / 1e6, 1),
+            "apply_us_avg": round(ms_ap / max(n_ap, 1) * 1e3, 2),
+            "apply_ns_per_voxel": round(ms_ap / max(n_ap, 1) * 1e6 / prob.nvox, 4)}
+
+
 def serve_stream(args):
     """Seeded request stream (synth.stream) through the request server:
     Poisson arrivals, admission by footprint into slots, per-request latency
@@ -297,6 +332,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the served request stream")
     ap.add_argument("--no-stagger", action="store_true",
                     help="skip the staggered strain-controlled increment")
+    ap.add_argument("--no-odd", action="store_true",
+                    help="skip the increment on a grid with prime factors above 3")
+    ap.add_argument("--odd-workload", default="pores3d_105")
     ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrivals per second")
     ap.add_argument("--serve-inc-scale", type=float, default=0.1,
@@ -436,6 +474,10 @@ def main():
         if "mixed_vs_fp64" in line:
             line["staggered_vs_crack_control"]["crack_control_fp64_seconds"] = \
                 line["mixed_vs_fp64"]["fp64_first_increment_s"]
+    if not args.no_odd:
+        line["odd_grid"] = odd_grid_leg(args)
+        line["odd_grid"]["apply_ns_per_voxel_main"] = round(
+            line["config"]["apply_us_avg"] * 1e3 / N, 4)
     if not args.no_serve:
         line["serving"] = serve_stream(args)
     if not args.no_cpu_baseline:

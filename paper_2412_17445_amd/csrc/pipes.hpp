@@ -106,7 +106,7 @@ struct TangentPipe {
       T eps[C];
 #pragma unroll
       for (int k = 0; k < C; ++k) eps[k] = A.ts[k * N + i];
-      split_eval<T, D>(eps, lam, mu, sp);
+      split_eval<T, D>(eps, lam, mu, sp, A.mat.iso != 0);
     } else {
       T q[4];
 #pragma unroll
@@ -114,29 +114,13 @@ struct TangentPipe {
 #pragma unroll
       for (int a = 0; a < 3; ++a) sp.e.z[a] = A.ts[(4 + a) * N + i];
       quat_to_rot<T>(q, sp.e.V);
-      split_from_eig<T, D>(lam, mu, sp.e.z[0] + sp.e.z[1] + sp.e.z[2], sp);
+      split_from_eig<T, D>(lam, mu, sp.e.z[0] + sp.e.z[1] + sp.e.z[2], sp, A.mat.iso != 0);
     }
     const T g = (T(1) - phi) * (T(1) - phi) + A.k;
     T Cw[C];
+    tangent_apply<T, D>(sp, lam, mu, g, w, Cw);
     T S[D][D];
-    if (A.mat.iso) {
-      // isotropic model: C = g C0 (Mandel: normal components first), b = g' sigma0
-      T trw = T(0);
-#pragma unroll
-      for (int a = 0; a < D; ++a) trw += w[a];
-#pragma unroll
-      for (int q = 0; q < C; ++q) Cw[q] = g * (T(2) * mu * w[q] + (q < D ? lam * trw : T(0)));
-      T Sm[D][D];
-      sigma0<T, D, true>(sp, lam, mu, S);
-      sigma0<T, D, false>(sp, lam, mu, Sm);
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = 0; b < D; ++b) S[a][b] += Sm[a][b];
-    } else {
-      tangent_apply<T, D>(sp, lam, mu, g, w, Cw);
-      sigma0<T, D, true>(sp, lam, mu, S);
-    }
+    sigma0<T, D, true>(sp, lam, mu, S);
     T b[C];
     tensor_to_mandel<T, D>(S, b);
     const T gp = T(-2) * (T(1) - phi);            // g'(phi)
@@ -232,29 +216,18 @@ struct ResidualPipe {
     const double phi = A.phi[i];
     const double Hn = A.Hn[i];
     Split<double, D> sp;
-    split_eval<double, D>(eps, lam, mu, sp);
+    split_eval<double, D>(eps, lam, mu, sp, A.mat.iso != 0);
     const double g = (1.0 - phi) * (1.0 - phi) + A.k;
     double Sp[D][D], Sm[D][D], Sg[D][D];
     sigma0<double, D, true>(sp, lam, mu, Sp);
     sigma0<double, D, false>(sp, lam, mu, Sm);
-    const double gm = A.mat.iso ? g : 1.0;    // isotropic model: the negative part degrades too
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
-      for (int b = 0; b < D; ++b) Sg[a][b] = g * Sp[a][b] + gm * Sm[a][b];
+      for (int b = 0; b < D; ++b) Sg[a][b] = g * Sp[a][b] + Sm[a][b];
     double sm[C];
     tensor_to_mandel<double, D>(Sg, sm);
-    double psi = sp.psi_p;                    // history driver
-    if (A.mat.iso) {
-      const double trm = sp.tr < 0.0 ? sp.tr : 0.0;
-      double sq = 0.0;
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const double zm = sp.e.z[a] < 0.0 ? sp.e.z[a] : 0.0;
-        sq += zm * zm;
-      }
-      psi += 0.5 * lam * trm * trm + mu * sq;
-    }
+    const double psi = sp.psi_p;              // history driver (the whole psi0 when iso)
     const double H = psi > Hn ? psi : Hn;
     const bool chi = psi >= Hn;
     const double Hs = chi ? -H : H;
@@ -282,10 +255,10 @@ struct ResidualPipe {
     }
     out[C] = A.lap_ext ? 0.0 : phi;
     if constexpr (DIM == 2) {
-      const double trp = sp.tr > 0.0 ? sp.tr : 0.0, trm = sp.tr < 0.0 ? sp.tr : 0.0;
+      const double trp = sp.trp, trm = sp.tr - sp.trp;
       red[0] += Sg[0][0];
       red[1] += Sg[1][1];
-      red[2] += g * lam * trp + gm * lam * trm;   // sigma_zz of plane strain
+      red[2] += g * lam * trp + lam * trm;     // sigma_zz of plane strain
       red[5] += Sg[0][1];
     } else {
       red[0] += Sg[0][0];

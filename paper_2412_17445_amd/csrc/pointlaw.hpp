@@ -147,23 +147,31 @@ __device__ __forceinline__ void eig_sym(const T (&E)[3][3], Eig<T, 3>& e) {
 }
 
 // Evaluated split state of one voxel.
+// The degraded part of the strain energy.  Spectral split: the positive
+// parts <tr>+ and <zeta_a>+; isotropic model (iso): the whole strain, i.e.
+// every part taken as "positive", so sigma0(+) = sigma0, P(+) = I, C = g C0
+// and psi0(+) = psi0, with empty negative parts.
 template <typename T, int D> struct Split {
   Eig<T, D> e;
   T tr;            // trace of eps (eps_zz = 0 in plane strain)
-  T zp[D];         // <zeta>+
-  T theta[D][D];   // multipliers of P(+) in the eigenbasis
-  T psi_p;         // psi0(+)
+  T trp;           // degraded part of the trace: <tr>+ (tr when iso)
+  T htr;           // Theta(tr) in the tangent's volumetric term (1 when iso)
+  T zp[D];         // degraded parts of the eigenvalues: <zeta>+ (zeta when iso)
+  T theta[D][D];   // multipliers of P(+) in the eigenbasis (1 when iso)
+  T psi_p;         // psi0(+) (psi0 when iso): the history driver
 };
 
 // Completes the split state once sp.e holds the eigen-decomposition.
 template <typename T, int D>
-__device__ __forceinline__ void split_from_eig(T lam, T mu, T tr, Split<T, D>& sp) {
+__device__ __forceinline__ void split_from_eig(T lam, T mu, T tr, Split<T, D>& sp, bool iso = false) {
   sp.tr = tr;
-  const T trp = tr > T(0) ? tr : T(0);
+  const T trp = (iso || tr > T(0)) ? tr : T(0);
+  sp.trp = trp;
+  sp.htr = (iso || tr > T(0)) ? T(1) : T(0);
   T sq = T(0);
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    sp.zp[a] = sp.e.z[a] > T(0) ? sp.e.z[a] : T(0);
+    sp.zp[a] = (iso || sp.e.z[a] > T(0)) ? sp.e.z[a] : T(0);
     sq += sp.zp[a] * sp.zp[a];
   }
   sp.psi_p = T(0.5) * lam * trp * trp + mu * sq;
@@ -172,20 +180,20 @@ __device__ __forceinline__ void split_from_eig(T lam, T mu, T tr, Split<T, D>& s
 #pragma unroll
     for (int b = 0; b < D; ++b) {
       const bool ta = sp.e.z[a] > T(0), tb = sp.e.z[b] > T(0);
-      sp.theta[a][b] = (ta != tb) ? (sp.zp[a] - sp.zp[b]) / (sp.e.z[a] - sp.e.z[b])
-                                  : (ta ? T(1) : T(0));
+      const T th = (ta != tb) ? (sp.zp[a] - sp.zp[b]) / (sp.e.z[a] - sp.e.z[b]) : (ta ? T(1) : T(0));
+      sp.theta[a][b] = iso ? T(1) : th;
     }
 }
 
 template <typename T, int D>
-__device__ __forceinline__ void split_eval(const T* eps_m, T lam, T mu, Split<T, D>& sp) {
+__device__ __forceinline__ void split_eval(const T* eps_m, T lam, T mu, Split<T, D>& sp, bool iso = false) {
   T E[D][D];
   mandel_to_tensor<T, D>(eps_m, E);
   eig_sym(E, sp.e);
   T tr = T(0);
 #pragma unroll
   for (int i = 0; i < D; ++i) tr += E[i][i];
-  split_from_eig<T, D>(lam, mu, tr, sp);
+  split_from_eig<T, D>(lam, mu, tr, sp, iso);
 }
 
 // Unit quaternion (w, x, y, z) of a proper rotation matrix (Shepperd's
@@ -240,7 +248,7 @@ __device__ __forceinline__ void quat_to_rot(const T* qin, T (&V)[3][3]) {
 // returned separately by the caller as lambda <tr>(+/-)).
 template <typename T, int D, bool POS>
 __device__ __forceinline__ void sigma0(const Split<T, D>& sp, T lam, T mu, T (&S)[D][D]) {
-  const T trx = POS ? (sp.tr > T(0) ? sp.tr : T(0)) : (sp.tr < T(0) ? sp.tr : T(0));
+  const T trx = POS ? sp.trp : sp.tr - sp.trp;
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
@@ -248,7 +256,7 @@ __device__ __forceinline__ void sigma0(const Split<T, D>& sp, T lam, T mu, T (&S
       T acc = T(0);
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        const T za = POS ? sp.zp[a] : (sp.e.z[a] < T(0) ? sp.e.z[a] : T(0));
+        const T za = POS ? sp.zp[a] : sp.e.z[a] - sp.zp[a];
         acc += za * sp.e.V[i][a] * sp.e.V[j][a];
       }
       S[i][j] = T(2) * mu * acc + (i == j ? lam * trx : T(0));
@@ -299,7 +307,7 @@ __device__ __forceinline__ void tangent_apply(const Split<T, D>& sp, T lam, T mu
   T trw = T(0);
 #pragma unroll
   for (int i = 0; i < D; ++i) trw += W[i][i];
-  const T lam_eff = lam * ((g - T(1)) * (sp.tr > T(0) ? T(1) : T(0)) + T(1));
+  const T lam_eff = lam * ((g - T(1)) * sp.htr + T(1));
   T O[D][D];
 #pragma unroll
   for (int i = 0; i < D; ++i)

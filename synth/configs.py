@@ -121,6 +121,18 @@ def problem_config(name: str) -> Problem:
             f=_dyad(2, 2), l=1.5, delta_a=4.0, n_increments=60, alpha=0.9,
             precision="mixed", krylov_rtol=1e-5,
             notes="64^3 porous, 15% spherical pores r~U[3,6]")
+    if name == "pores3d_105":
+        # stand-in for the paper's 3D porous case (Sec. 5.5: 105^3 voxels,
+        # 8 random spherical voids, 20% porosity); 105 = 3 * 5 * 7 takes
+        # generic radix-5 and radix-7 FFT stages
+        n = 105
+        pid, _ = spheres_random(n, 0.0, 0.0, 0.199, seed=5, gap=2.0, fixed_radius=19.05)
+        return Problem(
+            name=name, shape=(n, n, n),
+            phases=[(1.0, 0.3, 1e-3), (1e-6, 0.3, 1e-3)], phase_id=pid, mask=None,
+            f=_dyad(2, 2), l=1.5, delta_a=8.0, n_increments=40, alpha=0.9,
+            precision="mixed", krylov_rtol=1e-5,
+            notes="105^3 porous, 8 spherical voids r=19.05, ~20%")
     if name == "particles3d_128":
         n = 128
         pid, _ = spheres_random(n, 6.0, 6.0, 0.25, seed=4, gap=1.0, fixed_radius=6.0)
