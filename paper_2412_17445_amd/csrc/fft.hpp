@@ -4,10 +4,10 @@
 // product of the radices already applied, butterfly j of a radix-R stage
 // reads the R inputs j + r*n/R, multiplies input r by w_{Ns*R}^{r*(j mod Ns)},
 // applies an R-point DFT and writes output r to (j div Ns)*Ns*R + j mod Ns +
-// r*Ns.  Radices 2, 3, 4 and 8 have unrolled butterflies; every other
-// prime factor p of the length runs a stage of radix p in which each item
-// computes one output element from its p inputs (O(p) work per element), so
-// any length up to the tile limit is covered.  S = -1 is the
+// r*Ns.  Radices 2, 3, 4, 8 and the odd primes 5, 7, 11, 13 have unrolled
+// butterflies; every other prime factor p of the length runs a stage of
+// radix p in which each item computes one output element from its p inputs
+// (O(p) work per element), so any length up to the tile limit is covered.  S = -1 is the
 // forward transform (exp(-2 pi i jk/n), the numpy convention), S = +1 the
 // unnormalised inverse.  The caller scales by 1/N elsewhere.
 //
@@ -74,11 +74,63 @@ template <typename T, int S> __device__ __forceinline__ void dft8(cpx<T>* v) {
   v[7] = csub(e[3], o3);
 }
 
+// cos and sin of 2 pi j / P for the odd prime radices with unrolled butterflies
+__host__ __device__ constexpr double odd_cos(int P, int j) {
+  // j = 1 .. (P-1)/2
+  if (P == 5) { constexpr double t[] = {0.30901699437494745, -0.8090169943749473}; return t[j - 1]; }
+  if (P == 7) { constexpr double t[] = {0.6234898018587336, -0.22252093395631434, -0.900968867902419}; return t[j - 1]; }
+  if (P == 11) { constexpr double t[] = {0.8412535328311812, 0.41541501300188644, -0.142314838273285, -0.654860733945285, -0.9594929736144974}; return t[j - 1]; }
+  if (P == 13) { constexpr double t[] = {0.8854560256532099, 0.5680647467311559, 0.120536680255323, -0.35460488704253545, -0.7485107481711012, -0.970941817426052}; return t[j - 1]; }
+  return 0.0;
+}
+__host__ __device__ constexpr double odd_sin(int P, int j) {
+  // j = 1 .. (P-1)/2
+  if (P == 5) { constexpr double t[] = {0.9510565162951535, 0.5877852522924732}; return t[j - 1]; }
+  if (P == 7) { constexpr double t[] = {0.7818314824680298, 0.9749279121818236, 0.43388373911755823}; return t[j - 1]; }
+  if (P == 11) { constexpr double t[] = {0.5406408174555976, 0.9096319953545183, 0.9898214418809328, 0.7557495743542583, 0.28173255684142967}; return t[j - 1]; }
+  if (P == 13) { constexpr double t[] = {0.4647231720437685, 0.8229838658936564, 0.992708874098054, 0.9350162426854148, 0.6631226582407952, 0.23931566428755768}; return t[j - 1]; }
+  return 0.0;
+}
+
+// P-point DFT for odd prime P, pairing inputs j and P - j:
+//   y_k     = x_0 + sum_j [cos(2 pi jk/P) (x_j + x_{P-j}) + S i sin(2 pi jk/P) (x_j - x_{P-j})]
+//   y_{P-k} = the same with -S i,   j, k = 1 .. (P-1)/2.
+template <typename T, int S, int P> __device__ __forceinline__ void dft_odd(cpx<T>* v) {
+  constexpr int H = (P - 1) / 2;
+  cpx<T> a[H], b[H];
+  const cpx<T> x0 = v[0];
+  cpx<T> y0 = x0;
+#pragma unroll
+  for (int j = 1; j <= H; ++j) {
+    a[j - 1] = cadd(v[j], v[P - j]);
+    b[j - 1] = csub(v[j], v[P - j]);
+    y0 = cadd(y0, a[j - 1]);
+  }
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    cpx<T> re = x0, im = {T(0), T(0)};
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+      const int m = (j * k) % P;
+      const int idx = m <= H ? m : P - m;
+      const T c = T(odd_cos(P, idx));
+      const T sn = T(m <= H ? odd_sin(P, idx) : -odd_sin(P, idx));
+      re = {re.x + c * a[j - 1].x, re.y + c * a[j - 1].y};
+      im = {im.x + sn * b[j - 1].x, im.y + sn * b[j - 1].y};
+    }
+    const cpx<T> t = mul_si<T, S>(im);
+    v[k] = cadd(re, t);
+    v[P - k] = csub(re, t);
+  }
+  v[0] = y0;
+}
+
 template <typename T, int S, int R> __device__ __forceinline__ void dftR(cpx<T>* v) {
   if constexpr (R == 2) dft2<T, S>(v);
   else if constexpr (R == 3) dft3<T, S>(v);
   else if constexpr (R == 4) dft4<T, S>(v);
-  else dft8<T, S>(v);
+  else if constexpr (R == 8) dft8<T, S>(v);
+  else dft_odd<T, S, R>(v);
 }
 
 template <typename T, int S, int R, int MAXE>
@@ -281,7 +333,13 @@ __device__ void fft_lds(cpx<T>* buf, int nseq, int ltx, const AxisPlan& pl, cons
     else if (R == 4) stockham_stage<T, S, 4, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
     else if (R == 3) stockham_stage<T, S, 3, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
     else if (R == 2) stockham_stage<T, S, 2, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
-    else if constexpr (ANY) stockham_stage_any<T, S, MAXE>(buf, pl.n, R, Ns, nseq, ltx, tw);
+    else if constexpr (ANY) {
+      if (R == 5) stockham_stage<T, S, 5, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
+      else if (R == 7) stockham_stage<T, S, 7, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
+      else if (R == 11) stockham_stage<T, S, 11, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
+      else if (R == 13) stockham_stage<T, S, 13, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
+      else stockham_stage_any<T, S, MAXE>(buf, pl.n, R, Ns, nseq, ltx, tw);
+    }
     Ns *= R;
   }
 }
