@@ -714,6 +714,19 @@ struct Impl {
     s->ts_valid = true;
   }
 
+  // Isotropic model (FP64 solves): the BiCGSTAB directions p and s are
+  // projected onto compatible strains, so the solve runs on J restricted to
+  // compatible fields.  When every voxel is a history tie (the warm start of
+  // an increment: the whole psi0 drives the history) the bordered Jacobian
+  // has a null direction made mostly of incompatible strain; round-off lets
+  // an unprojected solve pick it up with a large amplitude, which the step
+  // projection after the solve cannot undo.
+  static void keep_compatible(pff_solver* s, TW* x) {
+    if constexpr (std::is_same<TW, double>::value) {
+      if (s->mat.iso) project_strain(s, x);
+    }
+  }
+
   static void reduce_ks(pff_solver* s, int nslot, int which) {
     const int nb = red_blocks(s->M);
     double* ks = s->scal + SC_KS;
@@ -768,21 +781,25 @@ struct Impl {
           if (!issued) {
             k_bicg_p<TW><<<g1, kBlock, 0, s->stream>>>(p, r, v, ks, M);
             LAUNCH_CHECK();
+            keep_compatible(s, p);
             apply_fused(s, 1, 0, p, nullptr, nullptr, nullptr, v, rhat);
           }
           issued = false;
           k_bicg_s<TW><<<g1, kBlock, 0, s->stream>>>(sv, r, v, ks, M);
           LAUNCH_CHECK();
+          keep_compatible(s, sv);
           apply_fused(s, 2, 0, sv, nullptr, nullptr, nullptr, t, sv);
         } else {
           k_bicg_p<TW><<<g1, kBlock, 0, s->stream>>>(p, r, v, ks, M);
           LAUNCH_CHECK();
+          keep_compatible(s, p);
           apply(s, p, v);
           k_dots<TW, 1><<<g1, kBlock, 0, s->stream>>>(rhat, v, nullptr, nullptr, nullptr, nullptr, M, s->part0);
           LAUNCH_CHECK();
           reduce_ks(s, 1, 2);
           k_bicg_s<TW><<<g1, kBlock, 0, s->stream>>>(sv, r, v, ks, M);
           LAUNCH_CHECK();
+          keep_compatible(s, sv);
           apply(s, sv, t);
           k_dots<TW, 2><<<g1, kBlock, 0, s->stream>>>(t, sv, t, t, nullptr, nullptr, M, s->part0);
           LAUNCH_CHECK();
@@ -804,6 +821,7 @@ struct Impl {
           if (s->fused == 1) {
             k_bicg_p<TW><<<g1, kBlock, 0, s->stream>>>(p, r, v, ks, M);
             LAUNCH_CHECK();
+            keep_compatible(s, p);
             apply_fused(s, 1, 0, p, nullptr, nullptr, nullptr, v, rhat);
           } else {
             apply_fused(s, 1, 1, p, r, v, p, v, rhat);

@@ -71,15 +71,6 @@ def _compare(out, ref, tol):
 # along the path, not by 1e-9.
 TOL_FP64 = {"crack2d_64": 1e-7}
 
-# Isotropic model in 3D (part24_iso): at the warm start of increment 2 every
-# voxel is a history tie (psi0 = H_n everywhere, since the whole energy
-# drives the history), and the bordered Jacobian has a null direction (mostly
-# incompatible strain coupled with damage and E: |J d| / |d| = 2e-14).  The
-# GPU's BiCGSTAB converged to 1e-10 onto a solution that carries that
-# direction (dE = 0.30 against the oracle's 6.7e-4; both solve the system to
-# 1e-10), after which Newton diverges.  Compared up to increment 1 until the
-# Krylov directions are kept compatible in this mode.
-MAX_INCREMENTS = {"part24_iso": 1}
 
 
 @pytest.mark.parametrize("case", ["tiny16", "gc16", "fib64", "pore24", "part24", "crack2d_64",
@@ -94,7 +85,7 @@ def test_fp64_increments_match_oracle(case):
     assert abs(es - g["E_s"]) <= 1e-12 * g["E_s"]
     tol = TOL_FP64.get(case, 1e-9 if prob.alpha == 1.0 else 1e-8)
     errs = []
-    for ref in g["increments"][:MAX_INCREMENTS.get(case)]:
+    for ref in g["increments"]:
         out = s.step()
         assert out["converged"], out
         errs.append(max(_errors(out, ref)))
@@ -117,7 +108,7 @@ def test_mixed_increments_match_fp64_oracle(case, rtol):
     prob = problem_config(case)
     s = gpu(prob, precision="mixed", krylov_rtol=rtol)
     s.bootstrap()
-    for ref in g["increments"][:MAX_INCREMENTS.get(case)]:
+    for ref in g["increments"]:
         out = s.step()
         err = _compare(out, ref, 1e-5)
         print(case, "mixed increment", ref["increment"], "max rel err %.2e" % err,
