@@ -111,15 +111,56 @@ __global__ void __launch_bounds__(kBlock) k_bicg_shadow(const T* __restrict__ r,
   write_partials<1>(acc, partials);
 }
 
+// 16-byte packets for the streaming BiCGSTAB updates (float4 / double2):
+// one load or store instruction per lane moves 16 bytes.  The Krylov vectors
+// are separate device allocations (256-byte aligned); any other pointer
+// that is not 16-byte aligned takes the element loop.
+template <typename T> struct Packet;
+template <> struct Packet<float> { using V = float4; static constexpr int W = 4; };
+template <> struct Packet<double> { using V = double2; static constexpr int W = 2; };
+template <typename T> struct Lanes { T v[Packet<T>::W]; };
+
+template <typename T> __device__ __forceinline__ Lanes<T> pk_load(const T* p, long long j) {
+  const typename Packet<T>::V q = reinterpret_cast<const typename Packet<T>::V*>(p)[j];
+  Lanes<T> o;
+  __builtin_memcpy(&o, &q, sizeof(o));
+  return o;
+}
+template <typename T> __device__ __forceinline__ void pk_store(T* p, long long j, const Lanes<T>& o) {
+  typename Packet<T>::V q;
+  __builtin_memcpy(&q, &o, sizeof(q));
+  reinterpret_cast<typename Packet<T>::V*>(p)[j] = q;
+}
+__device__ __forceinline__ bool aligned16(const void* a, const void* b = nullptr, const void* c = nullptr,
+                                          const void* d = nullptr, const void* e = nullptr,
+                                          const void* f = nullptr, const void* g = nullptr) {
+  return ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(c) |
+           reinterpret_cast<uintptr_t>(d) | reinterpret_cast<uintptr_t>(e) | reinterpret_cast<uintptr_t>(f) |
+           reinterpret_cast<uintptr_t>(g)) & 15) == 0;
+}
+
 // p = r + beta (p - omega v)
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_bicg_p(T* __restrict__ p, const T* __restrict__ r,
                                                    const T* __restrict__ v, const double* __restrict__ ks,
                                                    long long M) {
   const T beta = T(ks[KS_BETA]), omega = T(ks[KS_OMEGA]);
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
-       i += (long long)gridDim.x * blockDim.x)
-    p[i] = r[i] + beta * (p[i] - omega * v[i]);
+  constexpr int W = Packet<T>::W;
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  long long i0 = 0;
+  if (aligned16(p, r, v)) {
+    const long long nv = M / W;
+    for (long long j = tid; j < nv; j += stride) {
+      const Lanes<T> rr = pk_load(r, j), pp = pk_load(p, j), vv = pk_load(v, j);
+      Lanes<T> o;
+#pragma unroll
+      for (int w = 0; w < W; ++w) o.v[w] = rr.v[w] + beta * (pp.v[w] - omega * vv.v[w]);
+      pk_store(p, j, o);
+    }
+    i0 = nv * W;
+  }
+  for (long long i = i0 + tid; i < M; i += stride) p[i] = r[i] + beta * (p[i] - omega * v[i]);
 }
 
 // s = r - alpha v
@@ -128,9 +169,22 @@ __global__ void __launch_bounds__(kBlock) k_bicg_s(T* __restrict__ s, const T* _
                                                    const T* __restrict__ v, const double* __restrict__ ks,
                                                    long long M) {
   const T alpha = T(ks[KS_ALPHA]);
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
-       i += (long long)gridDim.x * blockDim.x)
-    s[i] = r[i] - alpha * v[i];
+  constexpr int W = Packet<T>::W;
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  long long i0 = 0;
+  if (aligned16(s, r, v)) {
+    const long long nv = M / W;
+    for (long long j = tid; j < nv; j += stride) {
+      const Lanes<T> rr = pk_load(r, j), vv = pk_load(v, j);
+      Lanes<T> o;
+#pragma unroll
+      for (int w = 0; w < W; ++w) o.v[w] = rr.v[w] - alpha * vv.v[w];
+      pk_store(s, j, o);
+    }
+    i0 = nv * W;
+  }
+  for (long long i = i0 + tid; i < M; i += stride) s[i] = r[i] - alpha * v[i];
 }
 
 // x_next = x + alpha p + omega s ; r = s - omega t ; partials (r, r), (r_hat, r)
@@ -142,9 +196,31 @@ __global__ void __launch_bounds__(kBlock) k_bicg_xr(T* __restrict__ xn, const T*
                                                     const double* __restrict__ ks, long long M,
                                                     double* __restrict__ partials) {
   const T alpha = T(ks[KS_ALPHA]), omega = T(ks[KS_OMEGA]);
+  constexpr int W = Packet<T>::W;
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
   double acc[2] = {0.0, 0.0};
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
-       i += (long long)gridDim.x * blockDim.x) {
+  long long i0 = 0;
+  if (aligned16(xn, x, p, s, t, r, rhat)) {
+    const long long nv = M / W;
+    for (long long j = tid; j < nv; j += stride) {
+      const Lanes<T> xx = pk_load(x, j), pp = pk_load(p, j), ss = pk_load(s, j), tt = pk_load(t, j),
+                     hh = pk_load(rhat, j);
+      Lanes<T> xo, ro;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        xo.v[w] = xx.v[w] + alpha * pp.v[w] + omega * ss.v[w];
+        const T ri = ss.v[w] - omega * tt.v[w];
+        ro.v[w] = ri;
+        acc[0] += double(ri) * double(ri);
+        acc[1] += double(hh.v[w]) * double(ri);
+      }
+      pk_store(xn, j, xo);
+      pk_store(r, j, ro);
+    }
+    i0 = nv * W;
+  }
+  for (long long i = i0 + tid; i < M; i += stride) {
     const T si = s[i];
     xn[i] = x[i] + alpha * p[i] + omega * si;
     const T ri = si - omega * t[i];

@@ -714,17 +714,17 @@ struct Impl {
     s->ts_valid = true;
   }
 
-  // Isotropic model (FP64 solves): the BiCGSTAB directions p and s are
-  // projected onto compatible strains, so the solve runs on J restricted to
-  // compatible fields.  When every voxel is a history tie (the warm start of
-  // an increment: the whole psi0 drives the history) the bordered Jacobian
-  // has a null direction made mostly of incompatible strain; round-off lets
-  // an unprojected solve pick it up with a large amplitude, which the step
-  // projection after the solve cannot undo.
+  // FP64 solves: the BiCGSTAB directions p and s are projected onto
+  // compatible strains, so the solve runs on J restricted to compatible
+  // fields.  At the warm start of an increment many voxels are history ties,
+  // and the bordered Jacobian can have a null direction made mostly of
+  // incompatible strain (found on the 24^3 particle composite, spectral split
+  // and isotropic model alike).  Without the projection, round-off let the
+  // solve pick that direction up with a large amplitude (the step projection
+  // after the solve cannot undo it, since the direction's compatible part
+  // alone is not null) whenever the Krylov trajectory happened to meet it.
   static void keep_compatible(pff_solver* s, TW* x) {
-    if constexpr (std::is_same<TW, double>::value) {
-      if (s->mat.iso) project_strain(s, x);
-    }
+    if constexpr (std::is_same<TW, double>::value) project_strain(s, x);
   }
 
   static void reduce_ks(pff_solver* s, int nslot, int which) {
