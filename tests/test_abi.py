@@ -100,9 +100,18 @@ def test_invalid_arguments_rejected_before_device_work():
     assert lib.pff_create(None, None, 0, None, None, None, None, C.byref(h)) == L.PFF_ERR_ARG
     pid = (C.c_ubyte * 64)()
     ok_phase = [L.pff_phase(1.0, 0.3, 1e-3)]
-    # grid sizes with a factor 5 (no radix-5 FFT)
-    st, h = _create(L.pff_grid(10, 8, 1), ok_phase, pid, _params())
+    # grid lengths above the 512 limit of the FFT tiles, and below the minimum
+    big = (C.c_ubyte * (1024 * 8))()
+    st, h = _create(L.pff_grid(1024, 8, 1), ok_phase, big, _params())
     assert st == L.PFF_ERR_ARG and not h.value
+    st, h = _create(L.pff_grid(1, 8, 1), ok_phase, pid, _params())
+    assert st == L.PFF_ERR_ARG and not h.value
+    # unknown model and control options
+    for opt in ("split", "projection", "control", "precision"):
+        st, h = _create(L.pff_grid(8, 8, 1), ok_phase, pid, _params(**{opt: 7}))
+        assert st == L.PFF_ERR_ARG, opt
+    st, h = _create(L.pff_grid(8, 8, 1), ok_phase, pid, _params(w_gamma=-1.0))
+    assert st == L.PFF_ERR_ARG
     # too many phases
     st, h = _create(L.pff_grid(8, 8, 1), ok_phase * 17, pid, _params())
     assert st == L.PFF_ERR_ARG
