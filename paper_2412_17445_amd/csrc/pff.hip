@@ -714,15 +714,17 @@ struct Impl {
     s->ts_valid = true;
   }
 
-  // FP64 solves: the BiCGSTAB directions p and s are projected onto
-  // compatible strains, so the solve runs on J restricted to compatible
-  // fields.  At the warm start of an increment many voxels are history ties,
-  // and the bordered Jacobian can have a null direction made mostly of
-  // incompatible strain (found on the 24^3 particle composite, spectral split
-  // and isotropic model alike).  Without the projection, round-off let the
-  // solve pick that direction up with a large amplitude (the step projection
-  // after the solve cannot undo it, since the direction's compatible part
-  // alone is not null) whenever the Krylov trajectory happened to meet it.
+  // FP64 solves: the BiCGSTAB direction p is projected onto compatible
+  // strains after each update.  At the warm start of an increment many voxels
+  // are history ties, and the bordered Jacobian can have a null direction made
+  // mostly of incompatible strain (found on the 24^3 particle composite,
+  // spectral split and isotropic model alike).  The update p = r + beta (p -
+  // omega v) carries the incompatible round-off of p forward with the factor
+  // beta every iteration, and the damage rows see it through b : w, so it can
+  // grow into that direction; the step projection after the solve cannot
+  // undo it, since the direction's compatible part alone is not null.  Every
+  // other vector only picks up round-off additively (the strain rows of J v
+  // lie in the range of G), so projecting p suffices.
   static void keep_compatible(pff_solver* s, TW* x) {
     if constexpr (std::is_same<TW, double>::value) project_strain(s, x);
   }
@@ -787,7 +789,6 @@ struct Impl {
           issued = false;
           k_bicg_s<TW><<<g1, kBlock, 0, s->stream>>>(sv, r, v, ks, M);
           LAUNCH_CHECK();
-          keep_compatible(s, sv);
           apply_fused(s, 2, 0, sv, nullptr, nullptr, nullptr, t, sv);
         } else {
           k_bicg_p<TW><<<g1, kBlock, 0, s->stream>>>(p, r, v, ks, M);
@@ -799,7 +800,6 @@ struct Impl {
           reduce_ks(s, 1, 2);
           k_bicg_s<TW><<<g1, kBlock, 0, s->stream>>>(sv, r, v, ks, M);
           LAUNCH_CHECK();
-          keep_compatible(s, sv);
           apply(s, sv, t);
           k_dots<TW, 2><<<g1, kBlock, 0, s->stream>>>(t, sv, t, t, nullptr, nullptr, M, s->part0);
           LAUNCH_CHECK();
