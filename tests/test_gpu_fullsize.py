@@ -1,0 +1,117 @@
+"""Parity and properties at the full benchmark sizes, in the launch
+configuration bench.py times: the 64^2 cracked cell and the 256^2 fibre
+composite in FP64, the 64^3 porous RVE and the 128^3 particle composite in
+mixed precision (FP32 tangent, FP64 residual).
+
+* Residual and tangent action on a seeded frozen state of the full grid,
+  element by element against the oracle (FP64 1e-11, FP32 tangent 2e-5;
+  the FP64 residual also in mixed mode).
+* One crack-length increment from the bootstrap (the bench's first
+  increment): it converges, its committed state is a root of the GPU's own
+  FP64 residual with a compatible strain fluctuation, the constraint holds,
+  and at 128^3 the mixed solver's increment equals the plain FP64 solver's
+  to the mixed bar 1e-5.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import fourier as fo
+from oracle.system import System
+from synth import problem_config, random_state, random_vector
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
+
+
+def frozen_state(sysm, seed):
+    """Seeded state with the history away from ties (half the voxels loading)."""
+    eps, phi, _, E = random_state(sysm.shape, sysm.ncomp, seed, f_mandel=sysm.f, E=0.01)
+    eps_t = fo.G_mandel(eps - sysm.fE(E))
+    st = sysm.point(eps_t + sysm.fE(E), phi, np.zeros(sysm.shape))
+    rng = np.random.default_rng(seed + 1)
+    Hn = st["psi_p"] * np.where(rng.uniform(size=sysm.shape) < 0.5, 0.7, 1.3)
+    phi = np.where(sysm.m > 0, 1.0, phi)
+    return eps_t, phi, E, Hn
+
+
+@pytest.mark.parametrize("case", ["crack2d_64", "fibres2d_256", "pores3d_64", "particles3d_128"])
+def test_residual_and_tangent_at_full_size(case):
+    from paper_2412_17445_amd import Solver
+    prob = problem_config(case)
+    sysm = System(prob)
+    eps_t, phi, E, Hn = frozen_state(sysm, 21)
+    a = 5.0
+    s = Solver.from_problem(prob)
+    s.set_state(eps_t, phi, Hn, E, a - 1.0, n=1)
+    F, gam, sig, dis = s.residual(a)
+    R = sysm.residual(eps_t, phi, E, Hn, a)
+    F = F.cpu().numpy()
+    c, N = sysm.ncomp, sysm.N
+    print(case, "F1 %.2e F2 %.2e" % (rel(F[: c * N], R["F1"].ravel()),
+                                     rel(F[c * N:(c + 1) * N], R["F2"].ravel())), flush=True)
+    assert rel(F[: c * N], R["F1"].ravel()) < 1e-11
+    assert rel(F[c * N:(c + 1) * N], R["F2"].ravel()) < 1e-11
+    assert abs(gam - R["Gamma"]) <= 1e-12 * abs(R["Gamma"])
+    sM = R["sigma_M"]
+    assert rel(sig, [sM[0, 0], sM[1, 1], sM[2, 2], sM[1, 2], sM[0, 2], sM[0, 1]]) < 1e-12
+    del R
+    v = random_vector(N * (c + 1) + 1, 22) * 1e-3
+    ref = sysm.tangent(eps_t, phi, E, Hn)(v)
+    dt = torch.float32 if prob.precision == "mixed" else torch.float64
+    Jv = s.apply(torch.tensor(v, dtype=dt, device="cuda")).double().cpu().numpy()
+    tol = 1e-11 if prob.precision == "fp64" else 2e-5
+    e1, e2 = rel(Jv[: c * N], ref[: c * N]), rel(Jv[c * N:(c + 1) * N], ref[c * N:(c + 1) * N])
+    print(case, prob.precision, "J1 %.2e J2 %.2e" % (e1, e2), flush=True)
+    assert e1 < tol and e2 < tol
+    s.close()
+
+
+def _compatible(s, eps_total, E, f, shape):
+    c = s.ncomp
+    fm = (np.array([f[0, 0], f[1, 1], np.sqrt(2.0) * f[0, 1]]) if c == 3 else
+          np.array([f[0, 0], f[1, 1], f[2, 2], np.sqrt(2.0) * f[1, 2], np.sqrt(2.0) * f[0, 2],
+                    np.sqrt(2.0) * f[0, 1]]))
+    eps_t = eps_total.reshape((c,) + shape) - fm.reshape((c, 1, 1, 1)) * E
+    x = np.zeros((c + 1,) + shape)
+    x[:c] = eps_t
+    Gx = s.project(torch.tensor(x.reshape(-1), dtype=torch.float64, device="cuda"))
+    Gx = Gx.cpu().numpy().reshape(x.shape)[:c]
+    return np.linalg.norm(eps_t - Gx) / np.linalg.norm(eps_t)
+
+
+@pytest.mark.parametrize("case", ["fibres2d_256", "particles3d_128"])
+def test_first_increment_at_full_size(case):
+    from paper_2412_17445_amd import Solver
+    prob = problem_config(case)
+    s = Solver.from_problem(prob)
+    a0, _ = s.bootstrap()
+    out = s.step()
+    print(case, {k: out[k] for k in ("converged", "newton_iters", "krylov_iters", "E", "Gamma",
+                                     "refinements", "fp64_fallbacks")}, flush=True)
+    assert out["converged"]
+    assert abs(out["Gamma"] - (a0 + prob.delta_a)) <= prob.newton_tol * (a0 + prob.delta_a)
+    eps, phi, Hn, E, a = s.get_state()
+    assert E == out["E"] and (Hn >= 0).all() and (phi <= 1 + 1e-12).all()
+    F, _, _, _ = s.residual(a)
+    F = F.cpu().numpy()
+    c, N = s.ncomp, s.N
+    smax = np.abs(np.array(out["sigma_M"])).max()
+    assert np.abs(F[: c * N]).max() <= 1e-6 * smax                 # equilibrium (Newton tol 1e-8)
+    assert abs(F[-1]) <= 1e-8 * a
+    assert _compatible(s, eps, E, np.asarray(prob.f), prob.shape) <= 1e-10
+    s.close()
+    if prob.precision == "mixed":
+        ref = Solver.from_problem(prob, precision="fp64")
+        ref.bootstrap()
+        r = ref.step()
+        assert r["converged"]
+        for k in ("E", "Gamma"):
+            assert abs(out[k] - r[k]) <= 1e-5 * abs(r[k]), (k, out[k], r[k])
+        sm, so = np.array(out["sigma_M"]), np.array(r["sigma_M"])
+        assert np.abs(sm - so).max() <= 1e-5 * np.abs(so).max()
+        ref.close()
