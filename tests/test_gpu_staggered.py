@@ -225,3 +225,31 @@ def test_argument_and_state_errors():
     assert out["converged"] and out["E"] == 0.0
     assert out["stagger_iters"] == 1 and max(abs(v) for v in out["sigma_M"]) == 0.0
     s.close()
+
+
+@pytest.mark.gpu
+def test_crack_length_control_follows_the_snap_back_that_strain_control_jumps():
+    """The paper's motivation (Sec. 2.3, Sec. 5.2) on the 16^2 cracked cell:
+    under crack-length control the load factor rises to a maximum and then
+    falls while the crack grows by delta_a per increment (a snap-back); a
+    strain-controlled staggered increment to just above that maximum finds
+    no neighbouring equilibrium and the crack runs through the cell at once."""
+    from synth import problem_config
+    prob = problem_config("tiny16")
+    s = _solver(prob)
+    E, G = [], []
+    for _ in range(16):
+        o = s.step()
+        assert o["converged"]
+        E.append(o["E"])
+        G.append(o["Gamma"])
+    s.close()
+    assert np.allclose(np.diff(G), prob.delta_a, rtol=1e-7)
+    k = int(np.argmax(E))
+    assert 0 < k < len(E) - 2 and E[-1] < E[k] * (1 - 1e-3), E       # interior maximum, then softening
+    st = _solver(prob)
+    jump = st.stagger_step(1.02 * E[k])
+    st.close()
+    assert jump["converged"]
+    # the crack-length path reaches Gamma[k] at E_max; strain control jumps far past it
+    assert jump["Gamma"] > G[-1] + 1.0, (jump["Gamma"], G[k], G[-1])
