@@ -167,3 +167,41 @@ def G_mandel(m, scheme="rotated"):
 def laplacian(phi):
     """Spectral Laplacian with standard frequencies, Nyquist kept."""
     return ifftn(laplacian_symbol(phi.shape) * fftn(phi)).real
+
+
+def fd_laplacian_symbol(shape):
+    """Symbol of the finite-difference Laplacian sum_j (u_{i+e_j} - 2 u_i +
+    u_{i-e_j}): -sum_j 4 sin^2(q_j / 2)."""
+    nz, ny, nx = shape
+    out = np.zeros(shape)
+    for n, sh in ((nx, (1, 1, nx)), (ny, (1, ny, 1)), (nz, (nz, 1, 1))):
+        q = 2.0 * np.pi * np.fft.fftfreq(n)
+        out = out - (4.0 * np.sin(q / 2.0) ** 2).reshape(sh)
+    return out
+
+
+def fd_laplacian(phi):
+    return ifftn(fd_laplacian_symbol(phi.shape) * fftn(phi)).real
+
+
+def face_average(k, axis_xyz):
+    """k on the faces between voxel i and its upper neighbour along an axis:
+    the arithmetic mean of the two voxels."""
+    ax = {0: 2, 1: 1, 2: 0}[axis_xyz]
+    return 0.5 * (k + np.roll(k, -1, axis=ax))
+
+
+def div_k_grad(u, k):
+    """Finite-difference div(k grad u) on the periodic grid (the variational
+    form of the heterogeneous-toughness term): forward differences of u,
+    times k on the faces (mean of the two voxels), backward differences of
+    the fluxes.  Symmetric and negative semi-definite; with constant k it is
+    k times the finite-difference Laplacian."""
+    out = np.zeros(u.shape)
+    for j in range(3):
+        ax = {0: 2, 1: 1, 2: 0}[j]
+        if u.shape[ax] == 1:
+            continue
+        flux = face_average(k, j) * (np.roll(u, -1, axis=ax) - u)
+        out += flux - np.roll(flux, 1, axis=ax)
+    return out

@@ -67,7 +67,7 @@ class Solver:
         if not np.any(s.m):
             return np.zeros(s.shape), {"iters": 0}
         l, m = s.l, s.m
-        B = lambda u: u / l - l * fo.laplacian(u)                # noqa: E731
+        B = lambda u: u / l - l * s.lap(u)                       # noqa: E731
         op = lambda x: ((1 - m) * B((1 - m) * x.reshape(s.shape))).ravel()  # noqa: E731
         rhs = (-(1 - m) * B(m)).ravel()
         u, info = krylov.cg(op, rhs, rtol=1e-14, maxit=20000)

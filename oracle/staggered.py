@@ -59,6 +59,8 @@ class StaggeredSolver:
                  max_newton=50, cg_maxit=20000):
         self.sys = System(prob)
         s = self.sys
+        if s.var:
+            raise ValueError("the staggered oracle uses the pointwise toughness term")
         self.dE = float(dE)
         self.tol_mech, self.tol_sta = tol_mech, tol_sta
         self.cg_rtol, self.cg_maxit = cg_rtol, cg_maxit

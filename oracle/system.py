@@ -57,8 +57,20 @@ class System:
         # the dissipation D = integral of Gc gamma_f (eq. `SystemDis`, last line);
         # the two coincide up to the factor Gc for homogeneous toughness
         self.dctl = getattr(prob, "control", "length") == "dissipation"
+        # heterogeneous toughness in the damage equation: the printed Gc l Lap phi
+        # (pointwise Gc) or the variational l div(Gc grad phi)
+        self.var = getattr(prob, "gc_form", "pointwise") == "variational"
+        if self.var and self.dctl:
+            raise ValueError("the variational toughness term is built for crack-length control only")
         self.f = fo.to_mandel(np.asarray(prob.f, dtype=np.float64)[:, :, None, None, None],
                               self.ncomp)[:, 0, 0, 0]
+
+    def lap(self, u):
+        """The Laplacian of the crack functional.  With the variational
+        toughness term the crack density uses the same finite differences as
+        div(Gc grad phi) (symbol -sum 4 sin^2(q/2)); otherwise the spectral
+        Laplacian with the Nyquist mode kept."""
+        return fo.fd_laplacian(u) if self.var else fo.laplacian(u)
 
     # -- helpers -----------------------------------------------------------
     def fE(self, E):
@@ -70,7 +82,7 @@ class System:
     def gamma(self, phi):
         """Crack length/area Gamma(phi) (eq. `CrackLenght`, spectral form)."""
         l = self.l
-        return float(np.sum(phi * phi / (2.0 * l) - 0.5 * l * phi * fo.laplacian(phi)))
+        return float(np.sum(phi * phi / (2.0 * l) - 0.5 * l * phi * self.lap(phi)))
 
     def controlled(self, phi):
         """The controlled quantity: Gamma, or D for dissipation control."""
@@ -80,16 +92,17 @@ class System:
         """D = integral of Gc gamma_f (eq. `JaviGc`, middle form; unit voxels),
         gamma_f in the spectral form of `gamma`."""
         l = self.l
-        return float(np.sum(self.Gc * (phi * phi / (2.0 * l) - 0.5 * l * phi * fo.laplacian(phi))))
+        return float(np.sum(self.Gc * (phi * phi / (2.0 * l) - 0.5 * l * phi * self.lap(phi))))
 
     # -- residual (eq. System_CrackLength) ---------------------------------
     def residual(self, eps_t, phi, E, Hn, a):
         eps = eps_t + self.fE(E)
         st = self.point(eps, phi, Hn)
         F1 = fo.to_mandel(fo.G_tensor(st["sigma"], self.scheme), self.ncomp)
-        lap = fo.laplacian(phi)
+        lap = self.lap(phi)
         l, Gc, H = self.l, self.Gc, st["H"]
-        F2 = (1.0 - self.m) * ((Gc / l + 2.0 * H) * phi - Gc * l * lap - 2.0 * H)
+        gterm = l * fo.div_k_grad(phi, Gc) if self.var else Gc * l * lap
+        F2 = (1.0 - self.m) * ((Gc / l + 2.0 * H) * phi - gterm - 2.0 * H)
         dens = phi * phi / (2.0 * l) - 0.5 * l * phi * lap
         gam = float(np.sum(dens))
         Q = float(np.sum(Gc * dens)) if self.dctl else gam
@@ -106,7 +119,7 @@ class System:
         l, Gc, m = self.l, self.Gc, self.m
         b = -2.0 * (1.0 - phi) * st["sigma0p"]          # d sigma / d phi
         A = Gc / l + 2.0 * st["H"]
-        r = phi / l - l * fo.laplacian(phi)
+        r = phi / l - l * self.lap(phi)
         # gradient of the controlled quantity: dGamma/dphi = r; with dissipation
         # control dD/dphi = Gc phi/l - (l/2) (Gc Lap phi + Lap(Gc phi)) (the
         # Laplacian is symmetric, Gc is not constant)
@@ -123,8 +136,8 @@ class System:
             tau = pl.tangent_apply(st, w) + b * dphi_f
             J1 = fo.to_mandel(fo.G_tensor(tau, self.scheme), c)
             bw = np.einsum("ij...,ij...->...", b, w)
-            J2 = (1.0 - m) * (st["chi"] * bw + A * dphi_f
-                              - Gc * l * fo.laplacian(dphi_f)) + m * d_phi
+            gterm = l * fo.div_k_grad(dphi_f, Gc) if self.var else Gc * l * fo.laplacian(dphi_f)
+            J2 = (1.0 - m) * (st["chi"] * bw + A * dphi_f - gterm) + m * d_phi
             J3 = self.wa * np.sum(rq * dphi_f) + self.wE * dE
             return np.concatenate([J1.ravel(), J2.ravel(), [J3]])
 

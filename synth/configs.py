@@ -53,6 +53,7 @@ class Problem:
     projection: str = "rotated"          # "rotated" (Willot) or "standard" frequencies in G
     control_weights: Tuple[float, float] = (1.0, 0.0)   # (w_a, w_E): F3 = w_a Gamma + w_E E - tau
     control: str = "length"              # controlled quantity: "length" (Gamma) or "dissipation" (D)
+    gc_form: str = "pointwise"           # "pointwise" Gc l Lap phi or "variational" l div(Gc grad phi)
     notes: str = ""
     extra: dict = field(default_factory=dict)
 
@@ -74,7 +75,13 @@ def problem_config(name: str) -> Problem:
     Suffixes: "_iso" gives the same problem with the isotropic (no split)
     degradation of Sec. 5.4, "_std" with the standard-frequency projection,
     "_w" with the weighted control 0.7 Gamma + 3 E, "_d" with dissipation
-    control (increment delta_a times the smallest Gc)."""
+    control (increment delta_a times the smallest Gc), "_v" with the
+    variational toughness term l div(Gc grad phi)."""
+    if name.endswith("_v"):
+        prob = problem_config(name[:-2])
+        prob.name, prob.gc_form = name, "variational"
+        prob.notes = (prob.notes + "; " if prob.notes else "") + "variational toughness term"
+        return prob
     if name.endswith("_d"):
         prob = problem_config(name[:-2])
         prob.name, prob.control = name, "dissipation"
