@@ -98,14 +98,23 @@ typedef struct {
  *               (1): the dissipation D = sum of Gc gamma_f takes its place
  *               (eq. SystemDis, last line), with the border row dD/dphi =
  *               Gc phi/l - (l/2)(Gc Lap phi + Lap(Gc phi)).  Equal up to the
- *               factor Gc for homogeneous toughness. */
+ *               factor Gc for homogeneous toughness.
+ *  gc_form      PFF_GC_POINTWISE (0): the printed Gc l Lap phi with pointwise
+ *               Gc; PFF_GC_VARIATIONAL (1): l div(Gc grad phi) in finite
+ *               differences (forward differences, Gc on the faces as the mean
+ *               of the two voxels, backward differences of the fluxes), with
+ *               the crack functional on the same finite-difference Laplacian
+ *               (symbol -sum 4 sin^2(q/2)).  Crack-length or weighted control
+ *               only (not with PFF_CONTROL_DISSIPATION), and not with the
+ *               staggered scheme. */
 typedef struct {
   double l, k_resid, f[9], delta_a, alpha, newton_tol, krylov_rtol;
-  int newton_maxit, krylov_maxit, precision, split, projection, control;
+  int newton_maxit, krylov_maxit, precision, split, projection, control, gc_form;
   double w_gamma, w_load;
 } pff_params;
 
 enum { PFF_CONTROL_LENGTH = 0, PFF_CONTROL_DISSIPATION = 1 };
+enum { PFF_GC_POINTWISE = 0, PFF_GC_VARIATIONAL = 1 };
 
 enum { PFF_SPLIT_SPECTRAL = 0, PFF_SPLIT_NONE = 1 };
 enum { PFF_PROJ_ROTATED = 0, PFF_PROJ_STANDARD = 1 };

@@ -171,6 +171,10 @@ struct pff_solver {
   double a = 0.0, E = 0.0, E_s = 0.0;   // a: control value tau
   double wa = 1.0, wE = 0.0;              // control weights (tau = wa Q + wE E)
   bool dctl = false;                      // Q = D (dissipation) instead of Gamma
+  bool var = false;                       // variational toughness term (finite differences)
+  bool var_het = false;                   // ... with more than one toughness (stencil kernel needed)
+  double* lgc64 = nullptr;                // l div(Gc grad .) of the last input (N)
+  float* lgc32 = nullptr;
   long long applies = 0, kiters = 0;
   std::string err;
 
@@ -198,6 +202,9 @@ template <> float* tstate<float>(pff_solver* s) { return s->ts32; }
 template <typename T> T* auxf(pff_solver* s);
 template <> double* auxf<double>(pff_solver* s) { return s->aux64; }
 template <> float* auxf<float>(pff_solver* s) { return s->aux32; }
+template <typename T> T* lgcf(pff_solver* s);
+template <> double* lgcf<double>(pff_solver* s) { return s->lgc64; }
+template <> float* lgcf<float>(pff_solver* s) { return s->lgc32; }
 
 template <> const DevTables<double>& pff_solver::tables<double>() const { return td; }
 template <> const DevTables<float>& pff_solver::tables<float>() const { return tf; }
@@ -389,6 +396,36 @@ __global__ void k_helm_rhs(double* __restrict__ b, const double* __restrict__ H,
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     b[i] = m[i] ? 0.0 : (H ? 2.0 * fabs(H[i]) / mat.Gc[pid[i]] : 0.0) - b[i];
+}
+
+// Finite-difference l div(Gc grad u) of the variational toughness term:
+// forward differences of u (masked: u = 0 on the crack mask when mask_in),
+// Gc on the faces as the mean of the two voxels, backward differences of
+// the fluxes; periodic.  The input u is `in` at stride 1.
+template <typename T>
+__global__ void k_div_gc_grad(T* __restrict__ out, const T* __restrict__ in, const uint8_t* __restrict__ pid,
+                              const uint8_t* __restrict__ mask, int mask_in, Material mat, double l, int nx,
+                              int ny, int nz, long long N) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % nx);
+    const long long yz = i / nx;
+    const int y = (int)(yz % ny), z = (int)(yz / ny);
+    auto val = [&](long long j) -> double { return (mask_in && mask[j]) ? 0.0 : double(in[j]); };
+    const double ui = val(i), gi = mat.Gc[pid[i]];
+    double acc = 0.0;
+    const long long nb[3][2] = {
+        {i - x + (x + 1 == nx ? 0 : x + 1), i - x + (x == 0 ? nx - 1 : x - 1)},
+        {i + (long long)((y + 1 == ny ? 0 : y + 1) - y) * nx, i + (long long)((y == 0 ? ny - 1 : y - 1) - y) * nx},
+        {i + (long long)((z + 1 == nz ? 0 : z + 1) - z) * nx * ny,
+         i + (long long)((z == 0 ? nz - 1 : z - 1) - z) * nx * ny}};
+    for (int a = 0; a < 3; ++a) {
+      if ((a == 0 && nx == 1) || (a == 1 && ny == 1) || (a == 2 && nz == 1)) continue;
+      const long long up = nb[a][0], dn = nb[a][1];
+      acc += 0.5 * (gi + mat.Gc[pid[up]]) * (val(up) - ui) - 0.5 * (gi + mat.Gc[pid[dn]]) * (ui - val(dn));
+    }
+    out[i] = T(l * acc);
+  }
 }
 
 // per-block partials: max |x_i| over the first n entries
@@ -585,6 +622,17 @@ struct Impl {
   static TW* vec(pff_solver* s, int k) { return vecs<TW>(s, k); }
   enum { X0 = 0, X1, X2, R, RHAT, P, V, S, T, RHS, SOL, VB, VD };
 
+  // variational toughness term of the damage block of the input (d phi' =
+  // (1-m) d phi), before the pipeline that consumes it
+  static const TW* var_term(pff_solver* s, const TW* v) {
+    if (!s->var_het) return nullptr;
+    TW* out = lgcf<TW>(s);
+    k_div_gc_grad<TW><<<grid1(s->N), kBlock, 0, s->stream>>>(out, v + (long long)C * s->N, s->pid, s->mask, 1,
+                                                             s->mat, s->prm.l, s->nx, s->ny, s->nz, s->N);
+    LAUNCH_CHECK();
+    return out;
+  }
+
   static void fill_tangent_args(pff_solver* s, typename TangentPipe<TW, DIM>::Args& A) {
     A.g = s->g;
     A.mat = s->mat;
@@ -610,6 +658,7 @@ struct Impl {
     A.mode = mode;
     A.pro = pro;
     A.mech = 0;
+    A.lgc = pro ? nullptr : var_term(s, v);   // pro modes are off with the variational term
     A.r = r;
     A.w = w;
     A.vout = vout;
@@ -636,6 +685,7 @@ struct Impl {
     A.mode = 0;
     A.pro = 0;
     A.mech = mech;
+    A.lgc = var_term(s, v);
     A.r = A.w = A.dv = nullptr;
     A.vout = nullptr;
     A.ks = nullptr;
@@ -675,6 +725,13 @@ struct Impl {
     A.tab = spec_tables<double>(s);
     A.lap_ext = nullptr;
     A.lapg = nullptr;
+    A.lgc = nullptr;
+    if (s->var_het) {
+      k_div_gc_grad<double><<<grid1(s->N), kBlock, 0, s->stream>>>(s->lgc64, s->phi, s->pid, s->mask, 0,
+                                                                   s->mat, s->prm.l, s->nx, s->ny, s->nz, s->N);
+      LAUNCH_CHECK();
+      A.lgc = s->lgc64;
+    }
     if (DIM == 2) {
       LapPipe::Args LA;
       LA.g = s->g;
@@ -1284,7 +1341,9 @@ void upload_tables(pff_solver* s, DevTables<T>& t) {
         hs[j] = T(sinl(half));
         hc[j] = nyq ? T(0) : T(cosl(half));
       }
-      q2[j] = T(q * q);
+      // Laplacian symbol: spectral (Nyquist kept), or the finite-difference
+      // one of the variational toughness term, 4 sin^2(q/2)
+      q2[j] = s->prm.gc_form == PFF_GC_VARIATIONAL ? T(4.0L * sinl(half) * sinl(half)) : T(q * q);
     }
     t.tw[a] = s->alloc<cpx<T>>(n);
     t.hs[a] = s->alloc<T>(n);
@@ -1406,6 +1465,10 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
       throw Fail("invalid solver parameters", PFF_ERR_ARG);
     if (p.control != PFF_CONTROL_LENGTH && p.control != PFF_CONTROL_DISSIPATION)
       throw Fail("invalid solver parameters", PFF_ERR_ARG);
+    if ((p.gc_form != PFF_GC_POINTWISE && p.gc_form != PFF_GC_VARIATIONAL) ||
+        (p.gc_form == PFF_GC_VARIATIONAL && p.control == PFF_CONTROL_DISSIPATION))
+      throw Fail("invalid solver parameters", PFF_ERR_ARG);
+    s->var = p.gc_form == PFF_GC_VARIATIONAL;
     s->dctl = p.control == PFF_CONTROL_DISSIPATION;
     if (p.w_gamma == 0.0 && p.w_load == 0.0) {
       s->wa = 1.0;                                    // crack-length control
@@ -1437,6 +1500,13 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
       s->mat.mu[k] = E / (2 * (1 + nu));
       s->mat.Gc[k] = phases[k].Gc;
     }
+    {
+      bool het = false;
+      for (int k = 1; k < n_phases; ++k) het = het || phases[k].Gc != phases[0].Gc;
+      // with one toughness the variational term is Gc times the (finite-
+      // difference) Laplacian of the pipelines; otherwise the stencil kernel
+      s->var_het = params->gc_form == PFF_GC_VARIATIONAL && het;
+    }
     s->h_pid.assign(phase_id, phase_id + s->N);
     for (uint8_t v : s->h_pid)
       if (v >= n_phases) throw Fail("phase id out of range", PFF_ERR_ARG);
@@ -1460,6 +1530,7 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     s->x_rows = envi("PFF_X_ROWS", 64);
     s->xcd_remap = envi("PFF_XCD_REMAP", 1) != 0 ? 1 : 0;
     s->fused = std::min(2, std::max(0, envi("PFF_FUSED", 1)));
+    if (s->var_het) s->fused = std::min(s->fused, 1);   // the variational term needs the input before the pass
     {
       const char* v = std::getenv("PFF_INNER32");
       s->inner32 = v ? std::atof(v) : kInner32;
@@ -1485,10 +1556,12 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     const size_t nts = (size_t)(s->dim == 2 ? TsLayout<2>::COUNT : TsLayout<3>::COUNT) * N;
     s->ts64 = s->alloc<double>(nts);
     s->aux64 = s->alloc<double>(N);
+    s->lgc64 = s->alloc<double>(N);
     for (int k = 0; k < kNumVec; ++k) s->kv64[k] = s->alloc<double>(M);
     if (s->mixed()) {
       s->ts32 = s->alloc<float>(nts);
       s->aux32 = s->alloc<float>(N);
+      s->lgc32 = s->alloc<float>(N);
       for (int k = 0; k < kNumVec; ++k) s->kv32[k] = s->alloc<float>(M);
     }
     s->spec_d = s->alloc<cpx<double>>((size_t)(C + 1) * s->Nh);
@@ -1735,6 +1808,7 @@ pff_status pff_stagger_defaults(pff_stagger_params* p) {
 pff_status pff_stagger_step(pff_solver* s, double dE, const pff_stagger_params* params, pff_stagger_result* out) {
   return guarded(s, [&]() -> pff_status {
     if (!s->bootstrapped) throw Fail("pff_stagger_step before pff_bootstrap/pff_set_state", PFF_ERR_STATE);
+    if (s->var) throw Fail("pff_stagger_step: the staggered scheme uses the pointwise toughness term", PFF_ERR_ARG);
     pff_stagger_params sp;
     pff_stagger_defaults(&sp);
     if (params) sp = *params;
@@ -1951,8 +2025,8 @@ pff_status pff_footprint_bytes(const pff_grid* grid, int precision, size_t* byte
   b += 6 * N * D;                                     // phi, committed phi, guess, mask, Hn, H
   if (dim == 2) b += N * D;                           // Laplacian of phi
   b += 4 * D;                                         // E
-  b += nts * D + N * D + kNumVec * M * D;             // tangent state, aux, Krylov vectors
-  if (mixed) b += nts * F + N * F + kNumVec * M * F;
+  b += nts * D + 2 * N * D + kNumVec * M * D;         // tangent state, aux, variational term, Krylov vectors
+  if (mixed) b += nts * F + 2 * N * F + kNumVec * M * F;
   b += (C + 1) * Nh * 2 * D;                          // FP64 spectra
   if (mixed) b += (C + 1) * Nh * 2 * F;               // FP32 spectra
   const size_t part_len = std::max<size_t>(kRedBlocks, ny * nz + 16);

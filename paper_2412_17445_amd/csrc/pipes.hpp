@@ -63,6 +63,7 @@ struct TangentPipe {
     int mode;
     int pro;
     int mech;        // 1: the damage rows of J are zero (mechanical operator G[C:d eps~])
+    const T* lgc;    // variational toughness term l div(Gc grad d phi') of this input, or null
     const T* r;
     const T* w;
     T* vout;
@@ -149,7 +150,8 @@ struct TangentPipe {
     for (int k = 0; k < C; ++k) A.Jv[k * N + i] = in[k];
     const bool m = A.mask[i] != 0;
     const T Gc = T(A.mat.Gc[A.pid[i]]);
-    const T j2 = A.mech ? T(0) : A.aux[i] - (m ? T(0) : Gc * A.l * in[C]);
+    const T gterm = A.lgc ? A.lgc[i] : Gc * A.l * in[C];
+    const T j2 = A.mech ? T(0) : A.aux[i] - (m ? T(0) : gterm);
     A.Jv[C * N + i] = j2;
     if (A.mode == 1) {
 #pragma unroll
@@ -203,6 +205,7 @@ struct ResidualPipe {
     // dissipation control: Lap(Gc phi), for the border row dD/dphi =
     // Gc phi/l - (l/2) (Gc Lap phi + Lap(Gc phi)); null for crack-length control
     const double* lapg;
+    const double* lgc;        // variational toughness term l div(Gc grad phi), or null
   };
 
   __device__ static void prologue(const Args& A, long long i, double* out, double* red) {
@@ -282,7 +285,8 @@ struct ResidualPipe {
     const double H = fabs(A.Hcur[i]);
     const double lap = A.lap_ext ? A.lap_ext[i] : in[C];
     const double l = A.l;
-    const double F2 = m ? 0.0 : (Gc / l + 2.0 * H) * phi - Gc * l * lap - 2.0 * H;
+    const double gterm = A.lgc ? A.lgc[i] : Gc * l * lap;
+    const double F2 = m ? 0.0 : (Gc / l + 2.0 * H) * phi - gterm - 2.0 * H;
     const double r = A.lapg ? Gc * phi / l - 0.5 * l * (Gc * lap + A.lapg[i]) : phi / l - l * lap;
     A.ts[L::R * N + i] = r;
     if (A.ts32) A.ts32[L::R * N + i] = float(r);

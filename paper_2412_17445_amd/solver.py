@@ -30,12 +30,15 @@ def _torch():
 def marshal_problem(shape, phases, phase_id, mask, f, l, k=1e-6, delta_a=1.0, alpha=1.0,
                     newton_tol=1e-8, krylov_rtol=1e-10, newton_maxit=50, krylov_maxit=5000,
                     precision="fp64", split="spectral", projection="rotated",
-                    control_weights=(1.0, 0.0), control="length"):
+                    control_weights=(1.0, 0.0), control="length", gc_form="pointwise"):
     """C structs and host arrays of one RVE problem (pff_create's inputs).
     split: "spectral" (Miehe split) or "none" (isotropic degradation);
     projection: "rotated" (Willot) or "standard" frequencies in G;
     control_weights: (w_a, w_E) of the controlled quantity w_a Q + w_E E;
-    control: Q is "length" (Gamma) or "dissipation" (sum of Gc gamma_f)."""
+    control: Q is "length" (Gamma) or "dissipation" (sum of Gc gamma_f);
+    gc_form: "pointwise" Gc l Lap phi or "variational" l div(Gc grad phi)."""
+    if gc_form not in ("pointwise", "variational"):
+        raise ValueError("gc_form must be 'pointwise' or 'variational'")
     if control not in ("length", "dissipation"):
         raise ValueError("control must be 'length' or 'dissipation'")
     if split not in ("spectral", "none"):
@@ -62,6 +65,7 @@ def marshal_problem(shape, phases, phase_id, mask, f, l, k=1e-6, delta_a=1.0, al
     prm.projection = L.PFF_PROJ_STANDARD if projection == "standard" else L.PFF_PROJ_ROTATED
     prm.w_gamma, prm.w_load = (float(w) for w in control_weights)
     prm.control = L.PFF_CONTROL_DISSIPATION if control == "dissipation" else L.PFF_CONTROL_LENGTH
+    prm.gc_form = L.PFF_GC_VARIATIONAL if gc_form == "variational" else L.PFF_GC_POINTWISE
     return grid, ph, pid, msk, prm
 
 
@@ -73,7 +77,8 @@ def problem_kwargs(prob, **over):
               precision=prob.precision, split=getattr(prob, "split", "spectral"),
               projection=getattr(prob, "projection", "rotated"),
               control_weights=getattr(prob, "control_weights", (1.0, 0.0)),
-              control=getattr(prob, "control", "length"))
+              control=getattr(prob, "control", "length"),
+              gc_form=getattr(prob, "gc_form", "pointwise"))
     kw.update(over)
     return kw
 
@@ -92,7 +97,7 @@ class Solver:
     def __init__(self, shape, phases, phase_id, mask, f, l, k=1e-6, delta_a=1.0, alpha=1.0,
                  newton_tol=1e-8, krylov_rtol=1e-10, newton_maxit=50, krylov_maxit=5000,
                  precision="fp64", split="spectral", projection="rotated",
-                 control_weights=(1.0, 0.0), control="length", stream=None):
+                 control_weights=(1.0, 0.0), control="length", gc_form="pointwise", stream=None):
         torch = _torch()
         self.lib = L.load()
         nz, ny, nx = shape
@@ -106,7 +111,7 @@ class Solver:
             shape, phases, phase_id, mask, f, l, k=k, delta_a=delta_a, alpha=alpha,
             newton_tol=newton_tol, krylov_rtol=krylov_rtol, newton_maxit=newton_maxit,
             krylov_maxit=krylov_maxit, precision=precision, split=split, projection=projection,
-            control_weights=control_weights, control=control)
+            control_weights=control_weights, control=control, gc_form=gc_form)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self._stream = stream
@@ -126,7 +131,8 @@ class Solver:
                   split=getattr(prob, "split", "spectral"),
                   projection=getattr(prob, "projection", "rotated"),
                   control_weights=getattr(prob, "control_weights", (1.0, 0.0)),
-                  control=getattr(prob, "control", "length"))
+                  control=getattr(prob, "control", "length"),
+                  gc_form=getattr(prob, "gc_form", "pointwise"))
         kw.update(over)
         return cls(prob.shape, prob.phases, prob.phase_id, prob.mask, prob.f, prob.l, **kw)
 

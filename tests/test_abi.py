@@ -40,8 +40,8 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts():
     assert C.sizeof(L.pff_grid) == 12
     assert C.sizeof(L.pff_phase) == 24
-    # 2 doubles + f[9] + 4 doubles, 5 ints (+ padding), 2 doubles
-    assert C.sizeof(L.pff_params) == 8 * (2 + 9 + 4) + 4 * 5 + 4 + 8 * 2
+    # 2 doubles + f[9] + 4 doubles, 7 ints (+ padding), 2 doubles
+    assert C.sizeof(L.pff_params) == 8 * (2 + 9 + 4) + 4 * 7 + 4 + 8 * 2
     assert C.sizeof(L.pff_increment_result) == 4 * 4 + 8 * 2 + 4 * 2 + 8 * (6 + 3 + 3 + 2)
 
 
@@ -107,11 +107,13 @@ def test_invalid_arguments_rejected_before_device_work():
     st, h = _create(L.pff_grid(1, 8, 1), ok_phase, pid, _params())
     assert st == L.PFF_ERR_ARG and not h.value
     # unknown model and control options
-    for opt in ("split", "projection", "control", "precision"):
+    for opt in ("split", "projection", "control", "precision", "gc_form"):
         st, h = _create(L.pff_grid(8, 8, 1), ok_phase, pid, _params(**{opt: 7}))
         assert st == L.PFF_ERR_ARG, opt
     st, h = _create(L.pff_grid(8, 8, 1), ok_phase, pid, _params(w_gamma=-1.0))
     assert st == L.PFF_ERR_ARG
+    st, h = _create(L.pff_grid(8, 8, 1), ok_phase, pid, _params(gc_form=1, control=1))
+    assert st == L.PFF_ERR_ARG                    # variational term with dissipation control
     # too many phases
     st, h = _create(L.pff_grid(8, 8, 1), ok_phase * 17, pid, _params())
     assert st == L.PFF_ERR_ARG

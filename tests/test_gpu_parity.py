@@ -146,7 +146,9 @@ def _frozen_state(sysm, seed):
                                               ("gc16_w", None), ("part24_w", (9, 8, 6)),
                                               ("tiny16", (1, 15, 20)), ("tiny16", (1, 39, 39)),
                                               ("part24", (5, 7, 10)), ("part24", (7, 11, 13)),
-                                              ("gc16_d", None), ("part24_d", (9, 8, 6))])
+                                              ("gc16_d", None), ("part24_d", (9, 8, 6)),
+                                              ("tiny16_v", None), ("gc16_v", None), ("part24_v", (9, 8, 6)),
+                                              ("part24_v", (12, 18, 16))])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_residual_and_tangent(name, shape, precision):
     prob = small_problem(name, shape, precision)

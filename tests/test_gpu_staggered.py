@@ -221,6 +221,11 @@ def test_argument_and_state_errors():
         s.stagger_step(float("nan"))
     with pytest.raises(TypeError):
         s.stagger_step(1e-3, tolerance=1.0)
+    sv = Solver.from_problem(problem_config("gc16_v"))
+    sv.bootstrap()
+    with pytest.raises(PffError):
+        sv.stagger_step(1e-3)                 # variational toughness term: pointwise scheme only
+    sv.close()
     out = s.stagger_step(0.0)                 # zero load: the bootstrap state is the solution
     assert out["converged"] and out["E"] == 0.0
     assert out["stagger_iters"] == 1 and max(abs(v) for v in out["sigma_M"]) == 0.0
