@@ -15,6 +15,17 @@ constexpr int kBlock = 256;          // threads per workgroup of vector kernels 
 // (1024-thread, 64 KB blocks left the x-forward pass latency-bound in the
 // solve: 89 us against 55 us per launch at 128^3).
 template <typename T> struct FftThreads { static constexpr int value = 512; };
+
+// The LDS tiles of the x passes are padded by one element every 32: their
+// Stockham stages write outputs at strides of R * Ns elements of contiguous
+// rows, which without the pad fall on few banks (measured: 2.3 bank-conflict
+// cycles per LDS instruction, halved by the pad, and the x-inverse pass's
+// LDS wait cycles halved).  The interleaved tiles of the y/z passes are not
+// padded: their columns already spread the banks, and the extra index
+// arithmetic cost more than it saved there.
+__host__ __device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
+template <bool PAD> __host__ __device__ __forceinline__ int lidx(int i) { return PAD ? lpad(i) : i; }
+__host__ __device__ __forceinline__ long long lds_padded(long long n) { return n + (n >> 5) + 1; }
 constexpr int kMaxPhases = 16;
 constexpr int kMaxRed = 12;          // reduction slots per pass
 constexpr int kMaxStages = 10;

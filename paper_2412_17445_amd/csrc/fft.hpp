@@ -12,7 +12,7 @@
 // unnormalised inverse.  The caller scales by 1/N elsewhere.
 //
 // Layout: element j of sequence q, interleaved column t, sits at
-// (q*n + j)*TX + t.  TX = 1 gives contiguous sequences (x passes); TX > 1
+// lidx<PAD>((q*n + j)*TX + t) (one pad element every 32, common.hpp).  TX = 1 gives contiguous sequences (x passes); TX > 1
 // interleaves TX columns so that a strided-axis tile is loaded and stored
 // with TX contiguous values per row and consecutive threads touch
 // consecutive columns.  Stages run in place: each thread first reads all
@@ -133,7 +133,7 @@ template <typename T, int S, int R> __device__ __forceinline__ void dftR(cpx<T>*
   else dft_odd<T, S, R>(v);
 }
 
-template <typename T, int S, int R, int MAXE>
+template <typename T, int S, int R, int MAXE, bool PAD>
 __device__ __forceinline__ void stockham_stage(cpx<T>* buf, int n, int Ns, int nseq, int ltx,
                                                const cpx<T>* tw, const FastDiv& dnb, const FastDiv& dns) {
   constexpr int MB = (MAXE + R - 1) / R;        // butterflies per thread
@@ -152,7 +152,7 @@ __device__ __forceinline__ void stockham_stage(cpx<T>* buf, int n, int Ns, int n
       const int j = rest - s * nb;
       const int base_in = (s * n + j) * TX + t;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = buf[base_in + r * nb * TX];
+      for (int r = 0; r < R; ++r) v[q][r] = buf[lidx<PAD>(base_in + r * nb * TX)];
     }
   }
   __syncthreads();
@@ -177,7 +177,7 @@ __device__ __forceinline__ void stockham_stage(cpx<T>* buf, int n, int Ns, int n
       // output base (j div Ns) * Ns * R + j mod Ns
       const int base_out = (s * n + (j - kk) * R + kk) * TX + t;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[base_out + r * Ns * TX] = v[q][r];
+      for (int r = 0; r < R; ++r) buf[lidx<PAD>(base_out + r * Ns * TX)] = v[q][r];
     }
   }
   __syncthreads();
@@ -188,7 +188,7 @@ __device__ __forceinline__ void stockham_stage(cpx<T>* buf, int n, int Ns, int n
 // w_{Ns R}^{m (j mod Ns)} w_R^{m r}, one table lookup per term (both factors
 // are powers of w_n: tw[(m (j mod Ns) n/(Ns R) + (m r mod R) n/R) mod n]).
 // All items read before the barrier and write their own element after it.
-template <typename T, int S, int MAXE>
+template <typename T, int S, int MAXE, bool PAD>
 __device__ __forceinline__ void stockham_stage_any(cpx<T>* buf, int n, int R, int Ns, int nseq, int ltx,
                                                 const cpx<T>* tw) {
   const int TX = 1 << ltx;
@@ -207,7 +207,7 @@ __device__ __forceinline__ void stockham_stage_any(cpx<T>* buf, int n, int R, in
       const int kk = o % Ns;
       const int r = (o / Ns) % R;
       const int j = (o / (Ns * R)) * Ns + kk;       // butterfly index
-      const cpx<T>* in = buf + (sq * n + j) * TX + t;
+      const int in0 = (sq * n + j) * TX + t;
       const int d1 = kk * twstep;                   // m kk twstep < n for every m < R
       const int d2 = r * nb;                        // (m r mod R) nb = m r nb mod n
       int e1 = 0, e2 = 0;
@@ -217,7 +217,7 @@ __device__ __forceinline__ void stockham_stage_any(cpx<T>* buf, int n, int R, in
         if (e >= n) e -= n;
         cpx<T> w = tw[e];
         if (S > 0) w.y = -w.y;
-        acc = cadd(acc, cmul(in[m * nb * TX], w));
+        acc = cadd(acc, cmul(buf[lidx<PAD>(in0 + m * nb * TX)], w));
         e1 += d1;
         e2 += d2;
         if (e2 >= n) e2 -= n;
@@ -229,7 +229,7 @@ __device__ __forceinline__ void stockham_stage_any(cpx<T>* buf, int n, int R, in
 #pragma unroll
   for (int q = 0; q < MAXE; ++q) {
     const int idx = threadIdx.x + q * blockDim.x;
-    if (idx < total) buf[idx] = out[q];           // element idx is the item's own output
+    if (idx < total) buf[lidx<PAD>(idx)] = out[q];     // element idx is the item's own output
   }
   __syncthreads();
 }
@@ -249,7 +249,7 @@ constexpr int c_radix(int n, int st) {
 
 // Stage with compile-time length N, radix R and span NS: all strides of the
 // index arithmetic are constants (shifts for powers of two).
-template <typename T, int S, int N, int R, int NS, int MAXE>
+template <typename T, int S, int N, int R, int NS, int MAXE, bool PAD>
 __device__ __forceinline__ void stockham_stage_c(cpx<T>* buf, int nseq, int ltx, const cpx<T>* tw) {
   constexpr int MB = (MAXE + R - 1) / R;
   constexpr int NB = N / R;
@@ -267,7 +267,7 @@ __device__ __forceinline__ void stockham_stage_c(cpx<T>* buf, int nseq, int ltx,
       const int j = rest - s * NB;
       const int base_in = ((s * N + j) << ltx) + t;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = buf[base_in + ((r * NB) << ltx)];
+      for (int r = 0; r < R; ++r) v[q][r] = buf[lidx<PAD>(base_in + ((r * NB) << ltx))];
     }
   }
   __syncthreads();
@@ -291,18 +291,18 @@ __device__ __forceinline__ void stockham_stage_c(cpx<T>* buf, int nseq, int ltx,
       dftR<T, S, R>(v[q]);
       const int base_out = ((s * N + (j - kk) * R + kk) << ltx) + t;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[base_out + ((r * NS) << ltx)] = v[q][r];
+      for (int r = 0; r < R; ++r) buf[lidx<PAD>(base_out + ((r * NS) << ltx))] = v[q][r];
     }
   }
   __syncthreads();
 }
 
-template <typename T, int S, int N, int ST, int NS, int MAXE>
+template <typename T, int S, int N, int ST, int NS, int MAXE, bool PAD>
 __device__ __forceinline__ void fft_c(cpx<T>* buf, int nseq, int ltx, const cpx<T>* tw) {
   if constexpr (ST < c_nstage(N)) {
     constexpr int R = c_radix(N, ST);
-    stockham_stage_c<T, S, N, R, NS, MAXE>(buf, nseq, ltx, tw);
-    fft_c<T, S, N, ST + 1, NS * R, MAXE>(buf, nseq, ltx, tw);
+    stockham_stage_c<T, S, N, R, NS, MAXE, PAD>(buf, nseq, ltx, tw);
+    fft_c<T, S, N, ST + 1, NS * R, MAXE, PAD>(buf, nseq, ltx, tw);
   }
 }
 
@@ -312,16 +312,16 @@ __device__ __forceinline__ void fft_c(cpx<T>* buf, int nseq, int ltx, const cpx<
 // path, every other length the generic one.
 // Must be called by every thread of the block; ends with a barrier.
 // ANY: the kernel may meet radices other than 2, 3, 4 and 8 (generic stage
-// compiled in).  Kernels of 2^a 3^b grids are instantiated without it, so the
+// compiled in).  PAD: the tile is padded (lidx).  Kernels of 2^a 3^b grids are instantiated without it, so the
 // generic stage's registers do not count against their occupancy.
-template <typename T, int S, int MAXE, bool ANY = false>
+template <typename T, int S, int MAXE, bool ANY, bool PAD>
 __device__ void fft_lds(cpx<T>* buf, int nseq, int ltx, const AxisPlan& pl, const cpx<T>* tw) {
   switch (pl.n) {
-    case 32: fft_c<T, S, 32, 0, 1, MAXE>(buf, nseq, ltx, tw); return;
-    case 64: fft_c<T, S, 64, 0, 1, MAXE>(buf, nseq, ltx, tw); return;
-    case 128: fft_c<T, S, 128, 0, 1, MAXE>(buf, nseq, ltx, tw); return;
-    case 256: fft_c<T, S, 256, 0, 1, MAXE>(buf, nseq, ltx, tw); return;
-    case 512: fft_c<T, S, 512, 0, 1, MAXE>(buf, nseq, ltx, tw); return;
+    case 32: fft_c<T, S, 32, 0, 1, MAXE, PAD>(buf, nseq, ltx, tw); return;
+    case 64: fft_c<T, S, 64, 0, 1, MAXE, PAD>(buf, nseq, ltx, tw); return;
+    case 128: fft_c<T, S, 128, 0, 1, MAXE, PAD>(buf, nseq, ltx, tw); return;
+    case 256: fft_c<T, S, 256, 0, 1, MAXE, PAD>(buf, nseq, ltx, tw); return;
+    case 512: fft_c<T, S, 512, 0, 1, MAXE, PAD>(buf, nseq, ltx, tw); return;
     default: break;
   }
   int Ns = 1;
@@ -329,16 +329,16 @@ __device__ void fft_lds(cpx<T>* buf, int nseq, int ltx, const AxisPlan& pl, cons
     const int R = pl.radix[st];
     const FastDiv& a = pl.dnb[st];
     const FastDiv& b = pl.dns[st];
-    if (R == 8) stockham_stage<T, S, 8, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
-    else if (R == 4) stockham_stage<T, S, 4, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
-    else if (R == 3) stockham_stage<T, S, 3, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
-    else if (R == 2) stockham_stage<T, S, 2, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
+    if (R == 8) stockham_stage<T, S, 8, MAXE, PAD>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
+    else if (R == 4) stockham_stage<T, S, 4, MAXE, PAD>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
+    else if (R == 3) stockham_stage<T, S, 3, MAXE, PAD>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
+    else if (R == 2) stockham_stage<T, S, 2, MAXE, PAD>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
     else if constexpr (ANY) {
-      if (R == 5) stockham_stage<T, S, 5, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
-      else if (R == 7) stockham_stage<T, S, 7, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
-      else if (R == 11) stockham_stage<T, S, 11, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
-      else if (R == 13) stockham_stage<T, S, 13, MAXE>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
-      else stockham_stage_any<T, S, MAXE>(buf, pl.n, R, Ns, nseq, ltx, tw);
+      if (R == 5) stockham_stage<T, S, 5, MAXE, PAD>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
+      else if (R == 7) stockham_stage<T, S, 7, MAXE, PAD>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
+      else if (R == 11) stockham_stage<T, S, 11, MAXE, PAD>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
+      else if (R == 13) stockham_stage<T, S, 13, MAXE, PAD>(buf, pl.n, Ns, nseq, ltx, tw, a, b);
+      else stockham_stage_any<T, S, MAXE, PAD>(buf, pl.n, R, Ns, nseq, ltx, tw);
     }
     Ns *= R;
   }

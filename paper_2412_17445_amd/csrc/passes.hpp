@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xfwd(co
   const int RB = rows_per_block;
   const int seq = RB * NP * nx;
   cpx<T>* bufa = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* tw = bufa + seq;
+  cpx<T>* tw = bufa + lds_padded(seq);
   for (int t = threadIdx.x; t < nx; t += blockDim.x) tw[t] = tw_g[t];
   const long long row0 = (long long)blockIdx.x * RB;
   double red[NR > 0 ? NR : 1];
@@ -63,10 +63,10 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xfwd(co
     for (int f = 0; f < 2 * NP; ++f) vals[f] = T(0);
     if (row < nrows) P::prologue(A, x + (long long)nx * row, vals, red);
 #pragma unroll
-    for (int p = 0; p < NP; ++p) bufa[(r * NP + p) * nx + x] = cpx<T>{vals[2 * p], vals[2 * p + 1]};
+    for (int p = 0; p < NP; ++p) bufa[lpad((r * NP + p) * nx + x)] = cpx<T>{vals[2 * p], vals[2 * p + 1]};
   }
   __syncthreads();
-  fft_lds<T, -1, FftCap<T>::MAXE, ANY>(bufa, RB * NP, 0, pl, tw);
+  fft_lds<T, -1, FftCap<T>::MAXE, ANY, true>(bufa, RB * NP, 0, pl, tw);
   const cpx<T>* res = bufa;
   const long long Nh = A.g.Nh;
   const int nxm = A.g.nxm;
@@ -79,8 +79,8 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xfwd(co
     for (int idx = threadIdx.x; idx < nrow_here * nxm; idx += blockDim.x) {
       const int r = (int)fdiv((uint32_t)idx, A.g.dnxm);
       const int k = idx - r * nxm;
-      const cpx<T> Z = res[(r * NP + p) * nx + k];
-      const cpx<T> Zm = res[(r * NP + p) * nx + (k == 0 ? 0 : nx - k)];
+      const cpx<T> Z = res[lpad((r * NP + p) * nx + k)];
+      const cpx<T> Zm = res[lpad((r * NP + p) * nx + (k == 0 ? 0 : nx - k))];
       // X_a = (Z + conj Zm)/2, X_b = (Z - conj Zm)/(2i)
       const long long o = row0 * nxm + idx;
       sa[o] = cpx<T>{T(0.5) * (Z.x + Zm.x), T(0.5) * (Z.y - Zm.y)};
@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xfwd(co
     // Nyquist plane (even nx): one value per row
     if (A.g.nyq) {
       for (int r = threadIdx.x; r < nrow_here; r += blockDim.x) {
-        const cpx<T> Z = res[(r * NP + p) * nx + nx / 2];
+        const cpx<T> Z = res[lpad((r * NP + p) * nx + nx / 2)];
         const long long o = A.g.Nm + row0 + r;
         sa[o] = cpx<T>{Z.x, T(0)};
         if (2 * p + 1 < NF) sb[o] = cpx<T>{Z.y, T(0)};
@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_axis(co
     }
   }
   __syncthreads();
-  fft_lds<T, S, MAXE, ANY>(buf, nfb, ltx, pl, tw);
+  fft_lds<T, S, MAXE, ANY, false>(buf, nfb, ltx, pl, tw);
   if constexpr (SPECTRAL) {
     for (int idx = threadIdx.x; idx < per_field; idx += blockDim.x) {
       const int t = idx & (TX - 1), j = idx >> ltx;
@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_axis(co
       for (int f = 0; f < NF; ++f) buf[f * per_field + idx] = v[f];
     }
     __syncthreads();
-    fft_lds<T, -S, MAXE, ANY>(buf, nfb, ltx, pl, tw);
+    fft_lds<T, -S, MAXE, ANY, false>(buf, nfb, ltx, pl, tw);
   }
   for (int f = 0; f < nfb; ++f) {
     cpx<T>* dst = spec + (long long)(f0 + f) * g.Nh + off0;
@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xinv(co
   const int RB = rows_per_block;
   const int seq = RB * NP * nx;
   cpx<T>* bufa = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* tw = bufa + seq;
+  cpx<T>* tw = bufa + lds_padded(seq);
   for (int t = threadIdx.x; t < nx; t += blockDim.x) tw[t] = tw_g[t];
   const long long row0 = (long long)blockIdx.x * RB;
   const int nxm = A.g.nxm;
@@ -269,11 +269,11 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xinv(co
         }
         Z = cpx<T>{a.x - b.y, a.y + b.x};   // a + i b
       }
-      bufa[(r * NP + p) * nx + x] = Z;
+      bufa[lpad((r * NP + p) * nx + x)] = Z;
     }
   }
   __syncthreads();
-  fft_lds<T, 1, FftCap<T>::MAXE, ANY>(bufa, RB * NP, 0, pl, tw);
+  fft_lds<T, 1, FftCap<T>::MAXE, ANY, true>(bufa, RB * NP, 0, pl, tw);
   const cpx<T>* res = bufa;
   double red[NR > 0 ? NR : 1];
 #pragma unroll
@@ -285,7 +285,7 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xinv(co
     T vals[2 * NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-      const cpx<T> z = res[(r * NP + p) * nx + x];
+      const cpx<T> z = res[lpad((r * NP + p) * nx + x)];
       vals[2 * p] = z.x;
       vals[2 * p + 1] = z.y;
     }

@@ -244,14 +244,15 @@ int choose_rb(int nx, int np, size_t csz, int rows_max) {
   while (true) {
     const int nr = rb * 2;
     const size_t elems = size_t(nr) * np * nx;
-    if (nr > rows_max || elems > cap || (elems + nx) * csz > g_lds_budget || nr * nx > 4096) break;
+    if (nr > rows_max || elems > cap || (size_t(lds_padded(elems)) + nx) * csz > g_lds_budget || nr * nx > 4096)
+      break;
     rb = nr;
   }
   return rb;
 }
 
 size_t lds_x(int rb, int np, int nx, size_t csz, int nred) {
-  size_t b = (size_t(rb) * np * nx + nx) * csz;
+  size_t b = (size_t(lds_padded((long long)rb * np * nx)) + nx) * csz;
   return std::max(b, size_t(nred) * fft_threads(csz) * sizeof(double));
 }
 
