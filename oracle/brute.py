@@ -20,7 +20,7 @@ from .newton import Solver
 def full_residual(sys, x, Hn, a):
     eps_t, phi, E = sys.unpack(x)
     R = sys.residual(eps_t, phi, E, Hn, a)
-    F1 = R["F1"] + (eps_t - fo.G_mandel(eps_t, sys.scheme))
+    F1 = R["F1"] + (eps_t - sys.G_mandel(eps_t))
     m = sys.m
     F2 = R["F2"] + m * (phi - 1.0) * (1.0 if np.any(m) else 0.0)
     return sys.pack(F1, F2, R["F3"])

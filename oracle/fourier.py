@@ -24,6 +24,14 @@ Readings taken here (the paper leaves them open):
   Nyquist frequency is undefined (m = N/2 and -N/2 alias), and taking either
   one would make the projected field complex; with xi_j = 0 the symbol is
   even in every m_j and the projection maps real fields to real fields.
+* Mixed macroscopic conditions (Sec. 2.3 names them as the alternative to
+  the prescribed macroscopic strain f E, done in FFT by stress control at
+  the zero frequency): only the component of the mean strain along f is
+  prescribed, and the mean stress must vanish on every direction Frobenius-
+  orthogonal to f, so Sigma_M = s f.  In the Galerkin form this is the
+  projection with G(0) = P_f^perp (A -> A - fh (fh : A), fh = f/|f|) instead
+  of 0; the strain fluctuation then carries the free mean strain along
+  P_f^perp, and the residual G[sigma] = 0 holds P_f^perp Sigma_M = 0.
 Arrays are [z, y, x]; tensor index 0 <-> x, 1 <-> y, 2 <-> z.
 """
 
@@ -151,17 +159,25 @@ def ifftn(a):
     return np.fft.ifftn(a, axes=(-3, -2, -1))
 
 
-def G_tensor(A, scheme="rotated"):
-    """Projection of a real symmetric tensor field A (3, 3, nz, ny, nx)."""
+def G_tensor(A, scheme="rotated", free_mean=None):
+    """Projection of a real symmetric tensor field A (3, 3, nz, ny, nx).
+    free_mean: None (prescribed mean strain, G(0) = 0) or the 3x3 loading
+    direction f of mixed macroscopic conditions (G(0) = P_f^perp)."""
     shape = A.shape[2:]
     n, zero = direction(shape, scheme)
-    out = project_hat(fftn(A), n, zero)
+    A_hat = fftn(A)
+    out = project_hat(A_hat, n, zero)
+    if free_mean is not None:
+        fh = np.asarray(free_mean, dtype=np.float64)
+        fh = fh / np.sqrt(np.sum(fh * fh))
+        a0 = A_hat[:, :, 0, 0, 0]
+        out[:, :, 0, 0, 0] = a0 - fh * np.sum(fh * a0)
     return ifftn(out).real
 
 
-def G_mandel(m, scheme="rotated"):
+def G_mandel(m, scheme="rotated", free_mean=None):
     """Projection acting on a Mandel field (c, nz, ny, nx)."""
-    return to_mandel(G_tensor(to_tensor(m), scheme), m.shape[0])
+    return to_mandel(G_tensor(to_tensor(m), scheme, free_mean), m.shape[0])
 
 
 def laplacian(phi):

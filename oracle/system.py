@@ -64,6 +64,20 @@ class System:
             raise ValueError("the variational toughness term is built for crack-length control only")
         self.f = fo.to_mandel(np.asarray(prob.f, dtype=np.float64)[:, :, None, None, None],
                               self.ncomp)[:, 0, 0, 0]
+        # macroscopic conditions: "strain" (mean strain f E, Sec. 2.3) or
+        # "mixed" (mean strain prescribed along f only, mean stress zero on the
+        # directions orthogonal to f; the zero mode of G projects onto them)
+        self.bc = getattr(prob, "macro_bc", "strain")
+        if self.bc not in ("strain", "mixed"):
+            raise ValueError(self.bc)
+        self.free_mean = (np.asarray(prob.f, dtype=np.float64) if self.bc == "mixed" else None)
+
+    def G(self, A):
+        """The compatibility projection of the problem on a tensor field."""
+        return fo.G_tensor(A, self.scheme, self.free_mean)
+
+    def G_mandel(self, m):
+        return fo.G_mandel(m, self.scheme, self.free_mean)
 
     def lap(self, u):
         """The Laplacian of the crack functional.  With the variational
@@ -98,7 +112,7 @@ class System:
     def residual(self, eps_t, phi, E, Hn, a):
         eps = eps_t + self.fE(E)
         st = self.point(eps, phi, Hn)
-        F1 = fo.to_mandel(fo.G_tensor(st["sigma"], self.scheme), self.ncomp)
+        F1 = fo.to_mandel(self.G(st["sigma"]), self.ncomp)
         lap = self.lap(phi)
         l, Gc, H = self.l, self.Gc, st["H"]
         gterm = l * fo.div_k_grad(phi, Gc) if self.var else Gc * l * lap
@@ -134,7 +148,7 @@ class System:
             w = fo.to_tensor(d_eps + self.fE(dE))
             dphi_f = (1.0 - m) * d_phi
             tau = pl.tangent_apply(st, w) + b * dphi_f
-            J1 = fo.to_mandel(fo.G_tensor(tau, self.scheme), c)
+            J1 = fo.to_mandel(self.G(tau), c)
             bw = np.einsum("ij...,ij...->...", b, w)
             gterm = l * fo.div_k_grad(dphi_f, Gc) if self.var else Gc * l * fo.laplacian(dphi_f)
             J2 = (1.0 - m) * (st["chi"] * bw + A * dphi_f - gterm) + m * d_phi

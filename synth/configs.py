@@ -54,6 +54,7 @@ class Problem:
     control_weights: Tuple[float, float] = (1.0, 0.0)   # (w_a, w_E): F3 = w_a Gamma + w_E E - tau
     control: str = "length"              # controlled quantity: "length" (Gamma) or "dissipation" (D)
     gc_form: str = "pointwise"           # "pointwise" Gc l Lap phi or "variational" l div(Gc grad phi)
+    macro_bc: str = "strain"             # "strain" (mean strain f E) or "mixed" (stress-free off f)
     notes: str = ""
     extra: dict = field(default_factory=dict)
 
@@ -76,7 +77,13 @@ def problem_config(name: str) -> Problem:
     degradation of Sec. 5.4, "_std" with the standard-frequency projection,
     "_w" with the weighted control 0.7 Gamma + 3 E, "_d" with dissipation
     control (increment delta_a times the smallest Gc), "_v" with the
-    variational toughness term l div(Gc grad phi)."""
+    variational toughness term l div(Gc grad phi), "_m" with mixed
+    macroscopic conditions (mean stress zero off the loading direction)."""
+    if name.endswith("_m"):
+        prob = problem_config(name[:-2])
+        prob.name, prob.macro_bc = name, "mixed"
+        prob.notes = (prob.notes + "; " if prob.notes else "") + "mixed macroscopic conditions"
+        return prob
     if name.endswith("_v"):
         prob = problem_config(name[:-2])
         prob.name, prob.gc_form = name, "variational"
