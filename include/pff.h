@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define PFF_ABI_VERSION 2
+#define PFF_ABI_VERSION 3
 
 typedef int pff_status;
 enum {
@@ -106,12 +106,24 @@ typedef struct {
  *               the crack functional on the same finite-difference Laplacian
  *               (symbol -sum 4 sin^2(q/2)).  Crack-length or weighted control
  *               only (not with PFF_CONTROL_DISSIPATION), and not with the
- *               staggered scheme. */
+ *               staggered scheme.
+ *  macro_bc     PFF_BC_STRAIN (0): the mean strain is f E (Sec. 2.3);
+ *               PFF_BC_MIXED (1): the mixed macroscopic conditions that
+ *               Sec. 2.3 names as the alternative: only the component of the
+ *               mean strain along f is prescribed (by E), and the mean stress
+ *               vanishes on every direction Frobenius-orthogonal to f, so
+ *               Sigma_M = s f.  Taken in the Galerkin form: the zero mode of
+ *               G projects onto the orthogonal complement of f instead of
+ *               vanishing, and the strain fluctuation (eps - f E) carries the
+ *               free mean strain.  Needs f != 0. */
 typedef struct {
   double l, k_resid, f[9], delta_a, alpha, newton_tol, krylov_rtol;
   int newton_maxit, krylov_maxit, precision, split, projection, control, gc_form;
   double w_gamma, w_load;
+  int macro_bc;
 } pff_params;
+
+enum { PFF_BC_STRAIN = 0, PFF_BC_MIXED = 1 };
 
 enum { PFF_CONTROL_LENGTH = 0, PFF_CONTROL_DISSIPATION = 1 };
 enum { PFF_GC_POINTWISE = 0, PFF_GC_VARIATIONAL = 1 };

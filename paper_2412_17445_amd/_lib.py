@@ -19,6 +19,7 @@ PFF_SPLIT_SPECTRAL, PFF_SPLIT_NONE = 0, 1
 PFF_PROJ_ROTATED, PFF_PROJ_STANDARD = 0, 1
 PFF_CONTROL_LENGTH, PFF_CONTROL_DISSIPATION = 0, 1
 PFF_GC_POINTWISE, PFF_GC_VARIATIONAL = 0, 1
+PFF_BC_STRAIN, PFF_BC_MIXED = 0, 1
 
 
 class pff_grid(C.Structure):
@@ -35,7 +36,7 @@ class pff_params(C.Structure):
                 ("krylov_rtol", C.c_double), ("newton_maxit", C.c_int),
                 ("krylov_maxit", C.c_int), ("precision", C.c_int), ("split", C.c_int),
                 ("projection", C.c_int), ("control", C.c_int), ("gc_form", C.c_int), ("w_gamma", C.c_double),
-                ("w_load", C.c_double)]
+                ("w_load", C.c_double), ("macro_bc", C.c_int)]
 
 
 class pff_increment_result(C.Structure):

@@ -29,6 +29,8 @@ template <typename T> struct SpecTables {
   const T* hc[3];   // cos(q/2), exactly 0 at an even axis' Nyquist index (standard scheme: 1)
   const T* q2[3];   // q^2 (standard frequencies, Nyquist kept)
   T invN;
+  const T* fh;      // f / |f| in Mandel components: the zero mode projects onto
+                    // its complement (mixed macroscopic conditions); null: G(0) = 0
 };
 
 // Max LDS elements per thread of the in-place FFT (64 KB per block).
@@ -345,8 +347,18 @@ __device__ __forceinline__ void spectral_proj_lap(const SpecTables<T>& tb, int k
   const T r2 = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
   if (C > 0) {
     if (r2 == T(0)) {
+      if (tb.fh && kx == 0 && ky == 0 && (DIM == 2 || kz == 0)) {
+        // mean of the field under mixed macroscopic conditions: keep the
+        // part orthogonal to f (the mean is real)
+        T d = T(0);
 #pragma unroll
-      for (int k = 0; k < C; ++k) vals[k] = cpx<T>{T(0), T(0)};
+        for (int k = 0; k < C; ++k) d += tb.fh[k] * vals[k].x;
+#pragma unroll
+        for (int k = 0; k < C; ++k) vals[k] = cpx<T>{(vals[k].x - d * tb.fh[k]) * tb.invN, T(0)};
+      } else {
+#pragma unroll
+        for (int k = 0; k < C; ++k) vals[k] = cpx<T>{T(0), T(0)};
+      }
     } else {
       const T s = T(1) / sqrt(r2);
       n[0] *= s; n[1] *= s; n[2] *= s;

@@ -103,6 +103,7 @@ template <typename T> struct DevTables {
   T* hs[3] = {nullptr, nullptr, nullptr};
   T* hc[3] = {nullptr, nullptr, nullptr};
   T* q2[3] = {nullptr, nullptr, nullptr};
+  T* fh = nullptr;   // f / |f| in Mandel components under mixed macroscopic conditions
 };
 
 }  // namespace
@@ -114,6 +115,8 @@ struct pff_solver {
   Material mat{};
   pff_params prm{};
   double fm[6] = {0, 0, 0, 0, 0, 0};   // f in Mandel form
+  double fh[6] = {0, 0, 0, 0, 0, 0};   // f / |f| (mixed macroscopic conditions)
+  int mixed_bc = 0;                     // 1: PFF_BC_MIXED
   std::vector<uint8_t> h_pid, h_mask;
   bool has_mask = false;
   std::vector<pff_phase> phases;
@@ -222,6 +225,7 @@ template <typename T> SpecTables<T> spec_tables(const pff_solver* s) {
     st.q2[a] = t.q2[a];
   }
   st.invN = T(1.0 / double(s->N));
+  st.fh = t.fh;
   return st;
 }
 
@@ -1355,6 +1359,12 @@ void upload_tables(pff_solver* s, DevTables<T>& t) {
     HC(hipMemcpy(t.hc[a], hc.data(), n * sizeof(T), hipMemcpyHostToDevice));
     HC(hipMemcpy(t.q2[a], q2.data(), n * sizeof(T), hipMemcpyHostToDevice));
   }
+  if (s->mixed_bc) {
+    T fh[6];
+    for (int k = 0; k < 6; ++k) fh[k] = T(s->fh[k]);
+    t.fh = s->alloc<T>(6);
+    HC(hipMemcpy(t.fh, fh, sizeof(fh), hipMemcpyHostToDevice));
+  }
 }
 
 hipEvent_t* timing_acquire(pff_solver* s, int group) {
@@ -1469,6 +1479,8 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     if ((p.gc_form != PFF_GC_POINTWISE && p.gc_form != PFF_GC_VARIATIONAL) ||
         (p.gc_form == PFF_GC_VARIATIONAL && p.control == PFF_CONTROL_DISSIPATION))
       throw Fail("invalid solver parameters", PFF_ERR_ARG);
+    if (p.macro_bc != PFF_BC_STRAIN && p.macro_bc != PFF_BC_MIXED)
+      throw Fail("invalid solver parameters", PFF_ERR_ARG);
     s->var = p.gc_form == PFF_GC_VARIATIONAL;
     s->dctl = p.control == PFF_CONTROL_DISSIPATION;
     if (p.w_gamma == 0.0 && p.w_load == 0.0) {
@@ -1489,6 +1501,13 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     } else {
       s->fm[0] = p.f[0]; s->fm[1] = p.f[4]; s->fm[2] = p.f[8];
       s->fm[3] = r2 * p.f[5]; s->fm[4] = r2 * p.f[2]; s->fm[5] = r2 * p.f[1];
+    }
+    if (p.macro_bc == PFF_BC_MIXED) {
+      double nf = 0.0;
+      for (int k = 0; k < 6; ++k) nf += s->fm[k] * s->fm[k];
+      if (!(nf > 0)) throw Fail("mixed macroscopic conditions need f != 0", PFF_ERR_ARG);
+      s->mixed_bc = 1;
+      for (int k = 0; k < 6; ++k) s->fh[k] = s->fm[k] / std::sqrt(nf);
     }
     s->mat.nphase = n_phases;
     s->mat.iso = p.split == PFF_SPLIT_NONE ? 1 : 0;

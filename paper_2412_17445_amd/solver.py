@@ -30,13 +30,18 @@ def _torch():
 def marshal_problem(shape, phases, phase_id, mask, f, l, k=1e-6, delta_a=1.0, alpha=1.0,
                     newton_tol=1e-8, krylov_rtol=1e-10, newton_maxit=50, krylov_maxit=5000,
                     precision="fp64", split="spectral", projection="rotated",
-                    control_weights=(1.0, 0.0), control="length", gc_form="pointwise"):
+                    control_weights=(1.0, 0.0), control="length", gc_form="pointwise",
+                    macro_bc="strain"):
     """C structs and host arrays of one RVE problem (pff_create's inputs).
     split: "spectral" (Miehe split) or "none" (isotropic degradation);
     projection: "rotated" (Willot) or "standard" frequencies in G;
     control_weights: (w_a, w_E) of the controlled quantity w_a Q + w_E E;
     control: Q is "length" (Gamma) or "dissipation" (sum of Gc gamma_f);
-    gc_form: "pointwise" Gc l Lap phi or "variational" l div(Gc grad phi)."""
+    gc_form: "pointwise" Gc l Lap phi or "variational" l div(Gc grad phi);
+    macro_bc: "strain" (mean strain f E) or "mixed" (mean strain prescribed
+    along f only, mean stress zero on the directions orthogonal to f)."""
+    if macro_bc not in ("strain", "mixed"):
+        raise ValueError("macro_bc must be 'strain' or 'mixed'")
     if gc_form not in ("pointwise", "variational"):
         raise ValueError("gc_form must be 'pointwise' or 'variational'")
     if control not in ("length", "dissipation"):
@@ -66,6 +71,7 @@ def marshal_problem(shape, phases, phase_id, mask, f, l, k=1e-6, delta_a=1.0, al
     prm.w_gamma, prm.w_load = (float(w) for w in control_weights)
     prm.control = L.PFF_CONTROL_DISSIPATION if control == "dissipation" else L.PFF_CONTROL_LENGTH
     prm.gc_form = L.PFF_GC_VARIATIONAL if gc_form == "variational" else L.PFF_GC_POINTWISE
+    prm.macro_bc = L.PFF_BC_MIXED if macro_bc == "mixed" else L.PFF_BC_STRAIN
     return grid, ph, pid, msk, prm
 
 
@@ -78,7 +84,8 @@ def problem_kwargs(prob, **over):
               projection=getattr(prob, "projection", "rotated"),
               control_weights=getattr(prob, "control_weights", (1.0, 0.0)),
               control=getattr(prob, "control", "length"),
-              gc_form=getattr(prob, "gc_form", "pointwise"))
+              gc_form=getattr(prob, "gc_form", "pointwise"),
+              macro_bc=getattr(prob, "macro_bc", "strain"))
     kw.update(over)
     return kw
 
@@ -97,7 +104,8 @@ class Solver:
     def __init__(self, shape, phases, phase_id, mask, f, l, k=1e-6, delta_a=1.0, alpha=1.0,
                  newton_tol=1e-8, krylov_rtol=1e-10, newton_maxit=50, krylov_maxit=5000,
                  precision="fp64", split="spectral", projection="rotated",
-                 control_weights=(1.0, 0.0), control="length", gc_form="pointwise", stream=None):
+                 control_weights=(1.0, 0.0), control="length", gc_form="pointwise",
+                 macro_bc="strain", stream=None):
         torch = _torch()
         self.lib = L.load()
         nz, ny, nx = shape
@@ -111,7 +119,8 @@ class Solver:
             shape, phases, phase_id, mask, f, l, k=k, delta_a=delta_a, alpha=alpha,
             newton_tol=newton_tol, krylov_rtol=krylov_rtol, newton_maxit=newton_maxit,
             krylov_maxit=krylov_maxit, precision=precision, split=split, projection=projection,
-            control_weights=control_weights, control=control, gc_form=gc_form)
+            control_weights=control_weights, control=control, gc_form=gc_form,
+            macro_bc=macro_bc)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self._stream = stream
@@ -132,7 +141,8 @@ class Solver:
                   projection=getattr(prob, "projection", "rotated"),
                   control_weights=getattr(prob, "control_weights", (1.0, 0.0)),
                   control=getattr(prob, "control", "length"),
-                  gc_form=getattr(prob, "gc_form", "pointwise"))
+                  gc_form=getattr(prob, "gc_form", "pointwise"),
+                  macro_bc=getattr(prob, "macro_bc", "strain"))
         kw.update(over)
         return cls(prob.shape, prob.phases, prob.phase_id, prob.mask, prob.f, prob.l, **kw)
 

@@ -34,14 +34,14 @@ def test_library_exports_every_declared_symbol():
     lib = L.load()
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert lib.pff_abi_version() == 2
+    assert lib.pff_abi_version() == 3
 
 
 def test_struct_layouts():
     assert C.sizeof(L.pff_grid) == 12
     assert C.sizeof(L.pff_phase) == 24
     # 2 doubles + f[9] + 4 doubles, 7 ints (+ padding), 2 doubles
-    assert C.sizeof(L.pff_params) == 8 * (2 + 9 + 4) + 4 * 7 + 4 + 8 * 2
+    assert C.sizeof(L.pff_params) == 8 * (2 + 9 + 4) + 4 * 7 + 4 + 8 * 2 + 4 + 4   # macro_bc + tail padding
     assert C.sizeof(L.pff_increment_result) == 4 * 4 + 8 * 2 + 4 * 2 + 8 * (6 + 3 + 3 + 2)
 
 
@@ -107,13 +107,18 @@ def test_invalid_arguments_rejected_before_device_work():
     st, h = _create(L.pff_grid(1, 8, 1), ok_phase, pid, _params())
     assert st == L.PFF_ERR_ARG and not h.value
     # unknown model and control options
-    for opt in ("split", "projection", "control", "precision", "gc_form"):
+    for opt in ("split", "projection", "control", "precision", "gc_form", "macro_bc"):
         st, h = _create(L.pff_grid(8, 8, 1), ok_phase, pid, _params(**{opt: 7}))
         assert st == L.PFF_ERR_ARG, opt
     st, h = _create(L.pff_grid(8, 8, 1), ok_phase, pid, _params(w_gamma=-1.0))
     assert st == L.PFF_ERR_ARG
     st, h = _create(L.pff_grid(8, 8, 1), ok_phase, pid, _params(gc_form=1, control=1))
     assert st == L.PFF_ERR_ARG                    # variational term with dissipation control
+    p = _params(macro_bc=1)
+    for i in range(9):
+        p.f[i] = 0.0
+    st, h = _create(L.pff_grid(8, 8, 1), ok_phase, pid, p)
+    assert st == L.PFF_ERR_ARG                    # mixed conditions without a loading direction
     # too many phases
     st, h = _create(L.pff_grid(8, 8, 1), ok_phase * 17, pid, _params())
     assert st == L.PFF_ERR_ARG
