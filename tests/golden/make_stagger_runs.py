@@ -26,7 +26,7 @@ from oracle.staggered import StaggeredSolver  # noqa: E402
 from synth import problem_config  # noqa: E402
 
 STEPS = {"tiny16": ["E1", "E1"], "gc16": [3e-3, 3e-3, -2e-3], "crack2d_64": ["E1"],
-         "pore24": ["E1"]}
+         "pore24": ["E1"], "tiny16_m": ["E1", "E1"], "gc16_m": [3e-3, 3e-3, -2e-3]}
 SAMPLES = 32
 
 

@@ -5,7 +5,8 @@ through the C ABI (pff_stagger_step).
   f E, phi = 2H / (Gc/l + 2H), H = (lambda/2 + mu) E^2).
 * Seeded cases against the staggered oracle's stored increments
   (tests/golden/stagger_<case>.json, written by make_stagger_runs.py from
-  oracle/ only): load, crack length, mean stress, sampled damage, and the
+  oracle/ only), also under mixed macroscopic conditions: load, crack
+  length, mean stress, sampled damage, and the
   stagger / Newton counts.
 * At the load factor of a crack-length-controlled increment both schemes
   reach the same root, and crack-length increments continue from the
@@ -150,7 +151,8 @@ def _check_increment(out, ref, tol):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("case,precision", [("tiny16", "fp64"), ("gc16", "fp64"), ("gc16", "mixed"),
-                                            ("crack2d_64", "fp64"), ("pore24", "fp64")])
+                                            ("crack2d_64", "fp64"), ("pore24", "fp64"),
+                                            ("tiny16_m", "fp64"), ("gc16_m", "fp64"), ("gc16_m", "mixed")])
 def test_matches_the_staggered_oracle(case, precision):
     from synth import problem_config
     g = _gold(case)
