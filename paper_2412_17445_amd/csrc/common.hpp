@@ -30,6 +30,42 @@ constexpr int kMaxPhases = 16;
 constexpr int kMaxRed = 12;          // reduction slots per pass
 constexpr int kMaxStages = 10;
 
+// Totals of NQ slots of per-block partials (slot q at src[q], nblk entries;
+// the first nq slots are summed) by one block of kBlock threads, in a fixed
+// order: every thread adds a strided subset of all slots at once, each
+// wavefront combines its 64 lanes by an xor butterfly (lane 0's sum is
+// taken), and the wavefront sums are added in order.  tot: nq doubles.
+template <int NQ>
+__device__ __forceinline__ void block_slot_sums(const double* const (&src)[NQ], int nq, int nblk,
+                                                double* tot) {
+  __shared__ double wsum[NQ][kBlock / 64];
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kBlock) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      if (q < nq) acc[q] += src[q][b];
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    if (q < nq) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, 64);
+      if (lane == 0) wsum[q][w] = acc[q];
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nq) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) t += wsum[threadIdx.x][i];
+    tot[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
 template <typename T> struct cpx { T x, y; };
 
 template <typename T> __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {

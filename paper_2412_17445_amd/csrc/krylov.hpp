@@ -354,21 +354,9 @@ __global__ void __launch_bounds__(kBlock) k_fin_fused(const double* __restrict__
                                                       const double* __restrict__ part1, int nblk, int mode,
                                                       int pro, T* Jv_last, T* vout_last, const T* dv_last,
                                                       const T* in_last, double wa, double wE, double* ks) {
-  __shared__ double lds[kBlock];
   __shared__ double tot[3];
-  const double* src[3] = {part0, part1, part1 + nblk};
-  for (int q = 0; q < 3; ++q) {
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc += src[q][b];
-    lds[threadIdx.x] = acc;
-    __syncthreads();
-    for (int h = kBlock / 2; h > 0; h >>= 1) {
-      if (threadIdx.x < h) lds[threadIdx.x] += lds[threadIdx.x + h];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) tot[q] = lds[0];
-    __syncthreads();
-  }
+  const double* const src[3] = {part0, part1, part1 + nblk};
+  block_slot_sums<3>(src, mode == 1 ? 2 : 3, nblk, tot);
   if (threadIdx.x != 0) return;
   // border row J3 = w_a (r, d phi) + w_E dE, dE the trailing entry of the input
   const double din = pro ? ks[KS_ULAST] : double(*in_last);

@@ -383,20 +383,11 @@ __device__ __forceinline__ void spectral_proj_lap(const SpecTables<T>& tb, int k
 template <class Fin>
 __global__ void __launch_bounds__(kBlock) k_reduce(const double* __restrict__ partials, int nblk,
                                                    int nslot, const typename Fin::Args F) {
-  __shared__ double lds[kBlock];
   __shared__ double tot[kMaxRed];
-  for (int q = 0; q < nslot; ++q) {
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc += partials[(long long)q * nblk + b];
-    lds[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) tot[q] = lds[0];
-    __syncthreads();
-  }
+  const double* src[kMaxRed];
+#pragma unroll
+  for (int q = 0; q < kMaxRed; ++q) src[q] = partials + (long long)q * nblk;
+  block_slot_sums<kMaxRed>(src, nslot, nblk, tot);
   if (threadIdx.x == 0) Fin::run(F, tot);
 }
 
