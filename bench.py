@@ -235,6 +235,47 @@ def odd_grid_leg(args):
             "apply_ns_per_voxel": round(ms_ap / max(n_ap, 1) * 1e6 / prob.nvox, 4)}
 
 
+def mixed_bc_leg(prob, first):
+    """The same workload under mixed macroscopic conditions (mean strain
+    prescribed along f only, mean stress zero off f): one warm-up and one
+    timed crack-length increment.  Reports its time and applies next to the
+    strain-controlled increment, and the mean stress off f relative to its
+    component along f (zero up to the Newton tolerance)."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_2412_17445_amd import Solver
+
+    pm = dataclasses.replace(prob, name=prob.name + "_m", macro_bc="mixed")
+    s = Solver.from_problem(pm)
+    s.bootstrap()
+    w = s.step()
+    log(f"{pm.name} warm-up increment: converged={w['converged']} {w['seconds']:.2f}s")
+    a0, _ = s.counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    o = s.step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    a1, _ = s.counters()
+    s.close()
+    log(f"{pm.name} timed increment: converged={o['converged']} {dt:.2f}s")
+    f = np.asarray(pm.f, dtype=np.float64)
+    sv = o["sigma_M"]
+    S = np.array([[sv[0], sv[5], sv[4]], [sv[5], sv[1], sv[3]], [sv[4], sv[3], sv[2]]])
+    if pm.dim == 2:                      # plane strain: sigma_zz is reported, not controlled
+        S[2, 2] = 0.0
+    fh = f / np.sqrt(np.sum(f * f))
+    along = float(np.sum(fh * S))
+    off = float(np.sqrt(np.sum((S - along * fh) ** 2)))
+    return {"workload": pm.name, "converged": o["converged"], "timed_increment": 2,
+            "ms_per_increment": round(dt * 1e3, 2), "tangent_applies": a1 - a0,
+            "newton_iters": o["newton_iters"], "E_increment1": w["E"],
+            "E_increment1_strain_control": first["E"], "sigma_off_f_over_along_f": off / abs(along)}
+
+
 def serve_stream(args):
     """Seeded request stream (synth.stream) through the request server:
     Poisson arrivals, admission by footprint into slots, per-request latency
@@ -335,6 +376,8 @@ def main():
     ap.add_argument("--no-odd", action="store_true",
                     help="skip the increment on a grid with prime factors above 3")
     ap.add_argument("--odd-workload", default="pores3d_105")
+    ap.add_argument("--no-mixed-bc", action="store_true",
+                    help="skip the increments under mixed macroscopic conditions")
     ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrivals per second")
     ap.add_argument("--serve-inc-scale", type=float, default=0.1,
@@ -474,6 +517,8 @@ def main():
         if "mixed_vs_fp64" in line:
             line["staggered_vs_crack_control"]["crack_control_fp64_seconds"] = \
                 line["mixed_vs_fp64"]["fp64_first_increment_s"]
+    if not args.no_mixed_bc:
+        line["mixed_bc"] = mixed_bc_leg(prob, (warm + outs)[0])
     if not args.no_odd:
         line["odd_grid"] = odd_grid_leg(args)
         line["odd_grid"]["apply_ns_per_voxel_main"] = round(
