@@ -16,6 +16,8 @@ G(0) = P_f^perp (A -> A - fh (fh : A), fh = f / |f|).
   volume average of the layers' uniaxial plane-strain moduli.
 * J v against central differences of the residual with mixed conditions, in
   2D with a crack and two phases and in 3D with particles.
+* The staggered scheme (Algorithm 1) on the homogeneous cell: uniform damage
+  at the root of the scalar fixed point phi(H(E, g(phi))), found by bisection.
 """
 
 import numpy as np
@@ -163,3 +165,46 @@ def test_tangent_is_residual_derivative_mixed(case):
     c = sy.ncomp
     mJ = Jv[: c * sy.N].reshape(c, -1).mean(axis=-1)
     assert abs(np.dot(mJ, sy.f)) <= 1e-12 * np.abs(Jv[: c * sy.N]).max()
+
+
+def test_staggered_homogeneous_uniaxial_stress():
+    """Algorithm 1 under mixed conditions on a homogeneous uncracked cell: at
+    every load E the converged state is uniform, with phi the root of
+    phi = 2H/(Gc/l + 2H), H = E^2 (lam/2 tr^2 + mu), tr = 1 + c(g),
+    c(g) = -g lam/(g lam + 2 mu), g = (1 - phi)^2 + k (plane strain, f = e_y e_y),
+    found here by bisection; stagger tolerance 1e-8."""
+    n = 8
+    prob = Problem(name="hom_m", shape=(1, n, n), phases=[(1.0, 0.3, 1e-3)],
+                   phase_id=np.zeros((1, n, n), np.uint8), mask=None, f=_dyad(1, 1), l=2.0, k=1e-6,
+                   macro_bc="mixed")
+    lam, mu = lame(1.0, 0.3)
+    Gc, l, k = 1e-3, 2.0, 1e-6
+    st = StaggeredSolver(prob, dE=4e-3)
+
+    def resid(phi, E):
+        g = (1 - phi) ** 2 + k
+        c = -g * lam / (g * lam + 2 * mu)
+        H = E * E * (0.5 * lam * (1 + c) ** 2 + mu)
+        return phi - 2 * H / (Gc / l + 2 * H)
+
+    for _ in range(4):
+        o = st.step()
+        E = o["E"]
+        lo, hi = 0.0, 1.0
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if resid(mid, E) > 0:
+                hi = mid
+            else:
+                lo = mid
+        phi = 0.5 * (lo + hi)
+        g = (1 - phi) ** 2 + k
+        c = -g * lam / (g * lam + 2 * mu)
+        assert np.abs(st.phi - phi).max() <= 1e-7 * phi, (st.phi.max(), phi)
+        S = o["sigma_M"]
+        sig = g * (lam * (1 + c) + 2 * mu) * E
+        assert abs(S[1, 1] - sig) <= 1e-7 * sig
+        # zero up to the mechanical Newton tolerance (1e-9 on the strain update)
+        assert abs(S[0, 0]) <= 1e-8 * sig and abs(S[0, 1]) <= 1e-8 * sig
+        m = st.eps_t.reshape(3, -1).mean(axis=-1)
+        assert abs(m[0] - c * E) <= 1e-7 * E
