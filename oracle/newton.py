@@ -130,6 +130,13 @@ class Solver:
             applies += info["applies"]
             d_eps, d_phi, dE = s.unpack(dx)
             d_phi = (1 - s.m) * d_phi
+            # E alone sets the mean strain along f (Sec. 2.3), so the
+            # fluctuation keeps no uniform part along f: (f t, -t) is a null
+            # direction of the bordered Jacobian (eps = eps~ + f E is
+            # unchanged), and a Krylov solve can wander along it
+            t = float(np.dot(d_eps.reshape(s.ncomp, -1).mean(axis=-1), s.f) / np.dot(s.f, s.f))
+            d_eps = d_eps - t * s.f.reshape((s.ncomp, 1, 1, 1))
+            dE = dE + t
             w = d_eps + s.fE(dE)
             eps_t = eps_t + self.alpha * d_eps
             phi = phi + self.alpha * d_phi

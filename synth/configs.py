@@ -207,6 +207,15 @@ def problem_config(name: str) -> Problem:
             name=name, shape=(n, n, n),
             phases=[(1.0, 0.3, 1e-3), (1e-6, 0.3, 1e-3)], phase_id=pid, mask=None,
             f=_dyad(2, 2), l=1.5, delta_a=2.0, n_increments=3, alpha=0.9)
+    if name == "part12":                 # the part24 recipe on a 12^3 cell (a quick 3D parity case)
+        n = 12
+        pid, _ = spheres_random(n, 2.0, 2.0, 0.15, seed=13, gap=1.0, fixed_radius=2.0)
+        f = _dyad(2, 2) + 0.3 * (2.0 * _dyad(0, 2))
+        return Problem(
+            name=name, shape=(n, n, n),
+            phases=[(1.0, 0.3, 1e-3), (8.0, 0.2, 5e-3)], phase_id=pid,
+            mask=penny_crack_mask(n, 6, 6, 6, 2), f=f, l=1.5, delta_a=1.0,
+            n_increments=3, alpha=0.9)
     if name == "part24":
         n = 24
         pid, _ = spheres_random(n, 3.0, 3.0, 0.15, seed=13, gap=1.0, fixed_radius=3.0)

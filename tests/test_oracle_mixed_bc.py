@@ -18,6 +18,8 @@ G(0) = P_f^perp (A -> A - fh (fh : A), fh = f / |f|).
   2D with a crack and two phases and in 3D with particles.
 * The staggered scheme (Algorithm 1) on the homogeneous cell: uniform damage
   at the root of the scalar fixed point phi(H(E, g(phi))), found by bisection.
+* (f t uniform, -t) is a null direction of the bordered Jacobian under either
+  condition, and the oracle's committed fluctuation has no mean along f.
 """
 
 import numpy as np
@@ -208,3 +210,35 @@ def test_staggered_homogeneous_uniaxial_stress():
         assert abs(S[0, 0]) <= 1e-8 * sig and abs(S[0, 1]) <= 1e-8 * sig
         m = st.eps_t.reshape(3, -1).mean(axis=-1)
         assert abs(m[0] - c * E) <= 1e-7 * E
+
+
+@pytest.mark.parametrize("case", ["gc16", "gc16_m", "part24_m"])
+def test_uniform_shift_along_f_is_a_null_direction(case):
+    """(d eps~ = f t uniform, d E = -t) leaves eps = eps~ + f E unchanged, so
+    the bordered Jacobian maps it to zero under either macroscopic condition;
+    E is fixed only by asking the fluctuation to carry no mean along f, which
+    the oracle's Newton enforces on every step."""
+    prob = problem_config(case)
+    sy = System(prob)
+    rng = np.random.default_rng(8)
+    eps_t = sy.G_mandel(rng.standard_normal((sy.ncomp,) + sy.shape) * 1e-3)
+    phi = np.clip(rng.uniform(0, 0.6, sy.shape) + sy.m, 0, 1)
+    E = 5e-3
+    Hn = sy.point(eps_t + sy.fE(E), phi, np.zeros(sy.shape))["psi_p"] * 0.8
+    J = sy.tangent(eps_t, phi, E, Hn)
+    t = 1e-3
+    n = sy.pack(np.broadcast_to(sy.fE(t), eps_t.shape), np.zeros(sy.shape), -t)
+    Jn = J(n)
+    ref = np.abs(J(sy.pack(sy.G_mandel(rng.standard_normal(eps_t.shape)) * t, np.zeros(sy.shape), 0.0))).max()
+    assert np.abs(Jn).max() <= 1e-13 * ref
+
+
+def test_committed_fluctuation_has_no_mean_along_f():
+    s = Solver(problem_config("tiny16_m"))
+    s.bootstrap()
+    for _ in range(2):
+        o = s.step()
+        assert o["converged"]
+        m = s.eps_t.reshape(s.sys.ncomp, -1).mean(axis=-1)
+        assert abs(np.dot(m, s.sys.f)) <= 1e-15 * np.abs(s.eps_t).max()
+        assert np.abs(m).max() > 1e-6 * o["E"]          # the free mean off f is there
