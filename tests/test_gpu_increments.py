@@ -76,7 +76,7 @@ TOL_FP64 = {"crack2d_64": 1e-7}
 @pytest.mark.parametrize("case", ["tiny16", "gc16", "fib64", "pore24", "part24", "crack2d_64",
                                   "gc16_iso", "part24_iso", "gc16_std", "gc16_w", "crack2d_39",
                                   "pore35", "gc16_d", "gc16_v", "tiny16_v", "gc16_m", "tiny16_m",
-                                  "part24_m"])
+                                  "part12", "part12_m"])
 def test_fp64_increments_match_oracle(case):
     g = golden(case)
     prob = problem_config(case)
@@ -104,7 +104,8 @@ def test_fp64_increments_match_oracle(case):
                                        ("pore24", 1e-6), ("part24", 1e-5), ("gc16_iso", 1e-6),
                                        ("part24_iso", 1e-5), ("gc16_std", 1e-6), ("gc16_w", 1e-6),
                                        ("crack2d_39", 1e-6), ("pore35", 1e-6), ("gc16_d", 1e-6),
-                                       ("gc16_v", 1e-6), ("gc16_m", 1e-6), ("part24_m", 1e-5)])
+                                       ("gc16_v", 1e-6), ("gc16_m", 1e-6), ("part12", 1e-5),
+                                       ("part12_m", 1e-5)])
 def test_mixed_increments_match_fp64_oracle(case, rtol):
     g = golden(case)
     prob = problem_config(case)
