@@ -23,7 +23,7 @@ from synth import problem_config  # noqa: E402
 CASES = {"tiny16": 4, "gc16": 4, "fib64": 4, "pore24": 3, "part24": 3, "crack2d_64": 30,
          "gc16_iso": 4, "part24_iso": 3, "gc16_std": 4, "gc16_w": 4,
          "crack2d_39": 4, "pore35": 1, "gc16_d": 4, "gc16_v": 4, "tiny16_v": 4,
-         "gc16_m": 4, "tiny16_m": 4, "part12": 3, "part12_m": 3}
+         "gc16_m": 4, "tiny16_m": 4, "part12": 3, "part12_m": 1}
 
 
 def run(case, n_inc):
