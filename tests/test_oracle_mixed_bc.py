@@ -20,6 +20,7 @@ G(0) = P_f^perp (A -> A - fh (fh : A), fh = f / |f|).
   at the root of the scalar fixed point phi(H(E, g(phi))), found by bisection.
 * (f t uniform, -t) is a null direction of the bordered Jacobian under either
   condition, and the oracle's committed fluctuation has no mean along f.
+* The stored mixed-condition runs are what the oracle computes now.
 """
 
 import numpy as np
@@ -242,3 +243,25 @@ def test_committed_fluctuation_has_no_mean_along_f():
         m = s.eps_t.reshape(s.sys.ncomp, -1).mean(axis=-1)
         assert abs(np.dot(m, s.sys.f)) <= 1e-15 * np.abs(s.eps_t).max()
         assert np.abs(m).max() > 1e-6 * o["E"]          # the free mean off f is there
+
+
+@pytest.mark.parametrize("case", ["tiny16_m", "gc16_m"])
+def test_stored_runs_are_what_the_oracle_computes(case):
+    """tests/golden/oracle_<case>.json (used by the GPU tests) is what the
+    oracle computes now, increment by increment (1e-9 relative: both stop on
+    a Newton update below 1e-8)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", f"oracle_{case}.json")) as fh:
+        g = json.load(fh)
+    s = Solver(problem_config(case))
+    boot = s.bootstrap()
+    assert abs(boot["a0"] - g["a0"]) <= 1e-12 * abs(g["a0"])
+    for ref in g["increments"][:2]:
+        o = s.step()
+        assert o["converged"]
+        assert abs(o["E"] - ref["E"]) <= 1e-9 * abs(ref["E"]), (o["E"], ref["E"])
+        assert abs(o["Gamma"] - ref["Gamma"]) <= 1e-9 * abs(ref["Gamma"])
+        sm = np.asarray(o["sigma_M"])
+        sv = np.array([sm[0, 0], sm[1, 1], sm[2, 2], sm[1, 2], sm[0, 2], sm[0, 1]])
+        assert np.abs(sv - np.asarray(ref["sigma_M"])).max() <= 1e-9 * np.abs(ref["sigma_M"]).max()
