@@ -386,7 +386,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce(const double* __restrict__ pa
   __shared__ double tot[kMaxRed];
   const double* src[kMaxRed];
 #pragma unroll
-  for (int q = 0; q < kMaxRed; ++q) src[q] = partials + (long long)q * nblk;
+  for (int q = 0; q < kMaxRed; ++q) src[q] = partials + (long long)(q < nslot ? q : 0) * nblk;
   block_slot_sums<kMaxRed>(src, nslot, nblk, tot);
   if (threadIdx.x == 0) Fin::run(F, tot);
 }
