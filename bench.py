@@ -5,10 +5,16 @@ update, FP64 residual, BiCGSTAB on the matrix-free bordered tangent,
 relaxed Newton updates and the history commit, i.e. every step of the hot
 path.  `value` is the in-solver throughput in Mvoxel tangent-applies/s
 (voxels x tangent applications / wall time of the K timed increments, all
-inputs resident in HBM).  The roofline object covers the dominant FFT pass
-kernel of the tangent apply, timed live with HIP events on the solver stream
-(every 7th apply sampled); `cpu_baseline` times the CPU oracle's tangent
-apply on a bounded sample of the same workload.
+inputs resident in HBM).  The roofline object covers the tangent apply,
+the unit of work of the metric: its algorithmic bytes (per voxel-apply:
+read the input vector, write J v, read the compact tangent state, one
+spectral round trip, the phase id) times the voxels, over the apply's
+average duration (its five FFT pass kernels and the finisher), timed live
+with HIP events on the solver stream (every 7th apply sampled).  The bare
+apply leg times 1000 applies on the frozen state of the last increment
+(median of 10 trials after 20 warm-ups), also for the other benchmark
+grids.  `cpu_baseline` times the CPU oracle's tangent apply on the full
+workload with every host core available to its FFTs.
 """
 
 from __future__ import annotations
@@ -26,6 +32,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BARE_WORKLOADS = ("crack2d_64", "fibres2d_256", "pores3d_64", "particles3d_128")
+
+
+def alg_bytes_per_voxel(prob, precision):
+    """Algorithmic HBM bytes of one voxel-apply of the bordered tangent:
+    read the input (c+1 words), write J v (c+1), read the compact tangent
+    state (strain c, phi, H, r: c+3), one spectral round trip (c+1 words
+    each way), plus 1 byte of phase id on a heterogeneous cell: 22 words in
+    2D (c = 3), 37 in 3D (c = 6)."""
+    words = 22 if prob.shape[0] == 1 else 37
+    T = 4 if precision == "mixed" else 8
+    return words * T + (1 if len(prob.phases) > 1 else 0)
 KERNEL_NAMES = {0: "x-forward pass (R2C, tangent prologue)",
                 1: "y pass (2D: forward, spectral stage, inverse)",
                 2: "z pass (forward, spectral stage, inverse)",
@@ -73,9 +91,11 @@ def src_hash():
     return h.hexdigest()
 
 
-def load_traffic(workload, kernel_id, launches_bytes):
-    """HBM traffic per launch from committed rocprofv3 counter summaries,
-    only if they were taken on the current kernel sources."""
+def load_traffic(workload):
+    """HBM traffic (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy
+    calibration) per apply, summed over the apply's kernels, from the
+    committed rocprofv3 counter summary, only if it was taken on the current
+    kernel sources."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -83,32 +103,23 @@ def load_traffic(workload, kernel_id, launches_bytes):
         d = json.load(fh)
     if d.get("kernel_src_sha1") != src_hash():
         return None
-    k = d.get("kernels", {}).get(str(kernel_id))
-    return None if k is None else k.get("hbm_bytes_per_launch")
+    return d.get("hbm_bytes_per_apply")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(prob, seconds=15.0, max_voxels=1 << 19):
-    """Oracle tangent apply (NumPy FP64) on a frozen state of the workload.
-    Workloads above max_voxels are timed on a corner crop of their phase map
-    (same phases and structure, fewer voxels): the rate is per voxel."""
-    import copy
-
+def cpu_baseline(prob, seconds=15.0):
+    """Oracle tangent apply (NumPy FP64, scipy.fft) on a frozen seeded state
+    of the whole workload, with os.cpu_count() FFT threads; the elementwise
+    NumPy work is single-threaded."""
     from oracle import fourier as fo
     from oracle.system import System
     from synth import random_state, random_vector
 
-    crop = None
-    if prob.nvox > max_voxels:
-        prob = copy.copy(prob)
-        n = 64 if prob.shape[0] > 1 else prob.shape[1]
-        crop = (min(n, prob.shape[0]), n, n)
-        prob.shape = crop
-        prob.phase_id = prob.phase_id[:crop[0], :crop[1], :crop[2]].copy()
-        prob.mask = None if prob.mask is None else prob.mask[:crop[0], :crop[1], :crop[2]].copy()
+    ncpu = os.cpu_count() or 1
+    fo.FFT_WORKERS = ncpu
     sysm = System(prob)
     eps, phi, Hn, E = random_state(sysm.shape, sysm.ncomp, 7, f_mandel=sysm.f, E=0.004)
     eps_t = fo.G_mandel(eps - sysm.fE(E))
@@ -117,19 +128,92 @@ def cpu_baseline(prob, seconds=15.0, max_voxels=1 << 19):
     J(v)
     n = 0
     w0, c0 = time.perf_counter(), time.process_time()
-    while time.perf_counter() - w0 < seconds:
+    while time.perf_counter() - w0 < seconds or n < 2:
         J(v)
         n += 1
     wall = time.perf_counter() - w0
     cpu = time.process_time() - c0
-    cores = max(1, int(round(cpu / wall)))
-    where = ("the " + "x".join(map(str, crop[::-1])) + " corner crop of the workload"
-             if crop else "the workload")
-    return {"value": n * sysm.N / wall / 1e6, "unit": "Mvoxel-applies/s", "cores": cores,
+    fo.FFT_WORKERS = 1
+    return {"value": round(n * sysm.N / wall / 1e6, 4), "unit": "Mvoxel-applies/s",
+            "cores": ncpu, "host_cpu_count": ncpu, "threads_busy_avg": round(cpu / wall, 2),
             "kind": "oracle",
-            "sample": f"{n} oracle tangent applies (NumPy FP64) on a frozen seeded state of "
-                      f"{where} ({sysm.N} voxels), {wall:.1f} s wall, "
-                      f"host threads used ~{cpu / wall:.2f}"}
+            "sample": f"{n} oracle tangent applies (NumPy FP64, scipy.fft with {ncpu} workers) on a "
+                      f"frozen seeded state of the whole {'x'.join(map(str, prob.shape[::-1]))} "
+                      f"workload, {wall:.1f} s wall"}
+
+
+def bare_apply(s, prob, precision, trials=10, n_applies=1000, warmup=20):
+    """Bare tangent applies at the solver's current tangent state: median of
+    `trials` timings of `n_applies` applies (HIP events on the solver stream,
+    torch's current stream) after `warmup` applies."""
+    import statistics
+
+    import torch
+
+    dt = torch.float32 if precision == "mixed" else torch.float64
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    v = torch.randn(s.M, dtype=dt, device="cuda", generator=g) * 1e-3
+    out = torch.empty_like(v)
+    for _ in range(warmup):
+        s.apply(v, out)
+    times = []
+    for _ in range(trials):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n_applies):
+            s.apply(v, out)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3 / n_applies)
+    t = statistics.median(times)
+    b = alg_bytes_per_voxel(prob, precision)
+    ach = b * prob.nvox / t / 1e9
+    return {"apply_us": round(t * 1e6, 2), "mvoxel_applies_per_s": round(prob.nvox / t / 1e6, 1),
+            "alg_bytes_per_voxel": b, "alg_GBs": round(ach, 1), "frac_of_hbm_peak": round(ach / HBM_PEAK_GBS, 4),
+            "trials": trials, "applies_per_trial": n_applies, "spread_us": [round(min(times) * 1e6, 2),
+                                                                            round(max(times) * 1e6, 2)]}
+
+
+def bare_apply_leg(name):
+    """Bootstrap and one increment of a benchmark grid, then bare applies at
+    its committed state."""
+    from paper_2412_17445_amd import Solver
+    from synth import problem_config
+
+    prob = problem_config(name)
+    s = Solver.from_problem(prob)
+    s.bootstrap()
+    o = s.step()
+    _, _, _, _, a = s.get_state()
+    s.residual(a, want_F=False)
+    r = bare_apply(s, prob, prob.precision)
+    s.close()
+    r.update(workload=name, grid=list(prob.shape[::-1]), precision=prob.precision,
+             state=f"committed state of increment 1 (converged={o['converged']})")
+    log(f"bare apply {name}: {r['apply_us']} us, {r['mvoxel_applies_per_s']} Mvoxel-applies/s, "
+        f"frac {r['frac_of_hbm_peak']}")
+    return r
+
+
+def vs_oracle(prob, outs, s):
+    """The benchmark's first increments against the oracle's stored ones (the
+    oracle's parity-mode roots; the benchmark runs its own tolerances)."""
+    import numpy as np
+
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_{prob.name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        g = json.load(fh)
+    res = []
+    for o, ref in zip(outs, g["increments"]):
+        sig, sref = np.array(o["sigma_M"]), np.array(ref["sigma_M"])
+        res.append({"increment": ref["increment"],
+                    "E": float("%.3e" % (abs(o["E"] - ref["E"]) / abs(ref["E"]))),
+                    "Gamma": float("%.3e" % (abs(o["Gamma"] - ref["Gamma"]) / abs(ref["Gamma"]))),
+                    "sigma_M": float("%.3e" % (np.abs(sig - sref).max() / np.abs(sref).max()))})
+    return res
 
 
 def compare_fp64(prob, args, mixed_outs, mixed_s_per_step):
@@ -376,6 +460,8 @@ def main():
     ap.add_argument("--no-odd", action="store_true",
                     help="skip the increment on a grid with prime factors above 3")
     ap.add_argument("--odd-workload", default="pores3d_105")
+    ap.add_argument("--no-bare-all", action="store_true",
+                    help="skip the bare-apply timing of the other benchmark grids")
     ap.add_argument("--no-mixed-bc", action="store_true",
                     help="skip the increments under mixed macroscopic conditions")
     ap.add_argument("--serve-requests", type=int, default=16)
@@ -450,38 +536,44 @@ def main():
     value = applies * N / elapsed / 1e6
 
     tim = s.timing_read()
-    # per (precision, pass kernel): algorithmic bytes and time over the timed
-    # launches of every apply mode
-    agg = {}
-    for slot, (n, ms) in tim.items():
-        group, k = divmod(slot, 6)
-        if k == 5:
-            continue
-        prec = "mixed" if group >= 5 else "fp64"
-        b = kernel_bytes(prob.shape, prec, group % 5)[k]
-        if b <= 0:
-            continue
-        a = agg.setdefault((prec, k), [0, 0.0, 0.0])
-        a[0] += n
-        a[1] += ms
-        a[2] += n * b
-    dom = max(agg, key=lambda q: agg[q][1])
-    n_dom, ms_dom, bytes_dom = agg[dom]
-    avg_ms = ms_dom / n_dom
-    alg_per_launch = bytes_dom / n_dom
-    achieved = alg_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = load_traffic(args.workload, dom[1], alg_per_launch) if dom[0] == "mixed" else None
+    prec_main = "mixed" if prob.precision == "mixed" else "fp64"
+    main_groups = range(5, 10) if prec_main == "mixed" else range(0, 5)
+    # whole apply (its five pass kernels and the finisher) over the sampled
+    # applies of the working precision, every fused variant
+    whole = [tim[6 * gp + 5] for gp in main_groups if 6 * gp + 5 in tim]
+    apply_n, apply_ms = sum(v[0] for v in whole), sum(v[1] for v in whole)
+    apply_s = apply_ms * 1e-3 / apply_n
+    bvox = alg_bytes_per_voxel(prob, prob.precision)
+    achieved = bvox * N / apply_s / 1e9
+    # per pass kernel: its own algorithmic bytes and time (secondary figures)
+    passes = {}
+    for gp in main_groups:
+        for k in range(5):
+            if 6 * gp + k not in tim:
+                continue
+            n, ms = tim[6 * gp + k]
+            b = kernel_bytes(prob.shape, prec_main, gp % 5)[k]
+            if b <= 0:
+                continue
+            a = passes.setdefault(k, [0, 0.0, 0.0])
+            a[0] += n
+            a[1] += ms
+            a[2] += n * b
+    pass_out = {KERNEL_NAMES[k]: {"avg_us": round(ms / n * 1e3, 2), "own_bytes_per_launch": round(b / n),
+                                  "own_GBs": round(b / n / (ms / n * 1e-3) / 1e9, 1)}
+                for k, (n, ms, b) in sorted(passes.items())}
+    traffic = load_traffic(args.workload)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": KERNEL_NAMES[dom[1]] + (" FP32" if dom[0] == "mixed" else " FP64"),
-                "alg_bytes_per_launch": round(alg_per_launch), "avg_launch_us": round(avg_ms * 1e3, 2),
-                "timed_launches": n_dom}
+                "kernel": "tangent apply (5 FFT pass kernels + finisher), "
+                          + ("FP32" if prec_main == "mixed" else "FP64"),
+                "alg_bytes_per_voxel_apply": bvox, "voxels_per_launch": N,
+                "alg_bytes_per_launch": bvox * N, "avg_launch_us": round(apply_s * 1e6, 2),
+                "timed_launches": apply_n, "passes": pass_out}
     by_mode = {"fp32": [0] * 5, "fp64": [0] * 5}
     for sl, (n, _) in tim.items():
         if sl % 6 == 5:
             by_mode["fp32" if sl // 6 >= 5 else "fp64"][(sl // 6) % 5] += n
-    whole = [v for sl, v in tim.items() if sl % 6 == 5]
-    apply_n, apply_ms = sum(v[0] for v in whole), sum(v[1] for v in whole)
     line = {
         "metric": "Mvoxel tangent-applies/s",
         "value": round(value, 2),
@@ -503,11 +595,20 @@ def main():
                    "fp64_applies": sum(o["applies_fp64"] for o in outs),
                    "fp64_refinements": sum(o["refinements"] for o in outs),
                    "fp64_fallback_solves": sum(o["fp64_fallbacks"] for o in outs),
-                   "apply_us_avg": round(apply_ms / max(apply_n, 1) * 1e3, 2),
+                   "apply_us_avg": round(apply_s * 1e6, 2),
                    "sampled_applies_by_mode": by_mode,
                    "parallelism": "single GPU"},
         "roofline": roofline,
     }
+    line["vs_oracle"] = vs_oracle(prob, warm + outs, s)
+    # bare applies at the committed state of the last timed increment
+    _, _, _, _, a_last = s.get_state()
+    s.residual(a_last, want_F=False)
+    line["bare_apply"] = bare_apply(s, prob, prob.precision)
+    line["bare_apply"]["state"] = f"committed state of increment {args.warmup + args.steps}"
+    log(f"bare apply: {line['bare_apply']}")
+    if not args.no_bare_all:
+        line["bare_apply_other_grids"] = [bare_apply_leg(w) for w in BARE_WORKLOADS if w != args.workload]
     if prob.precision == "mixed" and not args.no_compare:
         s.close()
         line["mixed_vs_fp64"] = compare_fp64(prob, args, warm + outs, elapsed / args.steps)

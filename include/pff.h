@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define PFF_ABI_VERSION 3
+#define PFF_ABI_VERSION 4
 
 typedef int pff_status;
 enum {
@@ -115,12 +115,22 @@ typedef struct {
  *               Sigma_M = s f.  Taken in the Galerkin form: the zero mode of
  *               G projects onto the orthogonal complement of f instead of
  *               vanishing, and the strain fluctuation (eps - f E) carries the
- *               free mean strain.  Needs f != 0. */
+ *               free mean strain.  Needs f != 0.
+ *  resid_tol    0 (default): Newton stops on the measures of eq.
+ *               errors_crack alone.  > 0 ("parity mode"): it also requires
+ *               the residual of eq. System_CrackLength at the new state to
+ *               satisfy ||F1|| / ||sigma|| <= resid_tol and ||F2|| / ||2H||
+ *               <= resid_tol (norms over all voxels; F1 and sigma in the
+ *               Mandel components of the strain unknowns).  With a relaxation
+ *               alpha < 1 Newton converges linearly, and the update measure
+ *               alone leaves the iterate as far from the root as its last
+ *               step; the residual stop pins the root itself. */
 typedef struct {
   double l, k_resid, f[9], delta_a, alpha, newton_tol, krylov_rtol;
   int newton_maxit, krylov_maxit, precision, split, projection, control, gc_form;
   double w_gamma, w_load;
   int macro_bc;
+  double resid_tol;
 } pff_params;
 
 enum { PFF_BC_STRAIN = 0, PFF_BC_MIXED = 1 };
@@ -147,17 +157,36 @@ typedef struct {
   double err[3];
   double seconds;
   double dissipation;      /* D = sum over voxels of Gc gamma_f (eq. JaviGc, middle form), h = 1 */
+  double resid[2];         /* ||F1|| / ||sigma||, ||F2|| / ||2H|| at the last Newton iterate */
 } pff_increment_result;
+
+/* Device memory hook.  alloc returns at least `bytes` of device memory of
+ * the device current at the call (aligned to 256 bytes), or NULL when it
+ * cannot; free returns a block alloc gave, with its size.  ctx is passed
+ * through.  The library calls them only from pff_create, from the lazy
+ * allocation of pff_project (FP32 spectra of an FP64 solver) and from
+ * pff_destroy, and for a request server from its worker threads, so they
+ * must be thread-safe there.  A NULL pff_allocator, or NULL alloc/free,
+ * means hipMalloc / hipFree.  A PyTorch caller passes its caching allocator,
+ * so that the solver's fields count in torch's memory accounting. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, size_t bytes, void* ctx);
+  void* ctx;
+} pff_allocator;
 
 int pff_abi_version(void);
 
 /* Create a solver.  phase_id: N bytes (host) with values < n_phases;
  * crack_mask: N bytes (host, 1 = initial crack, phi = 1 there) or NULL;
- * hip_stream: a hipStream_t or NULL for the default stream.
+ * allocator: device memory hook (copied; NULL = hipMalloc), every device
+ * buffer of the solver comes from it; hip_stream: a hipStream_t or NULL for
+ * the default stream.
  * Errors: PFF_ERR_ARG, PFF_ERR_OOM, PFF_ERR_DEVICE (*out is NULL then). */
 pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phases,
                       const uint8_t* phase_id, const uint8_t* crack_mask,
-                      const pff_params* params, void* hip_stream, pff_solver** out);
+                      const pff_params* params, const pff_allocator* allocator,
+                      void* hip_stream, pff_solver** out);
 
 /* Bootstrap (the paper is silent on the start of the path): damage-free Helmholtz
  * solution phi0 with phi = 1 on the crack mask, the control value a0 =
@@ -239,6 +268,17 @@ pff_status pff_stagger_step(pff_solver* s, double dE, const pff_stagger_params* 
  * eps_total C*N, phi N, Hn N (history), and scalars E, a. */
 pff_status pff_get_state(pff_solver* s, double* eps_total, double* phi, double* Hn,
                          double* E, double* a);
+
+/* Borrowed device pointers of the committed state (any output may be NULL):
+ * eps_tilde C*N doubles (the compatible strain fluctuation; the total strain
+ * adds f E), phi N doubles, Hn N doubles (history), in the layout of the
+ * conventions above.  The solver keeps ownership; the memory is valid until
+ * pff_destroy and holds the committed state between calls (pff_step,
+ * pff_stagger_step, pff_set_state and pff_load rewrite it).  Work queued on
+ * the solver's stream may still be writing it: synchronise that stream
+ * before reading on another one.  Writing through the pointers changes the
+ * committed state. */
+pff_status pff_device_views(pff_solver* s, double** eps_tilde, double** phi, double** Hn);
 
 /* Overwrite the committed state from host buffers (all required):
  * eps_tilde C*N (compatible fluctuation), phi N, Hn N, E, a.  Marks the
@@ -341,8 +381,11 @@ typedef struct {
   double clock;           /* server time of this snapshot */
 } pff_server_stats;
 
-/* Starts max_slots (1..64) worker threads.  PFF_ERR_DEVICE without a GPU. */
-pff_status pff_server_create(size_t hbm_budget_bytes, int max_slots, pff_server** out);
+/* Starts max_slots (1..64) worker threads.  allocator: as in pff_create
+ * (copied; NULL = hipMalloc), used for every request's solver from the
+ * worker threads.  PFF_ERR_DEVICE without a GPU. */
+pff_status pff_server_create(size_t hbm_budget_bytes, int max_slots, const pff_allocator* allocator,
+                             pff_server** out);
 /* Queues a request; *ticket identifies it.  PFF_ERR_ARG if its footprint
  * exceeds the budget. */
 pff_status pff_server_submit(pff_server* srv, const pff_grid* grid, const pff_phase* phases, int n_phases,
@@ -356,7 +399,8 @@ pff_status pff_server_info(pff_server* srv, uint64_t ticket, pff_request_info* o
  * *n_out = number available.  PFF_QUEUED if not finished. */
 pff_status pff_server_results(pff_server* srv, uint64_t ticket, pff_increment_result* out, int capacity,
                               int* n_out);
-/* Forgets a finished request. */
+/* Forgets a finished request.  PFF_ERR_STATE while it runs or while a
+ * thread waits on it in pff_server_wait. */
 pff_status pff_server_release(pff_server* srv, uint64_t ticket);
 pff_status pff_server_get_stats(pff_server* srv, pff_server_stats* out);
 const char* pff_server_last_error(pff_server* srv);

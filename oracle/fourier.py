@@ -38,6 +38,7 @@ Arrays are [z, y, x]; tensor index 0 <-> x, 1 <-> y, 2 <-> z.
 from __future__ import annotations
 
 import numpy as np
+import scipy.fft
 
 # Mandel ordering of symmetric tensors (inner product = Frobenius product).
 MANDEL3D = ((0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1))
@@ -151,12 +152,18 @@ def project_hat(A_hat, n, zero):
     return out
 
 
+# Threads of the library FFT (scipy.fft `workers`).  The transforms give the
+# same bits for any count; timing runs of the oracle on a many-core host
+# raise it, everything else leaves it at 1.
+FFT_WORKERS = 1
+
+
 def fftn(a):
-    return np.fft.fftn(a, axes=(-3, -2, -1))
+    return scipy.fft.fftn(a, axes=(-3, -2, -1), workers=FFT_WORKERS)
 
 
 def ifftn(a):
-    return np.fft.ifftn(a, axes=(-3, -2, -1))
+    return scipy.fft.ifftn(a, axes=(-3, -2, -1), workers=FFT_WORKERS)
 
 
 def G_tensor(A, scheme="rotated", free_mean=None):

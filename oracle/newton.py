@@ -30,6 +30,15 @@ Readings (see also `system`):
 * Dissipation control (eq. `SystemDis`, last line): Gamma is replaced by
   D = integral of Gc gamma_f in the constraint, its row (r -> Gc r), tau0
   and the predictor (S weighted by Gc).
+* Parity mode (`resid_tol` > 0): besides the update measures of eq.
+  `errors_crack`, Newton also requires the residual of eq.
+  `System_CrackLength` at the new state to be small, ||F1|| / ||sigma|| <=
+  resid_tol and ||F2|| / ||2H|| <= resid_tol (norms over all voxels, sigma
+  and F1 in the Mandel components of the strain unknowns).  The update
+  measure alone leaves a linearly converging iteration (relaxation
+  alpha < 1) as far from the root as its last step; the residual stop pins
+  the root itself, whatever the Krylov tolerance of the steps, so two
+  implementations that both meet it agree to the conditioning of the root.
 """
 
 from __future__ import annotations
@@ -44,8 +53,10 @@ BISECTION_STEPS = 100
 
 
 class Solver:
-    def __init__(self, prob, tol=None, rtol=None, kmaxit=None, alpha=None, maxit=None):
+    def __init__(self, prob, tol=None, rtol=None, kmaxit=None, alpha=None, maxit=None,
+                 resid_tol=0.0):
         self.sys = System(prob)
+        self.resid_tol = float(resid_tol)
         s = self.sys
         self.tol = prob.newton_tol if tol is None else tol
         self.rtol = prob.krylov_rtol if rtol is None else rtol
@@ -115,28 +126,50 @@ class Solver:
         return dict(a0=self.a, E_s=Es)
 
     # -- Newton -----------------------------------------------------------------
+    def compatible(self, x):
+        """The Krylov vector x with its strain block replaced by its projection
+        onto compatible fields (eq. `GFourier`)."""
+        s = self.sys
+        d_eps, d_phi, dE = s.unpack(x)
+        return s.pack(s.G_mandel(d_eps), d_phi, dE)
+
+    def residual_measures(self, R):
+        """(||F1|| / ||sigma||, ||F2|| / ||2H||) of a residual evaluation; a
+        zero numerator counts as zero whatever the scale."""
+        s = self.sys
+        sig = np.linalg.norm(fo.to_mandel(R["state"]["sigma"], s.ncomp))
+        h2 = 2.0 * np.linalg.norm(R["state"]["H"])
+        f1, f2 = np.linalg.norm(R["F1"]), np.linalg.norm(R["F2"])
+        rel = lambda num, den: 0.0 if num == 0.0 else (num / den if den > 0.0 else np.inf)  # noqa: E731
+        return rel(f1, sig), rel(f2, h2)
+
     def newton(self, eps_t, phi, E, a):
         s = self.sys
         kit = 0
         applies = 0
         err = np.inf
         errs = (np.inf, np.inf, np.inf)
+        res = (np.inf, np.inf)
+        R = s.residual(eps_t, phi, E, self.Hn, a)
         for it in range(1, self.maxit + 1):
-            R = s.residual(eps_t, phi, E, self.Hn, a)
             rhs = -s.pack(R["F1"], R["F2"], R["F3"])
             J = s.tangent(eps_t, phi, E, self.Hn)
-            dx, info = krylov.bicgstab(J, rhs, rtol=self.rtol, maxit=self.kmaxit)
+            # Newton on compatible strains: the strain unknown is a compatible
+            # fluctuation (Sec. 3.1), so the Krylov operator is J applied to
+            # the compatible part of its argument, and the step is that part.
+            # G[sigma] = 0 does not see an incompatible strain, so J alone has
+            # near-null directions made of incompatible strain coupled with
+            # damage and E wherever the history is at a tie (every warm start),
+            # which a Krylov solve can pick up.  Under mixed macroscopic
+            # conditions the projection also keeps the mean strain off f, so
+            # that E alone sets the mean along f: (f t, -t) is a null direction
+            # of the bordered system (eps = eps~ + f E is unchanged).
+            JP = lambda v: J(self.compatible(v))                        # noqa: E731
+            dx, info = krylov.bicgstab(JP, rhs, rtol=self.rtol, maxit=self.kmaxit)
             kit += info["iters"]
             applies += info["applies"]
-            d_eps, d_phi, dE = s.unpack(dx)
+            d_eps, d_phi, dE = s.unpack(self.compatible(dx))
             d_phi = (1 - s.m) * d_phi
-            # E alone sets the mean strain along f (Sec. 2.3), so the
-            # fluctuation keeps no uniform part along f: (f t, -t) is a null
-            # direction of the bordered Jacobian (eps = eps~ + f E is
-            # unchanged), and a Krylov solve can wander along it
-            t = float(np.dot(d_eps.reshape(s.ncomp, -1).mean(axis=-1), s.f) / np.dot(s.f, s.f))
-            d_eps = d_eps - t * s.f.reshape((s.ncomp, 1, 1, 1))
-            dE = dE + t
             w = d_eps + s.fE(dE)
             eps_t = eps_t + self.alpha * d_eps
             phi = phi + self.alpha * d_phi
@@ -147,12 +180,14 @@ class Solver:
                     np.linalg.norm(d_phi) / np.linalg.norm(phi),
                     abs(s.wa * q + s.wE * E - a) / abs(a))
             err = max(errs)
-            if err <= self.tol:
+            R = s.residual(eps_t, phi, E, self.Hn, a)
+            res = self.residual_measures(R)
+            if err <= self.tol and (self.resid_tol <= 0.0 or max(res) <= self.resid_tol):
                 return eps_t, phi, E, dict(converged=True, newton_iters=it,
                                            krylov_iters=kit, applies=applies,
-                                           err=errs)
+                                           err=errs, resid=res)
         return eps_t, phi, E, dict(converged=False, newton_iters=self.maxit,
-                                   krylov_iters=kit, applies=applies, err=errs)
+                                   krylov_iters=kit, applies=applies, err=errs, resid=res)
 
     def step(self):
         """One crack-length increment; returns the per-increment outputs."""

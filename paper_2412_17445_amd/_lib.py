@@ -36,7 +36,7 @@ class pff_params(C.Structure):
                 ("krylov_rtol", C.c_double), ("newton_maxit", C.c_int),
                 ("krylov_maxit", C.c_int), ("precision", C.c_int), ("split", C.c_int),
                 ("projection", C.c_int), ("control", C.c_int), ("gc_form", C.c_int), ("w_gamma", C.c_double),
-                ("w_load", C.c_double), ("macro_bc", C.c_int)]
+                ("w_load", C.c_double), ("macro_bc", C.c_int), ("resid_tol", C.c_double)]
 
 
 class pff_increment_result(C.Structure):
@@ -45,7 +45,15 @@ class pff_increment_result(C.Structure):
                 ("fp64_fallbacks", C.c_int), ("refinements", C.c_int), ("sigma_M", C.c_double * 6),
                 ("load_factor", C.c_double), ("crack_length", C.c_double),
                 ("target_a", C.c_double), ("err", C.c_double * 3), ("seconds", C.c_double),
-                ("dissipation", C.c_double)]
+                ("dissipation", C.c_double), ("resid", C.c_double * 2)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
+class pff_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
 
 
 class pff_stagger_params(C.Structure):
@@ -78,7 +86,8 @@ class pff_server_stats(C.Structure):
 EXPORTS = {
     "pff_abi_version": (C.c_int, []),
     "pff_create": (C.c_int, [C.POINTER(pff_grid), C.POINTER(pff_phase), C.c_int, C.c_void_p,
-                             C.c_void_p, C.POINTER(pff_params), C.c_void_p, C.POINTER(C.c_void_p)]),
+                             C.c_void_p, C.POINTER(pff_params), C.POINTER(pff_allocator), C.c_void_p,
+                             C.POINTER(C.c_void_p)]),
     "pff_bootstrap": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pff_step": (C.c_int, [C.c_void_p, C.POINTER(pff_increment_result)]),
     "pff_effective_toughness": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
@@ -88,6 +97,8 @@ EXPORTS = {
                                    C.POINTER(pff_stagger_result)]),
     "pff_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "pff_device_views": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                   C.POINTER(C.c_void_p)]),
     "pff_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                 C.c_double, C.c_int]),
     "pff_residual": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.POINTER(C.c_double),
@@ -106,7 +117,7 @@ EXPORTS = {
     "pff_destroy": (None, [C.c_void_p]),
     "pff_solver_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "pff_footprint_bytes": (C.c_int, [C.POINTER(pff_grid), C.c_int, C.POINTER(C.c_size_t)]),
-    "pff_server_create": (C.c_int, [C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),
+    "pff_server_create": (C.c_int, [C.c_size_t, C.c_int, C.POINTER(pff_allocator), C.POINTER(C.c_void_p)]),
     "pff_server_submit": (C.c_int, [C.c_void_p, C.POINTER(pff_grid), C.POINTER(pff_phase), C.c_int,
                                     C.c_void_p, C.c_void_p, C.POINTER(pff_params), C.c_int,
                                     C.POINTER(C.c_uint64)]),

@@ -61,6 +61,8 @@ enum {
   SC_ETA = 13,     // 2 slots: ||b - J x||^2, ||b||^2 of the FP64 check
   SC_DISS = 15,    // dissipation: sum of Gc gamma_f
   SC_F3 = 24,      // constraint residual F3 = w_a Gamma + w_E E - tau
+  SC_NSIG = 25,    // ||sigma||^2 (Mandel components of the strain unknowns)
+  SC_NH2 = 26,     // ||2H||^2
   SC_CG = 16,      // CG scratch (16..23); staggered scheme: [17] max |d eps~|, [18..21] stagger norms
   SC_KS = 32,      // Krylov scalars
   SC_COUNT = 64
@@ -126,8 +128,9 @@ struct pff_solver {
   bool plan_any = false;    // some axis has a prime factor above 3 (generic FFT stages)
   DevTables<double> td;
   DevTables<float> tf;
-  // device memory
-  std::vector<void*> allocs;
+  // device memory: every buffer comes from the caller's allocator (or hipMalloc)
+  pff_allocator allocator{nullptr, nullptr, nullptr};
+  std::vector<std::pair<void*, size_t>> allocs;
   uint8_t *pid = nullptr, *mask = nullptr;
   double *eps_t = nullptr, *phi = nullptr, *Hn = nullptr, *Hcur = nullptr;
   double* lap64 = nullptr;   // 2D: Laplacian of phi for the residual (N)
@@ -187,8 +190,18 @@ struct pff_solver {
   template <typename T> T* alloc(size_t count) {
     void* p = nullptr;
     const size_t b = std::max<size_t>(count, 1) * sizeof(T);
-    HC(hipMalloc(&p, b));
-    allocs.push_back(p);
+    if (allocator.alloc) {
+      p = allocator.alloc(b, allocator.ctx);
+      if (!p) throw Fail("device allocation of " + std::to_string(b) + " bytes failed (caller's allocator)",
+                         PFF_ERR_OOM);
+      if (reinterpret_cast<uintptr_t>(p) % 256 != 0) {
+        allocator.free(p, b, allocator.ctx);
+        throw Fail("the caller's allocator returned memory not aligned to 256 bytes", PFF_ERR_ARG);
+      }
+    } else {
+      HC(hipMalloc(&p, b));
+    }
+    allocs.emplace_back(p, b);
     bytes_alloc += b;
     return static_cast<T*>(p);
   }
@@ -594,6 +607,16 @@ struct FinNewton {
   }
 };
 
+// sums of the residual pass's prologue: sigma (6), ||sigma||^2, ||2H||^2
+struct FinSig {
+  struct Args { double* scal; };
+  __device__ static void run(const Args& F, const double* tot) {
+    for (int q = 0; q < 6; ++q) F.scal[SC_SIG + q] = tot[q];
+    F.scal[SC_NSIG] = tot[6];
+    F.scal[SC_NH2] = tot[7];
+  }
+};
+
 struct FinResid {
   struct Args {
     double* scal;
@@ -765,8 +788,7 @@ struct Impl {
     }
     int nblk = 0;
     run_pipeline<ResidualPipe<DIM>>(s, A, nblk);
-    FinStore::Args fs{s->scal + SC_SIG, 6};
-    k_reduce<FinStore><<<1, kBlock, 0, s->stream>>>(s->part0, nblk, 6, fs);
+    k_reduce<FinSig><<<1, kBlock, 0, s->stream>>>(s->part0, nblk, 8, FinSig::Args{s->scal});
     LAUNCH_CHECK();
     const long long last = (long long)(C + 1) * s->N;
     FinResid::Args fr{s->scal, a, s->wa, s->wE, s->dctl ? 1 : 0, s->Edev, vecs<double>(s, RHS) + last,
@@ -814,6 +836,9 @@ struct Impl {
     const int nb = red_blocks(M);
     const int g1 = nb;
     double* ks = s->scal + SC_KS;
+    // FP64 solves project the direction p after its update (keep_compatible),
+    // so they never form p inside the apply prologue (fused mode 2)
+    const int fused = std::is_same<TW, double>::value ? std::min(s->fused, 1) : s->fused;
     TW* xb[3] = {vec(s, X0), vec(s, X1), vec(s, X2)};
     TW *r = vec(s, R), *rhat = vec(s, RHAT), *p = vec(s, P), *v = vec(s, V), *sv = vec(s, S),
        *t = vec(s, T);
@@ -834,13 +859,13 @@ struct Impl {
       bool issued = false;   // this iteration's direction apply is already queued
       while (total < maxit) {
         ++total;
-        if (s->fused == 2) {
+        if (fused == 2) {
           // p = r + beta (p - omega v) formed in the prologue; v = J p; alpha = rho / (r_hat, v)
           if (!issued) apply_fused(s, 1, 1, p, r, v, p, v, rhat);
           issued = false;
           // s = r - alpha v formed in the prologue; t = J s; omega = (t, s) / (t, t)
           apply_fused(s, 2, 1, nullptr, r, v, sv, t, sv);
-        } else if (s->fused == 1) {
+        } else if (fused == 1) {
           // streaming p / s updates; inner products in the apply epilogues
           if (!issued) {
             k_bicg_p<TW><<<g1, kBlock, 0, s->stream>>>(p, r, v, ks, M);
@@ -879,8 +904,8 @@ struct Impl {
         // and x is untouched).
         HC(hipMemcpyAsync(s->hscal, s->scal, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s->stream));
         HC(hipEventRecord(s->ev_scal, s->stream));
-        if (s->fused != 0 && total < maxit) {
-          if (s->fused == 1) {
+        if (fused != 0 && total < maxit) {
+          if (fused == 1) {
             k_bicg_p<TW><<<g1, kBlock, 0, s->stream>>>(p, r, v, ks, M);
             LAUNCH_CHECK();
             keep_compatible(s, p);
@@ -1413,8 +1438,12 @@ void destroy_buffers(pff_solver* s) {
   s->tim_group.clear();
   if (s->ev_scal) (void)hipEventDestroy(s->ev_scal);
   s->ev_scal = nullptr;
-  for (void* p : s->allocs) (void)hipFree(p);
+  for (auto& pb : s->allocs) {
+    if (s->allocator.alloc) s->allocator.free(pb.first, pb.second, s->allocator.ctx);
+    else (void)hipFree(pb.first);
+  }
   s->allocs.clear();
+  s->bytes_alloc = 0;
   if (s->hscal) (void)hipHostFree(s->hscal);
   if (s->hstage) (void)hipHostFree(s->hstage);
   s->hscal = nullptr;
@@ -1432,14 +1461,16 @@ int pff_abi_version(void) { return PFF_ABI_VERSION; }
 const char* pff_last_error(const pff_solver* s) { return s ? s->err.c_str() : "null handle"; }
 
 pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phases, const uint8_t* phase_id,
-                      const uint8_t* crack_mask, const pff_params* params, void* hip_stream,
-                      pff_solver** out) {
+                      const uint8_t* crack_mask, const pff_params* params, const pff_allocator* allocator,
+                      void* hip_stream, pff_solver** out) {
   if (!out) return PFF_ERR_ARG;
   *out = nullptr;
   if (!grid || !phases || !phase_id || !params) return PFF_ERR_ARG;
   if (n_phases < 1 || n_phases > kMaxPhases) return PFF_ERR_ARG;
+  if (allocator && ((allocator->alloc == nullptr) != (allocator->free == nullptr))) return PFF_ERR_ARG;
   pff_solver* s = new (std::nothrow) pff_solver();
   if (!s) return PFF_ERR_OOM;
+  if (allocator && allocator->alloc) s->allocator = *allocator;
   pff_status st = guarded(s, [&]() -> pff_status {
     s->nx = grid->nx;
     s->ny = grid->ny;
@@ -1472,7 +1503,8 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
         (p.precision != PFF_PREC_FP64 && p.precision != PFF_PREC_MIXED) ||
         (p.split != PFF_SPLIT_SPECTRAL && p.split != PFF_SPLIT_NONE) ||
         (p.projection != PFF_PROJ_ROTATED && p.projection != PFF_PROJ_STANDARD) ||
-        !(p.w_gamma >= 0) || !(p.w_load >= 0) || !std::isfinite(p.w_gamma) || !std::isfinite(p.w_load))
+        !(p.w_gamma >= 0) || !(p.w_load >= 0) || !std::isfinite(p.w_gamma) || !std::isfinite(p.w_load) ||
+        !(p.resid_tol >= 0) || !std::isfinite(p.resid_tol))
       throw Fail("invalid solver parameters", PFF_ERR_ARG);
     if (p.control != PFF_CONTROL_LENGTH && p.control != PFF_CONTROL_DISSIPATION)
       throw Fail("invalid solver parameters", PFF_ERR_ARG);
@@ -1708,6 +1740,7 @@ pff_status pff_step(pff_solver* s, pff_increment_result* out) {
     }
     int conv = 0, it = 0;
     double err[3] = {0, 0, 0};
+    double res[2] = {0, 0};
     const bool trace = s->trace;
     const int fb0 = s->fallbacks;
     const int rf0 = s->refinements;
@@ -1740,8 +1773,16 @@ pff_status pff_step(pff_solver* s, pff_increment_result* out) {
         err[0] = std::sqrt(h[SC_NW]) / std::sqrt(h[SC_NEPS]);
         err[1] = std::sqrt(h[SC_NDPHI]) / std::sqrt(h[SC_NPHI]);
         err[2] = std::fabs(h[SC_F3]) / std::fabs(a_new);
+        // residual measures of the new state (parity-mode stop); a zero
+        // numerator is zero whatever the scale
+        auto rel = [](double num2, double den2) {
+          return num2 == 0.0 ? 0.0 : (den2 > 0.0 ? std::sqrt(num2 / den2) : HUGE_VAL);
+        };
+        res[0] = rel(h[SC_F1], h[SC_NSIG]);
+        res[1] = rel(h[SC_F2], h[SC_NH2]);
         const double e = std::max(err[0], std::max(err[1], err[2]));
-        if (e <= s->prm.newton_tol) {
+        const bool rok = !(s->prm.resid_tol > 0.0) || std::max(res[0], res[1]) <= s->prm.resid_tol;
+        if (e <= s->prm.newton_tol && rok) {
           conv = 1;
           break;
         }
@@ -1762,6 +1803,8 @@ pff_status pff_step(pff_solver* s, pff_increment_result* out) {
       out->converged = conv;
       out->target_a = a_new;
       for (int q = 0; q < 3; ++q) out->err[q] = err[q];
+      out->resid[0] = res[0];
+      out->resid[1] = res[1];
     }
     if (!conv) {
       // roll back to the committed increment
@@ -1896,6 +1939,15 @@ pff_status pff_get_state(pff_solver* s, double* eps_total, double* phi, double* 
     if (Hn) HC(hipMemcpy(Hn, s->Hn, N * sizeof(double), hipMemcpyDeviceToHost));
     if (E) *E = s->E;
     if (a) *a = s->a;
+    return PFF_OK;
+  });
+}
+
+pff_status pff_device_views(pff_solver* s, double** eps_tilde, double** phi, double** Hn) {
+  return guarded(s, [&]() -> pff_status {
+    if (eps_tilde) *eps_tilde = s->eps_c;
+    if (phi) *phi = s->phi_c;
+    if (Hn) *Hn = s->Hn;
     return PFF_OK;
   });
 }

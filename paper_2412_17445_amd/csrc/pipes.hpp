@@ -176,7 +176,9 @@ struct ResidualPipe {
   static constexpr int C = DIM == 2 ? 3 : 6;
   static constexpr int D = DIM == 2 ? 2 : 3;
   static constexpr int NF = C + 1;
-  static constexpr int NRED_PRO = 6;   // sum of sigma: 11, 22, 33, 23, 13, 12
+  // sums of sigma (11, 22, 33, 23, 13, 12), ||sigma||^2 over the Mandel
+  // components of the strain unknowns, ||2H||^2 (scales of the residual stop)
+  static constexpr int NRED_PRO = 8;
   static constexpr int NRED_EPI = 4;   // Gamma, ||F1||^2, ||F2||^2, dissipation
   struct Args {
     GridDesc g;
@@ -257,6 +259,11 @@ struct ResidualPipe {
       A.ts32[L::HS * N + i] = float(Hs);
     }
     out[C] = A.lap_ext ? 0.0 : phi;
+    double s2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < C; ++k) s2 += sm[k] * sm[k];
+    red[6] += s2;
+    red[7] += 4.0 * H * H;
     if constexpr (DIM == 2) {
       const double trp = sp.trp, trm = sp.tr - sp.trp;
       red[0] += Sg[0][0];

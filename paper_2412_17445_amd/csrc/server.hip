@@ -54,12 +54,14 @@ struct Request {
   double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
   int slot = -1;
   int skipped = 0;
+  int waiters = 0;        // threads inside pff_server_wait on this request
 };
 
 }  // namespace
 
 struct pff_server {
   int device = 0;
+  pff_allocator allocator{nullptr, nullptr, nullptr};   // for every request's solver
   size_t budget = 0;
   int nslots = 0;
   std::mutex m;
@@ -96,34 +98,50 @@ Request* pick(pff_server* S) {
   return nullptr;
 }
 
-void run_request(Request* r, hipStream_t st) {
+// Runs one request on the slot's stream.  Everything the request reports is
+// written under the server lock (pff_server_info reads it while it runs).
+void run_request(pff_server* S, Request* r, hipStream_t st) {
   pff_solver* s = nullptr;
   pff_status status = pff_create(&r->grid, r->phases.data(), (int)r->phases.size(), r->pid.data(),
-                                 r->has_mask ? r->mask.data() : nullptr, &r->prm, st, &s);
+                                 r->has_mask ? r->mask.data() : nullptr, &r->prm,
+                                 S->allocator.alloc ? &S->allocator : nullptr, st, &s);
   if (status != PFF_OK) {
+    std::lock_guard<std::mutex> lk(S->m);
     r->status = status;
     r->err = "pff_create failed";
     return;
   }
-  status = pff_bootstrap(s, &r->a0, &r->E_s);
+  double a0 = 0.0, E_s = 0.0;
+  status = pff_bootstrap(s, &a0, &E_s);
+  {
+    std::lock_guard<std::mutex> lk(S->m);
+    r->a0 = a0;
+    r->E_s = E_s;
+  }
   if (status == PFF_OK) {
     for (int k = 0; k < r->n_inc; ++k) {
       pff_increment_result res;
       std::memset(&res, 0, sizeof(res));
       const pff_status st2 = pff_step(s, &res);
-      r->results.push_back(res);
+      {
+        std::lock_guard<std::mutex> lk(S->m);
+        r->results.push_back(res);
+      }
       if (st2 != PFF_OK) {
         status = st2;
         break;
       }
     }
   }
+  std::string err;
   if (status != PFF_OK) {
     const char* e = pff_last_error(s);
-    r->err = e ? e : "";
+    err = e ? e : "";
   }
-  r->status = status;
   pff_destroy(s);
+  std::lock_guard<std::mutex> lk(S->m);
+  r->err = err;
+  r->status = status;
 }
 
 void worker(pff_server* S, int slot) {
@@ -144,14 +162,13 @@ void worker(pff_server* S, int slot) {
       S->running++;
       S->max_running = std::max(S->max_running, S->running);
     }
-    if (have_stream) {
-      run_request(r, st);
-    } else {
-      r->status = PFF_ERR_DEVICE;
-      r->err = "could not create a stream for the slot";
-    }
+    if (have_stream) run_request(S, r, st);
     {
       std::lock_guard<std::mutex> lk(S->m);
+      if (!have_stream) {
+        r->status = PFF_ERR_DEVICE;
+        r->err = "could not create a stream for the slot";
+      }
       S->in_use -= r->footprint;
       S->running--;
       S->completed++;
@@ -173,10 +190,12 @@ Request* find(pff_server* S, uint64_t ticket) {
 
 extern "C" {
 
-pff_status pff_server_create(size_t hbm_budget_bytes, int max_slots, pff_server** out) {
+pff_status pff_server_create(size_t hbm_budget_bytes, int max_slots, const pff_allocator* allocator,
+                             pff_server** out) {
   if (!out) return PFF_ERR_ARG;
   *out = nullptr;
   if (hbm_budget_bytes == 0 || max_slots < 1 || max_slots > kMaxSlots) return PFF_ERR_ARG;
+  if (allocator && ((allocator->alloc == nullptr) != (allocator->free == nullptr))) return PFF_ERR_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return PFF_ERR_DEVICE;
   auto* S = new (std::nothrow) pff_server();
@@ -187,6 +206,7 @@ pff_status pff_server_create(size_t hbm_budget_bytes, int max_slots, pff_server*
   }
   S->budget = hbm_budget_bytes;
   S->nslots = max_slots;
+  if (allocator && allocator->alloc) S->allocator = *allocator;
   S->t0 = std::chrono::steady_clock::now();
   for (int k = 0; k < max_slots; ++k) S->workers.emplace_back(worker, S, k);
   *out = S;
@@ -239,12 +259,15 @@ pff_status pff_server_wait(pff_server* S, uint64_t ticket, double timeout_second
   std::unique_lock<std::mutex> lk(S->m);
   Request* r = find(S, ticket);
   if (!r) return PFF_ERR_ARG;
+  // the request stays alive while it has waiters: pff_server_release refuses it
+  r->waiters++;
   auto done = [&] { return r->state == RQ_DONE; };
   if (timeout_seconds < 0) {
     S->cv_done.wait(lk, done);
   } else {
     S->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_seconds), done);
   }
+  r->waiters--;
   return done() ? PFF_OK : PFF_QUEUED;
 }
 
@@ -286,7 +309,7 @@ pff_status pff_server_release(pff_server* S, uint64_t ticket) {
   std::lock_guard<std::mutex> lk(S->m);
   auto it = S->all.find(ticket);
   if (it == S->all.end()) return PFF_ERR_ARG;
-  if (it->second->state != RQ_DONE) return PFF_ERR_STATE;
+  if (it->second->state != RQ_DONE || it->second->waiters > 0) return PFF_ERR_STATE;
   S->all.erase(it);
   return PFF_OK;
 }

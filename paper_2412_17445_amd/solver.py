@@ -31,7 +31,7 @@ def marshal_problem(shape, phases, phase_id, mask, f, l, k=1e-6, delta_a=1.0, al
                     newton_tol=1e-8, krylov_rtol=1e-10, newton_maxit=50, krylov_maxit=5000,
                     precision="fp64", split="spectral", projection="rotated",
                     control_weights=(1.0, 0.0), control="length", gc_form="pointwise",
-                    macro_bc="strain"):
+                    macro_bc="strain", resid_tol=0.0):
     """C structs and host arrays of one RVE problem (pff_create's inputs).
     split: "spectral" (Miehe split) or "none" (isotropic degradation);
     projection: "rotated" (Willot) or "standard" frequencies in G;
@@ -39,7 +39,8 @@ def marshal_problem(shape, phases, phase_id, mask, f, l, k=1e-6, delta_a=1.0, al
     control: Q is "length" (Gamma) or "dissipation" (sum of Gc gamma_f);
     gc_form: "pointwise" Gc l Lap phi or "variational" l div(Gc grad phi);
     macro_bc: "strain" (mean strain f E) or "mixed" (mean strain prescribed
-    along f only, mean stress zero on the directions orthogonal to f)."""
+    along f only, mean stress zero on the directions orthogonal to f);
+    resid_tol: parity-mode residual stop of Newton (0 = off)."""
     if macro_bc not in ("strain", "mixed"):
         raise ValueError("macro_bc must be 'strain' or 'mixed'")
     if gc_form not in ("pointwise", "variational"):
@@ -72,6 +73,7 @@ def marshal_problem(shape, phases, phase_id, mask, f, l, k=1e-6, delta_a=1.0, al
     prm.control = L.PFF_CONTROL_DISSIPATION if control == "dissipation" else L.PFF_CONTROL_LENGTH
     prm.gc_form = L.PFF_GC_VARIATIONAL if gc_form == "variational" else L.PFF_GC_POINTWISE
     prm.macro_bc = L.PFF_BC_MIXED if macro_bc == "mixed" else L.PFF_BC_STRAIN
+    prm.resid_tol = float(resid_tol)
     return grid, ph, pid, msk, prm
 
 
@@ -95,7 +97,44 @@ def _result_dict(r):
                 converged=bool(r.converged), applies=r.applies, applies_fp64=r.applies_fp64,
                 fp64_fallbacks=r.fp64_fallbacks, refinements=r.refinements,
                 sigma_M=list(r.sigma_M), E=r.load_factor, Gamma=r.crack_length,
-                a=r.target_a, err=list(r.err), seconds=r.seconds, dissipation=r.dissipation)
+                a=r.target_a, err=list(r.err), seconds=r.seconds, dissipation=r.dissipation,
+                resid=list(r.resid))
+
+
+class TorchAllocator:
+    """pff_allocator backed by PyTorch's caching allocator on the current
+    device: the library's device buffers are torch allocations and count in
+    torch.cuda.memory_allocated().  Keeps the C callbacks alive; the blocks
+    are associated with `stream` (the library synchronises its stream before
+    freeing).  `requested` sums the bytes the library asked for."""
+
+    def __init__(self, stream=None):
+        torch = _torch()
+        self._torch = torch
+        self.device = torch.cuda.current_device()
+        self.stream = stream
+        self.requested = 0
+        self.live = {}
+
+        def _alloc(nbytes, ctx):
+            try:
+                ptr = self._torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except Exception:                   # out of memory: the library reports PFF_ERR_OOM
+                return None
+            self.live[ptr] = int(nbytes)
+            self.requested += int(nbytes)
+            return ptr
+
+        def _free(ptr, nbytes, ctx):
+            self.live.pop(ptr, None)
+            self._torch.cuda.caching_allocator_delete(ptr)
+
+        self._alloc = L.ALLOC_FN(_alloc)
+        self._free = L.FREE_FN(_free)
+        self.struct = L.pff_allocator(self._alloc, self._free, None)
+
+    def bytes_live(self):
+        return sum(self.live.values())
 
 
 class Solver:
@@ -105,7 +144,9 @@ class Solver:
                  newton_tol=1e-8, krylov_rtol=1e-10, newton_maxit=50, krylov_maxit=5000,
                  precision="fp64", split="spectral", projection="rotated",
                  control_weights=(1.0, 0.0), control="length", gc_form="pointwise",
-                 macro_bc="strain", stream=None):
+                 macro_bc="strain", resid_tol=0.0, stream=None, allocator="torch"):
+        """allocator: "torch" (device buffers from torch's caching allocator,
+        the default), "hip" (the library's own hipMalloc) or a TorchAllocator."""
         torch = _torch()
         self.lib = L.load()
         nz, ny, nx = shape
@@ -120,13 +161,19 @@ class Solver:
             newton_tol=newton_tol, krylov_rtol=krylov_rtol, newton_maxit=newton_maxit,
             krylov_maxit=krylov_maxit, precision=precision, split=split, projection=projection,
             control_weights=control_weights, control=control, gc_form=gc_form,
-            macro_bc=macro_bc)
+            macro_bc=macro_bc, resid_tol=resid_tol)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self._stream = stream
+        if allocator == "torch":
+            allocator = TorchAllocator(torch.cuda.current_stream())
+        elif allocator == "hip":
+            allocator = None
+        self.allocator = allocator
         h = C.c_void_p()
         st = self.lib.pff_create(C.byref(grid), ph, len(phases), pid.ctypes.data,
                                  None if msk is None else msk.ctypes.data, C.byref(prm),
+                                 None if allocator is None else C.byref(allocator.struct),
                                  C.c_void_p(stream), C.byref(h))
         if st != L.PFF_OK:
             raise PffError(st, "pff_create failed")
@@ -145,6 +192,13 @@ class Solver:
                   macro_bc=getattr(prob, "macro_bc", "strain"))
         kw.update(over)
         return cls(prob.shape, prob.phases, prob.phase_id, prob.mask, prob.f, prob.l, **kw)
+
+    def device_views(self):
+        """Borrowed device pointers (eps_tilde, phi, Hn) of the committed state."""
+        e, p, h = C.c_void_p(), C.c_void_p(), C.c_void_p()
+        self._check(self.lib.pff_device_views(self.h, C.byref(e), C.byref(p), C.byref(h)),
+                    "pff_device_views")
+        return e.value, p.value, h.value
 
     # -- helpers ------------------------------------------------------------
     def _check(self, st, what):
@@ -324,11 +378,16 @@ class Server:
     """Request server of the C ABI: RVE solves admitted by memory footprint
     into `slots` concurrent slots on the current device."""
 
-    def __init__(self, budget_bytes, slots):
+    def __init__(self, budget_bytes, slots, allocator=None):
+        """allocator: None (hipMalloc) or a TorchAllocator (its callbacks
+        run on the server's worker threads)."""
         _torch()
         self.lib = L.load()
+        self.allocator = allocator
         h = C.c_void_p()
-        st = self.lib.pff_server_create(int(budget_bytes), int(slots), C.byref(h))
+        st = self.lib.pff_server_create(int(budget_bytes), int(slots),
+                                        None if allocator is None else C.byref(allocator.struct),
+                                        C.byref(h))
         if st != L.PFF_OK:
             raise PffError(st, "pff_server_create")
         self.h = h

@@ -34,19 +34,20 @@ def test_library_exports_every_declared_symbol():
     lib = L.load()
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert lib.pff_abi_version() == 3
+    assert lib.pff_abi_version() == 4
 
 
 def test_struct_layouts():
     assert C.sizeof(L.pff_grid) == 12
     assert C.sizeof(L.pff_phase) == 24
-    # 2 doubles + f[9] + 4 doubles, 7 ints (+ padding), 2 doubles
-    assert C.sizeof(L.pff_params) == 8 * (2 + 9 + 4) + 4 * 7 + 4 + 8 * 2 + 4 + 4   # macro_bc + tail padding
-    assert C.sizeof(L.pff_increment_result) == 4 * 4 + 8 * 2 + 4 * 2 + 8 * (6 + 3 + 3 + 2)
+    # 2 doubles + f[9] + 4 doubles, 7 ints (+ padding), 2 doubles, macro_bc (+ padding), resid_tol
+    assert C.sizeof(L.pff_params) == 8 * (2 + 9 + 4) + 4 * 7 + 4 + 8 * 2 + 4 + 4 + 8
+    assert C.sizeof(L.pff_increment_result) == 4 * 4 + 8 * 2 + 4 * 2 + 8 * (6 + 3 + 3 + 2 + 2)
+    assert C.sizeof(L.pff_allocator) == 3 * 8
 
 
 STRUCTS = ["pff_grid", "pff_phase", "pff_params", "pff_increment_result", "pff_stagger_params",
-           "pff_stagger_result", "pff_request_info", "pff_server_stats"]
+           "pff_stagger_result", "pff_request_info", "pff_server_stats", "pff_allocator"]
 
 
 def test_ctypes_layouts_match_the_c_compiler(tmp_path):
@@ -90,14 +91,15 @@ def _create(grid, phases, pid, params):
     lib = L.load()
     h = C.c_void_p()
     ph = (L.pff_phase * len(phases))(*phases)
-    st = lib.pff_create(C.byref(grid), ph, len(phases), pid, None, C.byref(params), None, C.byref(h))
+    st = lib.pff_create(C.byref(grid), ph, len(phases), pid, None, C.byref(params), None, None,
+                        C.byref(h))
     return st, h
 
 
 def test_invalid_arguments_rejected_before_device_work():
     lib = L.load()
     h = C.c_void_p()
-    assert lib.pff_create(None, None, 0, None, None, None, None, C.byref(h)) == L.PFF_ERR_ARG
+    assert lib.pff_create(None, None, 0, None, None, None, None, None, C.byref(h)) == L.PFF_ERR_ARG
     pid = (C.c_ubyte * 64)()
     ok_phase = [L.pff_phase(1.0, 0.3, 1e-3)]
     # grid lengths above the 512 limit of the FFT tiles, and below the minimum
@@ -112,6 +114,16 @@ def test_invalid_arguments_rejected_before_device_work():
         assert st == L.PFF_ERR_ARG, opt
     st, h = _create(L.pff_grid(8, 8, 1), ok_phase, pid, _params(w_gamma=-1.0))
     assert st == L.PFF_ERR_ARG
+    for bad in (-1e-11, float("nan"), float("inf")):   # parity-mode residual tolerance
+        st, h = _create(L.pff_grid(8, 8, 1), ok_phase, pid, _params(resid_tol=bad))
+        assert st == L.PFF_ERR_ARG, bad
+    # an allocator with only one of its two functions
+    half = L.pff_allocator(L.ALLOC_FN(lambda n, c: None), L.FREE_FN(), None)
+    ph = (L.pff_phase * 1)(*ok_phase)
+    st = lib.pff_create(C.byref(L.pff_grid(8, 8, 1)), ph, 1, pid, None, C.byref(_params()), C.byref(half),
+                        None, C.byref(h))
+    assert st == L.PFF_ERR_ARG and not h.value
+    assert lib.pff_server_create(1 << 20, 1, C.byref(half), C.byref(h)) == L.PFF_ERR_ARG
     st, h = _create(L.pff_grid(8, 8, 1), ok_phase, pid, _params(gc_form=1, control=1))
     assert st == L.PFF_ERR_ARG                    # variational term with dissipation control
     p = _params(macro_bc=1)
@@ -137,5 +149,6 @@ def test_invalid_arguments_rejected_before_device_work():
     assert st == L.PFF_ERR_ARG
     # null handle calls
     assert lib.pff_step(None, None) == L.PFF_ERR_ARG
+    assert lib.pff_device_views(None, None, None, None) == L.PFF_ERR_ARG
     assert lib.pff_last_error(None) == b"null handle"
     lib.pff_destroy(None)

@@ -46,9 +46,9 @@ def test_server_refuses_to_start_without_a_device():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     h = C.c_void_p()
-    assert L.load().pff_server_create(1 << 30, 2, C.byref(h)) == L.PFF_ERR_DEVICE
+    assert L.load().pff_server_create(1 << 30, 2, None, C.byref(h)) == L.PFF_ERR_DEVICE
     assert not h.value
-    assert L.load().pff_server_create(0, 2, C.byref(h)) == L.PFF_ERR_ARG
+    assert L.load().pff_server_create(0, 2, None, C.byref(h)) == L.PFF_ERR_ARG
 
 
 # ---- GPU ----------------------------------------------------------------------
