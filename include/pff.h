@@ -305,6 +305,26 @@ pff_status pff_apply_tangent(pff_solver* s, const void* v_dev, void* Jv_dev);
  * prec selects double (0) or float (1) buffers. */
 pff_status pff_project(pff_solver* s, const void* in_dev, void* out_dev, int prec);
 
+/* pff_project without a solver and without allocating: for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same output as pff_project of a
+ * solver on this grid with the given projection scheme (PFF_PROJ_ROTATED or
+ * PFF_PROJ_STANDARD), the prescribed-mean-strain zero mode and the spectral
+ * Laplacian: out = [G(in_1..C) | Lap(in_{C+1})], C+1 fields of N values,
+ * double (prec 0) or float (prec 1), device buffers of the current device.
+ * The half spectra and axis tables live in a static device array of the
+ * library (64 MiB per device, held until the process ends), so the grid is
+ * limited to (C+1) (nx/2+1) ny nz complex values of the precision within
+ * 64 MiB - 256 KiB (e.g. 128^3 in float, 96^3 in double, 512^2 in either);
+ * larger grids return PFF_ERR_ARG before any device work.  The work is only
+ * queued on hip_stream (NULL: the default stream); the call neither
+ * allocates nor synchronises.  Every call on a device shares that device's
+ * array: calls that overlap on one GPU (on different streams or host
+ * threads) race and corrupt each other's results; serialise them.  Errors:
+ * PFF_ERR_ARG (NULL or aliasing buffers, sizes, options), PFF_ERR_DEVICE. */
+pff_status pff_project_noalloc(const pff_grid* grid, int projection, const void* in_dev, void* out_dev,
+                               int prec, void* hip_stream);
+
 /* Step (a7): BiCGSTAB on the tangent at the last residual state,
  * x = J^{-1} b.  b_dev, x_dev: Krylov vectors in working precision.
  * Outputs (may be NULL): iterations, relative residual of the returned

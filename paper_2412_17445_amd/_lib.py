@@ -105,6 +105,8 @@ EXPORTS = {
                                C.c_void_p, C.POINTER(C.c_double)]),
     "pff_apply_tangent": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pff_project": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "pff_project_noalloc": (C.c_int, [C.POINTER(pff_grid), C.c_int, C.c_void_p, C.c_void_p, C.c_int,
+                                      C.c_void_p]),
     "pff_krylov_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
                                    C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "pff_timing": (C.c_int, [C.c_void_p, C.c_int]),

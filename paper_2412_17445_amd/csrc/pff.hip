@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <type_traits>
@@ -295,13 +296,15 @@ size_t lds_axis(int n, int nfb, int tx, size_t csz) { return (size_t(nfb) * n * 
 
 // Runs the FFT round trip of pipe P: forward passes with its prologue, the
 // spectral stage, inverse passes with its epilogue.
-template <class P, bool ANY>
-void run_passes(pff_solver* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev) {
+// S: a solver, or any context with the same members (tables, spectra,
+// plans, launch knobs, stream).
+template <class P, bool ANY, class S>
+void run_passes(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev) {
   using T = typename P::real;
   constexpr int NF = P::NF;
   constexpr int NP = (NF + 1) / 2;
-  const DevTables<T>& tb = s->tables<T>();
-  cpx<T>* spec = s->spec<T>();
+  const DevTables<T>& tb = s->template tables<T>();
+  cpx<T>* spec = s->template spec<T>();
   const size_t csz = sizeof(cpx<T>);
   const int nthr = fft_threads(csz);
   const int nred = std::max(P::NRED_PRO, P::NRED_EPI);
@@ -361,8 +364,8 @@ void run_passes(pff_solver* s, const typename P::Args& A, int& nblk_x, hipEvent_
 
 // The kernels with the generic-radix FFT stage run only where a grid length
 // has a prime factor above 3.
-template <class P>
-void run_pipeline(pff_solver* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev = nullptr) {
+template <class P, class S>
+void run_pipeline(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev = nullptr) {
   if (s->plan_any) run_passes<P, true>(s, A, nblk_x, ev);
   else run_passes<P, false>(s, A, nblk_x, ev);
 }
@@ -1450,6 +1453,116 @@ void destroy_buffers(pff_solver* s) {
   s->hstage = nullptr;
 }
 
+// ---- allocation-free projection ------------------------------------------------
+//
+// pff_project_noalloc runs steps (a3)-(a5) on caller buffers for callers that
+// cannot allocate device memory (graph capture, serving loops): its spectra
+// and axis tables live in the library's static device array `scratch` (one
+// per device, held until the process ends) instead of a solver's buffers.
+
+struct NoAllocCtx {
+  int nx = 0, ny = 0, nz = 0, dim = 0;
+  GridDesc g{};
+  AxisPlan plan[3]{};
+  bool plan_any = false;
+  hipStream_t stream = nullptr;
+  // the launch configuration of a solver (pff_create's defaults)
+  int x_rows = 64, spec_threads = 512, spec_tx = 8, axis_threads = 0, axis_tx = 16, xcd_remap = 1;
+  size_t part_len = 0;                 // the projection has no reductions
+  double* part0 = nullptr;
+  double* part1 = nullptr;
+  DevTables<double> td;
+  DevTables<float> tf;
+  cpx<double>* spec_d = nullptr;
+  cpx<float>* spec_f = nullptr;
+  template <typename T> const DevTables<T>& tables() const;
+  template <typename T> cpx<T>* spec() const;
+};
+template <> const DevTables<double>& NoAllocCtx::tables<double>() const { return td; }
+template <> const DevTables<float>& NoAllocCtx::tables<float>() const { return tf; }
+template <> cpx<double>* NoAllocCtx::spec<double>() const { return spec_d; }
+template <> cpx<float>* NoAllocCtx::spec<float>() const { return spec_f; }
+
+// Per-axis tables of upload_tables (twiddles, rotated or standard symbol
+// factors, q^2 with the Nyquist mode kept), formed on the device in double.
+template <typename T>
+__global__ void k_axis_tables(cpx<T>* __restrict__ tw, T* __restrict__ hs, T* __restrict__ hc, T* __restrict__ q2,
+                              int n, int standard) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    double sn, cs;
+    sincospi(-2.0 * double(j) / double(n), &sn, &cs);
+    tw[j] = cpx<T>{T(cs), T(sn)};
+    const int m = (2 * j < n) ? j : j - n;                 // signed frequency, Nyquist reads -n/2
+    const bool nyq = n % 2 == 0 && 2 * j == n;
+    double sh, ch;
+    sincospi(double(m) / double(n), &sh, &ch);             // sin, cos of q/2
+    const double q = 2.0 * 3.14159265358979323846 * double(m) / double(n);
+    if (standard) {
+      hs[j] = nyq ? T(0) : T(q);
+      hc[j] = T(1);
+    } else {
+      hs[j] = T(sh);
+      hc[j] = nyq ? T(0) : T(ch);
+    }
+    q2[j] = T(q * q);
+  }
+}
+
+}  // namespace
+
+// Scratch of the allocation-free entry point: its spectra (C+1 half spectra,
+// at most kScratchBytes - kScratchTables bytes) and axis tables.  Host code
+// never uses this name as an address: the per-device address comes from
+// hipGetSymbolAddress.
+namespace {
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr size_t kScratchTables = size_t(256) << 10;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on the current device, looked up once per device.
+unsigned char* scratch_on_current_device() {
+  int dev = 0;
+  HC(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw Fail("device index out of range", PFF_ERR_DEVICE);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HC(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Fail("hipGetSymbolAddress returned no address for the scratch array", PFF_ERR_DEVICE);
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
+template <typename T>
+void noalloc_tables(NoAllocCtx& c, DevTables<T>& t, unsigned char* base, int standard) {
+  const int ns[3] = {c.nx, c.ny, c.nz};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* p = base + off;
+    off += (bytes + 255) / 256 * 256;
+    if (off > kScratchTables) throw Fail("axis tables exceed the scratch table area", PFF_ERR_ARG);
+    return p;
+  };
+  for (int a = 0; a < 3; ++a) {
+    const int n = ns[a];
+    t.tw[a] = reinterpret_cast<cpx<T>*>(take(n * sizeof(cpx<T>)));
+    t.hs[a] = reinterpret_cast<T*>(take(n * sizeof(T)));
+    t.hc[a] = reinterpret_cast<T*>(take(n * sizeof(T)));
+    t.q2[a] = reinterpret_cast<T*>(take(n * sizeof(T)));
+    k_axis_tables<T><<<(n + 255) / 256, 256, 0, c.stream>>>(t.tw[a], t.hs[a], t.hc[a], t.q2[a], n, standard);
+    LAUNCH_CHECK();
+  }
+  t.fh = nullptr;
+}
+
 }  // namespace
 
 // ================================================================== C ABI ====
@@ -2030,6 +2143,77 @@ pff_status pff_project(pff_solver* s, const void* in_dev, void* out_dev, int pre
     HC(hipStreamSynchronize(s->stream));
     return PFF_OK;
   });
+}
+
+pff_status pff_project_noalloc(const pff_grid* grid, int projection, const void* in_dev, void* out_dev,
+                               int prec, void* hip_stream) {
+  if (!grid || !in_dev || !out_dev || in_dev == out_dev || (prec != 0 && prec != 1) ||
+      (projection != PFF_PROJ_ROTATED && projection != PFF_PROJ_STANDARD))
+    return PFF_ERR_ARG;
+  NoAllocCtx c;
+  c.nx = grid->nx;
+  c.ny = grid->ny;
+  c.nz = grid->nz;
+  if (c.nx < 2 || c.ny < 2 || c.nz < 1 || c.nx > 512 || c.ny > 512 || c.nz > 512) return PFF_ERR_ARG;
+  if (!make_plan(c.nx, c.plan[0]) || !make_plan(c.ny, c.plan[1]) || !make_plan(c.nz, c.plan[2]))
+    return PFF_ERR_ARG;
+  for (int a = 0; a < 3; ++a)
+    for (int st = 0; st < c.plan[a].nstage; ++st) {
+      const int R = c.plan[a].radix[st];
+      if (R != 2 && R != 3 && R != 4 && R != 8) c.plan_any = true;
+    }
+  c.dim = c.nz == 1 ? 2 : 3;
+  const int C = c.dim == 2 ? 3 : 6;
+  const int nxh = c.nx / 2 + 1;
+  const long long N = (long long)c.nx * c.ny * c.nz, Nh = (long long)nxh * c.ny * c.nz;
+  const int nxm = c.nx % 2 == 0 ? c.nx / 2 : nxh;
+  c.g = GridDesc{c.nx, c.ny, c.nz, nxh, N, Nh, nxm, c.nx % 2 == 0 ? 1 : 0, (long long)nxm * c.ny * c.nz,
+                 make_fastdiv((uint32_t)nxm)};
+  const size_t spec_bytes = (size_t)(C + 1) * Nh * (prec == 0 ? sizeof(cpx<double>) : sizeof(cpx<float>));
+  if (spec_bytes > kScratchBytes - kScratchTables) return PFF_ERR_ARG;   // beyond the scratch array
+  c.stream = static_cast<hipStream_t>(hip_stream);
+  try {
+    unsigned char* base = scratch_on_current_device();
+    const int standard = projection == PFF_PROJ_STANDARD ? 1 : 0;
+    auto go = [&](auto tag, auto dimc) {
+      using T = decltype(tag);
+      constexpr int DIM = decltype(dimc)::value;
+      if constexpr (std::is_same<T, double>::value) {
+        noalloc_tables<double>(c, c.td, base, standard);
+        c.spec_d = reinterpret_cast<cpx<double>*>(base + kScratchTables);
+      } else {
+        noalloc_tables<float>(c, c.tf, base, standard);
+        c.spec_f = reinterpret_cast<cpx<float>*>(base + kScratchTables);
+      }
+      typename ProjectPipe<T, DIM>::Args A;
+      A.g = c.g;
+      A.in = static_cast<const T*>(in_dev);
+      A.out = static_cast<T*>(out_dev);
+      const DevTables<T>& t = c.template tables<T>();
+      for (int a = 0; a < 3; ++a) {
+        A.tab.hs[a] = t.hs[a];
+        A.tab.hc[a] = t.hc[a];
+        A.tab.q2[a] = t.q2[a];
+      }
+      A.tab.invN = T(1.0 / double(N));
+      A.tab.fh = nullptr;
+      int nblk = 0;
+      c.part_len = (size_t)c.ny * c.nz + 16;
+      run_pipeline<ProjectPipe<T, DIM>>(&c, A, nblk);
+    };
+    if (c.dim == 2) {
+      if (prec == 0) go(double(), std::integral_constant<int, 2>());
+      else go(float(), std::integral_constant<int, 2>());
+    } else {
+      if (prec == 0) go(double(), std::integral_constant<int, 3>());
+      else go(float(), std::integral_constant<int, 3>());
+    }
+  } catch (const Fail& e) {
+    return e.code;
+  } catch (const std::exception&) {
+    return PFF_ERR_DEVICE;
+  }
+  return PFF_OK;
 }
 
 pff_status pff_krylov_solve(pff_solver* s, const void* b_dev, void* x_dev, double rtol, int maxit, int* iters,
