@@ -125,6 +125,53 @@ template <typename T, int S, int P> __device__ __forceinline__ void dft_odd(cpx<
   v[0] = y0;
 }
 
+// cos(2 pi k / 32) for k = 0..8 (the first quadrant); the other angles of the
+// radix-16/32 butterflies follow by symmetry.
+__host__ __device__ constexpr double cos32_q(int k) {
+  constexpr double t[9] = {1.0, 0.98078528040323044913, 0.92387953251128675613, 0.83146961230254523708,
+                           0.70710678118654752440, 0.55557023301960222474, 0.38268343236508977173,
+                           0.19509032201612826785, 0.0};
+  return t[k];
+}
+__host__ __device__ constexpr double cos32(int k) {
+  k &= 31;
+  return k <= 8 ? cos32_q(k) : k <= 16 ? -cos32_q(16 - k) : k <= 24 ? -cos32_q(k - 16) : cos32_q(32 - k);
+}
+__host__ __device__ constexpr double sin32(int k) { return cos32(k + 24); }   // sin x = cos(x - pi/2)
+
+// R-point DFT (R a power of two up to 32) in registers, natural order in
+// and out: v[m] <- sum_r v[r] exp(S 2 pi i r m / R).  Radix-2 decimation in
+// time over the radix-8/4/2 butterflies, with compile-time twiddles.
+template <typename T, int S, int R> __device__ __forceinline__ void dft_pow2(cpx<T>* v) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 2) {
+    dft2<T, S>(v);
+  } else if constexpr (R == 4) {
+    dft4<T, S>(v);
+  } else if constexpr (R == 8) {
+    dft8<T, S>(v);
+  } else {
+    static_assert(R == 16 || R == 32, "radix");
+    constexpr int H = R / 2;
+    cpx<T> e[H], o[H];
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      e[k] = v[2 * k];
+      o[k] = v[2 * k + 1];
+    }
+    dft_pow2<T, S, H>(e);
+    dft_pow2<T, S, H>(o);
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const int m = k * (32 / R);
+      const cpx<T> w = {T(cos32(m)), T(S) * T(sin32(m))};
+      const cpx<T> t = cmul(o[k], w);
+      v[k] = cadd(e[k], t);
+      v[k + H] = csub(e[k], t);
+    }
+  }
+}
+
 template <typename T, int S, int R> __device__ __forceinline__ void dftR(cpx<T>* v) {
   if constexpr (R == 2) dft2<T, S>(v);
   else if constexpr (R == 3) dft3<T, S>(v);

@@ -222,6 +222,134 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_axis(co
   }
 }
 
+// The last axis of a 3D round trip (z) for lengths N = 32, 64, 128 as one
+// pass with the first and the last radix stage in registers: N = RA * 4,
+//   forward stage A (radix RA, span 1): loaded straight from the spectra,
+//                 written to LDS;
+//   forward stage B (radix 4, span RA), the spectral stage on the four modes
+//                 kz = j2 + r RA of the item (all NF fields at once) and the
+//                 inverse stage B' (radix 4, span 1), which reads exactly the
+//                 outputs of stage B: all in registers, one LDS read and one
+//                 LDS write;
+//   inverse stage A' (radix RA, span 4): read from LDS, stored straight to
+//                 the spectra.
+// Each element crosses the LDS twice per direction instead of once per
+// radix stage plus the staging copies.  Tiles as in k_axis (axis 2): TX
+// consecutive kx columns of the main block at one y, or TX consecutive y of
+// the Nyquist plane; RA * TX threads.
+template <class P, int N, int TX>
+__global__ void __launch_bounds__(N / 4 * TX) k_zspec(const typename P::Args A,
+                                                     const cpx<typename P::real>* __restrict__ tw_g,
+                                                     cpx<typename P::real>* __restrict__ spec, int remap) {
+  using T = typename P::real;
+  constexpr int NF = P::NF;
+  constexpr int RA = N / 4;
+  constexpr int NT = RA * TX;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const GridDesc& g = A.g;
+  int bx = blockIdx.x, by = blockIdx.y;
+  if (remap) {
+    const int nb = gridDim.x * gridDim.y;
+    const int per = nb / kXcds;
+    int b = blockIdx.y * gridDim.x + blockIdx.x;
+    if (b < per * kXcds) b = (b % kXcds) * per + b / kXcds;
+    bx = b % gridDim.x;
+    by = b / gridDim.x;
+  }
+  const int nkt = (g.nxm + TX - 1) / TX;
+  long long off0;
+  int js, ts, tc, kxb, kxs, kb, ks;
+  if (bx < nkt) {
+    const int kx0 = bx * TX;
+    tc = min(TX, g.nxm - kx0);
+    ts = 1;
+    kxb = kx0;
+    kxs = 1;
+    kb = by;
+    ks = 0;
+    off0 = (long long)by * g.nxm + kx0;
+    js = g.ny * g.nxm;
+  } else {
+    kxb = g.nx / 2;
+    kxs = 0;
+    const int q0 = by * TX;
+    if (q0 >= g.ny) return;
+    tc = min(TX, g.ny - q0);
+    kb = q0;
+    ks = 1;
+    off0 = g.Nm + q0;
+    js = g.ny;
+    ts = 1;
+  }
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw = buf + lds_padded((long long)NF * N * TX);
+  for (int t = threadIdx.x; t < N; t += NT) tw[t] = tw_g[t];
+  auto L = [](int f, int pos, int t) { return lpad((f * N + pos) * TX + t); };
+  // forward stage A
+  for (int item = threadIdx.x; item < NF * 4 * TX; item += NT) {
+    const int t = item % TX, j = (item / TX) % 4, f = item / (4 * TX);
+    const cpx<T>* src = spec + (long long)f * g.Nh + off0 + (long long)t * ts;
+    cpx<T> v[RA];
+#pragma unroll
+    for (int r = 0; r < RA; ++r) v[r] = t < tc ? src[(long long)(j + 4 * r) * js] : cpx<T>{T(0), T(0)};
+    dft_pow2<T, -1, RA>(v);
+#pragma unroll
+    for (int m = 0; m < RA; ++m) buf[L(f, j * RA + m, t)] = v[m];
+  }
+  __syncthreads();
+  {
+    const int t = threadIdx.x % TX, j2 = threadIdx.x / TX;
+    cpx<T> v[NF][4];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[f][r] = buf[L(f, j2 + r * RA, t)];
+#pragma unroll
+      for (int r = 1; r < 4; ++r) v[f][r] = cmul(v[f][r], tw[r * j2]);
+      dft4<T, -1>(v[f]);
+    }
+    if (t < tc) {
+      const int kx = kxb + t * kxs, ky = kb + t * ks;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        cpx<T> vals[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) vals[f] = v[f][r];
+        P::spectral(A, kx, ky, j2 + r * RA, vals);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) v[f][r] = vals[f];
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) dft4<T, 1>(v[f]);
+    __syncthreads();      // every stage-B read is done before the stage-B' writes
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) buf[L(f, j2 * 4 + r, t)] = v[f][r];
+  }
+  __syncthreads();
+  // inverse stage A'
+  for (int item = threadIdx.x; item < NF * 4 * TX; item += NT) {
+    const int t = item % TX, j = (item / TX) % 4, f = item / (4 * TX);
+    cpx<T> v[RA];
+#pragma unroll
+    for (int r = 0; r < RA; ++r) v[r] = buf[L(f, j + 4 * r, t)];
+#pragma unroll
+    for (int r = 1; r < RA; ++r) {
+      cpx<T> w = tw[r * j];
+      w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
+    dft_pow2<T, 1, RA>(v);
+    if (t < tc) {
+      cpx<T>* dst = spec + (long long)f * g.Nh + off0 + (long long)t * ts;
+#pragma unroll
+      for (int m = 0; m < RA; ++m) dst[(long long)(j + 4 * m) * js] = v[m];
+    }
+  }
+}
+
 template <class P, bool ANY>
 __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xinv(const typename P::Args A, const AxisPlan pl,
                                                  const cpx<typename P::real>* __restrict__ tw_g,

@@ -166,6 +166,7 @@ struct pff_solver {
   int axis_threads = 0, spec_threads = 0, axis_tx = 64, spec_tx = 64, x_rows = 64;
   double inner32 = 0.0;     // mixed: FP32 inner-solve tolerance (env PFF_INNER32)
   int xcd_remap = 1;        // z pass: consecutive tiles on one XCD (env PFF_XCD_REMAP)
+  int zspec = 1;            // z pass with register-resident end stages for nz = 32, 64, 128 (env PFF_ZSPEC)
   int fused = 1;            // BiCGSTAB steps fused into the applies (env PFF_FUSED): 0 none,
                             // 1 inner products in the epilogues, 2 also the p / s updates in the prologues
   hipEvent_t ev_scal = nullptr;   // marks the scalar copy of a BiCGSTAB iteration
@@ -296,6 +297,42 @@ size_t lds_axis(int n, int nfb, int tx, size_t csz) { return (size_t(nfb) * n * 
 
 // Runs the FFT round trip of pipe P: forward passes with its prologue, the
 // spectral stage, inverse passes with its epilogue.
+// Pipes of plane-strain problems never take the 3D z pass.
+template <class P> struct Only2D : std::false_type {};
+template <typename T> struct Only2D<TangentPipe<T, 2>> : std::true_type {};
+template <> struct Only2D<ResidualPipe<2>> : std::true_type {};
+template <> struct Only2D<CompatPipe<2>> : std::true_type {};
+template <typename T> struct Only2D<ProjectPipe<T, 2>> : std::true_type {};
+
+// The z pass with register-resident first and last radix stages (k_zspec),
+// for z lengths 32, 64 and 128; returns false where it does not apply.
+// FP32 tiles run 256 threads, FP64 tiles 128 (the same LDS bytes).
+template <class P, int N, class S>
+void launch_zspec_n(S* s, const typename P::Args& A, const cpx<typename P::real>* tw, cpx<typename P::real>* spec) {
+  using T = typename P::real;
+  constexpr int TX = (sizeof(T) == 4 ? 256 : 128) / (N / 4);
+  const size_t lds = (size_t(lds_padded((long long)P::NF * N * TX)) + N) * sizeof(cpx<T>);
+  const int nkt = (s->g.nxm + TX - 1) / TX;
+  const dim3 gs(nkt + s->g.nyq, s->ny, 1);
+  k_zspec<P, N, TX><<<gs, N / 4 * TX, lds, s->stream>>>(A, tw, spec, s->xcd_remap);
+  LAUNCH_CHECK();
+}
+
+template <class P, class S>
+bool launch_zspec(S* s, const typename P::Args& A, const cpx<typename P::real>* tw, cpx<typename P::real>* spec) {
+  if constexpr (Only2D<P>::value) {
+    return false;
+  } else {
+    if (!s->zspec) return false;
+    switch (s->nz) {
+      case 32: launch_zspec_n<P, 32>(s, A, tw, spec); return true;
+      case 64: launch_zspec_n<P, 64>(s, A, tw, spec); return true;
+      case 128: launch_zspec_n<P, 128>(s, A, tw, spec); return true;
+      default: return false;
+    }
+  }
+}
+
 // S: a solver, or any context with the same members (tables, spectra,
 // plans, launch knobs, stream).
 template <class P, bool ANY, class S>
@@ -348,9 +385,11 @@ void run_passes(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev) {
                                                              0);
     LAUNCH_CHECK();
     if (ev) HC(hipEventRecord(ev[2], s->stream));
-    k_axis<P, -1, true, ANY><<<gs, sthr, ldss, s->stream>>>(A, s->plan[2], tb.tw[2], spec, 2, log2i(txs), NF,
-                                                            s->xcd_remap);
-    LAUNCH_CHECK();
+    if (!launch_zspec<P>(s, A, tb.tw[2], spec)) {
+      k_axis<P, -1, true, ANY><<<gs, sthr, ldss, s->stream>>>(A, s->plan[2], tb.tw[2], spec, 2, log2i(txs), NF,
+                                                              s->xcd_remap);
+      LAUNCH_CHECK();
+    }
     if (ev) HC(hipEventRecord(ev[3], s->stream));
     k_axis<P, 1, false, ANY><<<gy, athr, ldsy, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txy), 1,
                                                             0);
@@ -1467,7 +1506,7 @@ struct NoAllocCtx {
   bool plan_any = false;
   hipStream_t stream = nullptr;
   // the launch configuration of a solver (pff_create's defaults)
-  int x_rows = 64, spec_threads = 512, spec_tx = 8, axis_threads = 0, axis_tx = 16, xcd_remap = 1;
+  int x_rows = 64, spec_threads = 512, spec_tx = 8, axis_threads = 0, axis_tx = 16, xcd_remap = 1, zspec = 1;
   size_t part_len = 0;                 // the projection has no reductions
   double* part0 = nullptr;
   double* part1 = nullptr;
@@ -1694,6 +1733,7 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     s->spec_tx = envi("PFF_SPEC_TX", 8);
     s->x_rows = envi("PFF_X_ROWS", 64);
     s->xcd_remap = envi("PFF_XCD_REMAP", 1) != 0 ? 1 : 0;
+    s->zspec = envi("PFF_ZSPEC", 1) != 0 ? 1 : 0;
     s->fused = std::min(2, std::max(0, envi("PFF_FUSED", 1)));
     if (s->var_het) s->fused = std::min(s->fused, 1);   // the variational term needs the input before the pass
     {

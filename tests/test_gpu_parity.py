@@ -41,6 +41,11 @@ def small_problem(name, shape=None, precision="fp64"):
 SHAPES = [("tiny16", None), ("tiny16", (1, 12, 18)), ("fib64", None), ("pore24", None),
           ("part24", (12, 18, 16)), ("part24", (9, 8, 6))]
 
+# z lengths 32, 64 and 128 take the z pass with register-resident end stages;
+# odd x lengths (no Nyquist plane) and other radices on x and y included
+ZSPEC_SHAPES = [("part24", (32, 12, 10)), ("pore24", (64, 6, 10)), ("part24", (128, 4, 6)),
+                ("part24", (32, 8, 9)), ("part24", (32, 7, 13))]
+
 
 def rel(a, b):
     return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
@@ -56,7 +61,8 @@ STD_SHAPES = [("tiny16_std", None), ("tiny16_std", (1, 12, 18)), ("tiny16_std", 
               ("part24_std", (12, 18, 16)), ("part24_std", (9, 8, 6))]
 
 
-@pytest.mark.parametrize("name,shape", SHAPES + STD_SHAPES + ODD_SHAPES)
+@pytest.mark.parametrize("name,shape", SHAPES + STD_SHAPES + ODD_SHAPES + ZSPEC_SHAPES +
+                         [("part24_std", (64, 8, 6))])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_projection_and_laplacian(name, shape, prec):
     prob = small_problem(name, shape)
@@ -74,7 +80,7 @@ def test_projection_and_laplacian(name, shape, prec):
     assert rel(out[c], refL) < tol
 
 
-@pytest.mark.parametrize("name,shape", SHAPES)
+@pytest.mark.parametrize("name,shape", SHAPES + ZSPEC_SHAPES)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_projection_of_nearly_equilibrated_field_stays_compatible(name, shape, prec):
     """G of a field that is mostly divergence-free (the residual near a root:
@@ -148,7 +154,8 @@ def _frozen_state(sysm, seed):
                                               ("part24", (5, 7, 10)), ("part24", (7, 11, 13)),
                                               ("gc16_d", None), ("part24_d", (9, 8, 6)),
                                               ("tiny16_v", None), ("gc16_v", None), ("part24_v", (9, 8, 6)),
-                                              ("part24_v", (12, 18, 16))])
+                                              ("part24_v", (12, 18, 16))] + ZSPEC_SHAPES +
+                         [("part24_iso", (32, 8, 9)), ("part24_std", (64, 8, 6)), ("part24_d", (32, 12, 10))])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_residual_and_tangent(name, shape, precision):
     prob = small_problem(name, shape, precision)
