@@ -355,7 +355,9 @@ pff_status pff_counters(pff_solver* s, long long* applies, long long* krylov_ite
 pff_status pff_save(pff_solver* s, void* buf, size_t* bytes);
 pff_status pff_load(pff_solver* s, const void* buf, size_t bytes);
 
-/* Text of the last error on this handle ("" if none). */
+/* Text of the last error on this handle ("" if none); with a NULL handle,
+ * the text of the last failed pff_create on the calling thread ("null
+ * handle" if none). */
 const char* pff_last_error(const pff_solver* s);
 
 void pff_destroy(pff_solver* s);
@@ -378,7 +380,15 @@ pff_status pff_footprint_bytes(const pff_grid* grid, int precision, size_t* byte
  * footprints of the running requests; a request that has been overtaken 8
  * times stops further overtaking.  Each slot is a host thread with its own
  * non-blocking HIP stream on the device current at pff_server_create, so
- * running requests overlap on the device.  A request gives the same
+ * running requests overlap on the device.  The FP32 Krylov solves of the
+ * mixed-precision requests are batched: an engine thread groups the solves
+ * in flight by grid and advances each group by a chunk of BiCGSTAB
+ * iterations (env PFF_BATCH_CHUNK, default 4) whose kernels each cover the
+ * whole group (at most PFF_BATCH_MAX solves, default 8), replayed from a
+ * captured HIP graph (PFF_BATCH_GRAPH=0: launched directly); a solve joins
+ * or leaves its group between chunks.  PFF_SERVER_BATCH=0 solves every
+ * request on its slot's stream instead.  The engine holds a few kilobytes of
+ * hipMalloc memory per grid.  A request gives the same
  * results alone and in a mix.  Inputs are copied at submission.  All
  * functions are thread-safe.  Times are seconds since pff_server_create. */
 typedef struct pff_server pff_server;
@@ -399,6 +409,12 @@ typedef struct {
   int slots, reserved;
   size_t budget, bytes_in_use, peak_bytes;
   double clock;           /* server time of this snapshot */
+  /* batched FP32 inner solves: chunks launched, solves and BiCGSTAB
+   * iterations finished, graphs captured, the largest and the mean number
+   * of solves in one chunk */
+  long long batch_chunks, batch_solves, batch_iterations, batch_graphs;
+  int batch_max, reserved2;
+  double batch_mean;
 } pff_server_stats;
 
 /* Starts max_slots (1..64) worker threads.  allocator: as in pff_create
@@ -423,6 +439,9 @@ pff_status pff_server_results(pff_server* srv, uint64_t ticket, pff_increment_re
  * thread waits on it in pff_server_wait. */
 pff_status pff_server_release(pff_server* srv, uint64_t ticket);
 pff_status pff_server_get_stats(pff_server* srv, pff_server_stats* out);
+/* Text of the last error of a server call, or of the last request that
+ * ended with an error or without convergence ("request <ticket> (status
+ * <status>): <text>"). */
 const char* pff_server_last_error(pff_server* srv);
 /* Finishes the running requests, drops the queued ones, joins the slots. */
 void pff_server_destroy(pff_server* srv);

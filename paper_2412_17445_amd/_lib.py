@@ -80,7 +80,10 @@ class pff_server_stats(C.Structure):
                 ("queued", C.c_longlong), ("running", C.c_longlong),
                 ("max_running", C.c_longlong), ("slots", C.c_int), ("reserved", C.c_int),
                 ("budget", C.c_size_t), ("bytes_in_use", C.c_size_t),
-                ("peak_bytes", C.c_size_t), ("clock", C.c_double)]
+                ("peak_bytes", C.c_size_t), ("clock", C.c_double), ("batch_chunks", C.c_longlong),
+                ("batch_solves", C.c_longlong), ("batch_iterations", C.c_longlong),
+                ("batch_graphs", C.c_longlong), ("batch_max", C.c_int), ("reserved2", C.c_int),
+                ("batch_mean", C.c_double)]
 
 
 EXPORTS = {
@@ -144,6 +147,14 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() or "
                            "python -m paper_2412_17445_amd.build")
+    # PyTorch ships its own HIP runtime (same soname as the system one, but
+    # loaded by file name).  Importing torch first makes the library bind to
+    # that runtime; loaded the other way round, the process would hold two
+    # HIP runtimes, and the second to initialise finds no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in EXPORTS.items():
         fn = getattr(lib, name)

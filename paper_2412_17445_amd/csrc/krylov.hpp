@@ -13,8 +13,17 @@ namespace pff {
 
 enum KrylovScalar {
   KS_RHO = 0, KS_RHO_OLD, KS_ALPHA, KS_OMEGA, KS_BETA, KS_RR, KS_BNORM, KS_FLAG,
-  KS_RV, KS_TS, KS_TT, KS_RNORM, KS_TRUE, KS_ULAST, KS_COUNT
+  KS_RV, KS_TS, KS_TT, KS_RNORM, KS_TRUE, KS_ULAST,
+  // device-side run control of the batched solves (k_fin_rr_b): stop flag
+  // (non-zero: every later kernel of this solve returns at once), reason,
+  // iteration count, current and best iterate buffers, best residual,
+  // rtol ||b|| and the iteration cap
+  KS_STOP, KS_REASON, KS_ITER, KS_CUR, KS_BEST, KS_RESBEST, KS_RTOLB, KS_MAXIT,
+  KS_COUNT
 };
+
+// reasons a batched run stops (KS_REASON)
+enum { KR_CONVERGED = 1, KR_BREAKDOWN = 2, KR_OTHER = 3, KR_MAXIT = 4 };
 
 constexpr int kRedBlocks = 1024;   // upper bound on the blocks of a vector reduction
 
@@ -402,5 +411,252 @@ struct FinLast {    // border row: J3 = w_a (r, d phi) + w_E dE into the trailin
     *F.dst = T(F.wa * tot[0] + F.wE * double(*F.vlast));
   }
 };
+
+// ---- batched BiCGSTAB (one solve per RVE of a size class, blockIdx.y) ------
+//
+// Every RVE of the batch runs its own iteration with its own scalars; the
+// arithmetic of each RVE is that of the kernels above, so a solve gives the
+// same bits alone and in a batch.  A stopped solve (KS_STOP) returns at the
+// top of every kernel, so a fixed chunk of iterations can be queued (or
+// replayed from a graph) without the host deciding between iterations.
+
+template <typename T> struct KryEntry {
+  T* x[3];            // iterate buffers: current, best and the next one rotate
+  T* r;
+  const T* rhat;
+  T* p;
+  T* v;
+  T* s;
+  T* t;
+  double* ks;         // Krylov scalars of this solve
+  double* part;       // partials of the vector reductions
+  double* part0;      // partials of the apply prologue (border row)
+  double* part1;      // partials of the apply epilogue (inner products)
+  double wa, wE;      // control weights of the border row
+};
+
+__device__ __forceinline__ int kry_next(const double* ks) {
+  const int cur = int(ks[KS_CUR]), best = int(ks[KS_BEST]);
+  int nxt = 0;
+  while (nxt == cur || nxt == best) ++nxt;
+  return nxt;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bicg_p_b(const KryEntry<T>* __restrict__ E, long long M) {
+  const KryEntry<T>& e = E[blockIdx.y];
+  if (e.ks[KS_STOP] != 0.0) return;
+  const T beta = T(e.ks[KS_BETA]), omega = T(e.ks[KS_OMEGA]);
+  T* __restrict__ p = e.p;
+  const T* __restrict__ r = e.r;
+  const T* __restrict__ v = e.v;
+  constexpr int W = Packet<T>::W;
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  long long i0 = 0;
+  if (aligned16(p, r, v)) {
+    const long long nv = M / W;
+    for (long long j = tid; j < nv; j += stride) {
+      const Lanes<T> rr = pk_load(r, j), pp = pk_load(p, j), vv = pk_load(v, j);
+      Lanes<T> o;
+#pragma unroll
+      for (int w = 0; w < W; ++w) o.v[w] = rr.v[w] + beta * (pp.v[w] - omega * vv.v[w]);
+      pk_store(p, j, o);
+    }
+    i0 = nv * W;
+  }
+  for (long long i = i0 + tid; i < M; i += stride) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bicg_s_b(const KryEntry<T>* __restrict__ E, long long M) {
+  const KryEntry<T>& e = E[blockIdx.y];
+  if (e.ks[KS_STOP] != 0.0) return;
+  const T alpha = T(e.ks[KS_ALPHA]);
+  T* __restrict__ sv = e.s;
+  const T* __restrict__ r = e.r;
+  const T* __restrict__ v = e.v;
+  constexpr int W = Packet<T>::W;
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  long long i0 = 0;
+  if (aligned16(sv, r, v)) {
+    const long long nv = M / W;
+    for (long long j = tid; j < nv; j += stride) {
+      const Lanes<T> rr = pk_load(r, j), vv = pk_load(v, j);
+      Lanes<T> o;
+#pragma unroll
+      for (int w = 0; w < W; ++w) o.v[w] = rr.v[w] - alpha * vv.v[w];
+      pk_store(sv, j, o);
+    }
+    i0 = nv * W;
+  }
+  for (long long i = i0 + tid; i < M; i += stride) sv[i] = r[i] - alpha * v[i];
+}
+
+// x[next] = x[cur] + alpha p + omega s ; r = s - omega t ; partials (r, r), (r_hat, r)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bicg_xr_b(const KryEntry<T>* __restrict__ E, long long M) {
+  const KryEntry<T>& e = E[blockIdx.y];
+  if (e.ks[KS_STOP] != 0.0) return;
+  const T alpha = T(e.ks[KS_ALPHA]), omega = T(e.ks[KS_OMEGA]);
+  T* __restrict__ xn = e.x[kry_next(e.ks)];
+  const T* __restrict__ x = e.x[int(e.ks[KS_CUR])];
+  const T* __restrict__ p = e.p;
+  const T* __restrict__ s = e.s;
+  const T* __restrict__ t = e.t;
+  T* __restrict__ r = e.r;
+  const T* __restrict__ rhat = e.rhat;
+  constexpr int W = Packet<T>::W;
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  double acc[2] = {0.0, 0.0};
+  long long i0 = 0;
+  if (aligned16(xn, x, p, s, t, r, rhat)) {
+    const long long nv = M / W;
+    for (long long j = tid; j < nv; j += stride) {
+      const Lanes<T> xx = pk_load(x, j), pp = pk_load(p, j), ss = pk_load(s, j), tt = pk_load(t, j),
+                     hh = pk_load(rhat, j);
+      Lanes<T> xo, ro;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        xo.v[w] = xx.v[w] + alpha * pp.v[w] + omega * ss.v[w];
+        const T ri = ss.v[w] - omega * tt.v[w];
+        ro.v[w] = ri;
+        acc[0] += double(ri) * double(ri);
+        acc[1] += double(hh.v[w]) * double(ri);
+      }
+      pk_store(xn, j, xo);
+      pk_store(r, j, ro);
+    }
+    i0 = nv * W;
+  }
+  for (long long i = i0 + tid; i < M; i += stride) {
+    const T si = s[i];
+    xn[i] = x[i] + alpha * p[i] + omega * si;
+    const T ri = si - omega * t[i];
+    r[i] = ri;
+    acc[0] += double(ri) * double(ri);
+    acc[1] += double(rhat[i]) * double(ri);
+  }
+  __shared__ double lds[2 * kBlock];
+  block_reduce<2>(acc, lds);
+  if (threadIdx.x == 0) {
+    e.part[blockIdx.x] = acc[0];
+    e.part[gridDim.x + blockIdx.x] = acc[1];
+  }
+}
+
+// finisher of the fused applies, one block per RVE (blockIdx.x): mode 1 is
+// v = J p with (r_hat, v), mode 2 t = J s with (t, s), (t, t); as k_fin_fused
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fin_fused_b(const KryEntry<T>* __restrict__ E, int nblk, int mode,
+                                                        long long last) {
+  const KryEntry<T>& e = E[blockIdx.x];
+  double* ks = e.ks;
+  if (ks[KS_STOP] != 0.0) return;
+  __shared__ double tot[3];
+  const double* const src[3] = {e.part0, e.part1, e.part1 + nblk};
+  block_slot_sums<3>(src, mode == 1 ? 2 : 3, nblk, tot);
+  if (threadIdx.x != 0) return;
+  const T* in = mode == 1 ? e.p : e.s;
+  T* Jv = mode == 1 ? e.v : e.t;
+  const T* dv = mode == 1 ? e.rhat : e.s;
+  const T j3 = T(e.wa * tot[0] + e.wE * double(in[last]));
+  const T dlast = dv[last];
+  Jv[last] = j3;
+  if (mode == 1) {
+    const double rv = tot[1] + double(dlast) * double(j3);
+    ks[KS_RV] = rv;
+    if (rv == 0.0 || !isfinite(rv)) {
+      ks[KS_FLAG] = 1.0;
+      ks[KS_ALPHA] = 0.0;
+    } else {
+      ks[KS_ALPHA] = ks[KS_RHO] / rv;
+    }
+  } else {
+    const double ts = tot[1] + double(j3) * double(dlast);
+    const double tt = tot[2] + double(j3) * double(j3);
+    ks[KS_TS] = ts;
+    ks[KS_TT] = tt;
+    if (tt == 0.0 || !isfinite(tt)) {
+      ks[KS_FLAG] = 2.0;
+      ks[KS_OMEGA] = 0.0;
+    } else {
+      ks[KS_OMEGA] = ts / tt;
+    }
+  }
+}
+
+// end of a batched iteration, one block per RVE: ||r||^2, the next rho and
+// beta (as FinRR), then the run control of the host loop: a breakdown
+// before the update (flag 1, 2) stops without adopting the new iterate;
+// otherwise the new iterate becomes current, the best is tracked, and the
+// run stops on convergence (||r|| <= rtol ||b||), on any other breakdown,
+// divergence or non-finite residual, or at the iteration cap.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fin_rr_b(const KryEntry<T>* __restrict__ E, int nb, double diverged) {
+  const KryEntry<T>& e = E[blockIdx.x];
+  double* ks = e.ks;
+  if (ks[KS_STOP] != 0.0) return;
+  __shared__ double tot[2];
+  const double* const src[2] = {e.part, e.part + nb};
+  block_slot_sums<2>(src, 2, nb, tot);
+  if (threadIdx.x != 0) return;
+  FinRR::run(FinRR::Args{ks}, tot);
+  const double flag = ks[KS_FLAG];
+  if (flag == 1.0 || flag == 2.0) {
+    ks[KS_STOP] = 1.0;
+    ks[KS_REASON] = KR_BREAKDOWN;
+    return;
+  }
+  ks[KS_ITER] += 1.0;
+  const int nxt = kry_next(ks);
+  ks[KS_CUR] = nxt;
+  const double res = sqrt(ks[KS_RR]);
+  if (res < ks[KS_RESBEST]) {
+    ks[KS_BEST] = nxt;
+    ks[KS_RESBEST] = res;
+  }
+  int reason = 0;
+  if (res <= ks[KS_RTOLB]) reason = KR_CONVERGED;
+  else if (flag != 0.0 || !isfinite(res) || res > diverged * ks[KS_BNORM]) reason = KR_OTHER;
+  else if (ks[KS_ITER] >= ks[KS_MAXIT]) reason = KR_MAXIT;
+  if (reason) {
+    ks[KS_STOP] = 1.0;
+    ks[KS_REASON] = reason;
+  }
+}
+
+// run control of a batched solve at the start of a run (one thread): the
+// first run starts from x = 0 with the best residual ||b|| (resbest < 0),
+// a later one from the best iterate `cur` with its true residual.  rtol ||b||
+// is formed from ||b|| on the device; b = 0 is solved at once.
+__global__ void k_ks_run_start(double* ks, double iter, double cur, double resbest, double rtol, double maxit) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const double bnorm = ks[KS_BNORM];
+    ks[KS_STOP] = bnorm == 0.0 ? 1.0 : 0.0;
+    ks[KS_REASON] = bnorm == 0.0 ? double(KR_CONVERGED) : 0.0;
+    ks[KS_ITER] = iter;
+    ks[KS_CUR] = cur;
+    ks[KS_BEST] = cur;
+    ks[KS_RESBEST] = resbest < 0.0 ? bnorm : resbest;
+    ks[KS_RTOLB] = rtol * bnorm;
+    ks[KS_MAXIT] = maxit;
+  }
+}
+
+// stop flag, reason, iteration count and best iterate of every solve of a
+// batch -> out[4 b ...]
+template <typename T>
+__global__ void k_gather_run(const KryEntry<T>* __restrict__ E, int B, double* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) {
+    out[4 * b] = E[b].ks[KS_STOP];
+    out[4 * b + 1] = E[b].ks[KS_REASON];
+    out[4 * b + 2] = E[b].ks[KS_ITER];
+    out[4 * b + 3] = E[b].ks[KS_BEST];
+  }
+}
 
 }  // namespace pff

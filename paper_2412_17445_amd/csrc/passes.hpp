@@ -36,11 +36,27 @@ template <typename T> struct SpecTables {
 // Max LDS elements per thread of the in-place FFT (64 KB per block).
 template <typename T> struct FftCap { static constexpr int MAXE = 8; };
 
+// One RVE of a batched launch: its pipe arguments, half spectra, partial-sum
+// buffers and the stop flag of its Krylov solve (non-zero: every block of
+// this RVE returns at once).  A batched launch adds one grid dimension over
+// the entries; an unbatched one passes a null batch and its own arguments.
+// Pipes whose kernels take batched launches (the others compile without
+// the batched branch).
+template <class P> struct Batchable : std::false_type {};
+
+template <class P> struct BatchEntry {
+  typename P::Args A;
+  cpx<typename P::real>* spec;
+  double* part0;
+  double* part1;
+  const double* stop;
+};
+
 template <class P, bool ANY>
-__global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xfwd(const typename P::Args A, const AxisPlan pl,
-                                                 const cpx<typename P::real>* __restrict__ tw_g,
-                                                 cpx<typename P::real>* __restrict__ spec,
-                                                 int rows_per_block, double* __restrict__ partials) {
+__device__ __forceinline__ void xfwd_body(const typename P::Args& A, const AxisPlan& pl,
+                                          const cpx<typename P::real>* __restrict__ tw_g,
+                                          cpx<typename P::real>* __restrict__ spec, int rows_per_block,
+                                          double* __restrict__ partials) {
   using T = typename P::real;
   constexpr int NF = P::NF;
   constexpr int NP = (NF + 1) / 2;
@@ -106,6 +122,24 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xfwd(co
   }
 }
 
+// rows_per_block rows of x per block (blockIdx.x); batched: RVE blockIdx.y
+template <class P, bool ANY>
+__global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xfwd(const typename P::Args A, const AxisPlan pl,
+                                                 const cpx<typename P::real>* __restrict__ tw_g,
+                                                 cpx<typename P::real>* __restrict__ spec,
+                                                 int rows_per_block, double* __restrict__ partials,
+                                                 const BatchEntry<P>* __restrict__ batch) {
+  if constexpr (Batchable<P>::value) {
+    if (batch) {
+      const BatchEntry<P>& e = batch[blockIdx.y];
+      if (e.stop && *e.stop != 0.0) return;
+      xfwd_body<P, ANY>(e.A, pl, tw_g, e.spec, rows_per_block, e.part0);
+      return;
+    }
+  }
+  xfwd_body<P, ANY>(A, pl, tw_g, spec, rows_per_block, partials);
+}
+
 constexpr int kXcds = 8;   // MI355X: workgroups are dispatched round-robin over 8 XCDs
 
 // Complex FFT along y (axis 1) or z (axis 2) for one tile and a group of NFB
@@ -121,10 +155,10 @@ constexpr int kXcds = 8;   // MI355X: workgroups are dispatched round-robin over
 // given to workgroups on the same XCD, so that two tiles sharing 128-byte
 // lines meet in that XCD's L2.
 template <class P, int S, bool SPECTRAL, bool ANY>
-__global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_axis(const typename P::Args A, const AxisPlan pl,
-                                                 const cpx<typename P::real>* __restrict__ tw_g,
-                                                 cpx<typename P::real>* __restrict__ spec, int axis,
-                                                 int ltx, int NFB, int remap) {
+__device__ __forceinline__ void axis_body(const typename P::Args& A, const AxisPlan& pl,
+                                          const cpx<typename P::real>* __restrict__ tw_g,
+                                          cpx<typename P::real>* __restrict__ spec, int axis, int ltx, int NFB,
+                                          int remap, int fg) {
   using T = typename P::real;
   constexpr int NF = P::NF;
   constexpr int MAXE = FftCap<T>::MAXE;
@@ -180,7 +214,7 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_axis(co
       ts = 1;
     }
   }
-  const int f0 = blockIdx.z * NFB;
+  const int f0 = fg * NFB;
   const int nfb = (f0 + NFB <= NF) ? NFB : NF - f0;
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* tw = buf + NFB * n * TX;
@@ -237,10 +271,29 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_axis(co
 // radix stage plus the staging copies.  Tiles as in k_axis (axis 2): TX
 // consecutive kx columns of the main block at one y, or TX consecutive y of
 // the Nyquist plane; RA * TX threads.
+// field groups of NFB fields on blockIdx.z; batched: blockIdx.z = RVE * NG +
+// group, NG = ceil(NF / NFB)
+template <class P, int S, bool SPECTRAL, bool ANY>
+__global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_axis(const typename P::Args A, const AxisPlan pl,
+                                                 const cpx<typename P::real>* __restrict__ tw_g,
+                                                 cpx<typename P::real>* __restrict__ spec, int axis,
+                                                 int ltx, int NFB, int remap,
+                                                 const BatchEntry<P>* __restrict__ batch) {
+  if constexpr (Batchable<P>::value) {
+    if (batch) {
+      const int ng = (P::NF + NFB - 1) / NFB;
+      const BatchEntry<P>& e = batch[blockIdx.z / ng];
+      if (e.stop && *e.stop != 0.0) return;
+      axis_body<P, S, SPECTRAL, ANY>(e.A, pl, tw_g, e.spec, axis, ltx, NFB, remap, blockIdx.z % ng);
+      return;
+    }
+  }
+  axis_body<P, S, SPECTRAL, ANY>(A, pl, tw_g, spec, axis, ltx, NFB, remap, blockIdx.z);
+}
+
 template <class P, int N, int TX>
-__global__ void __launch_bounds__(N / 4 * TX) k_zspec(const typename P::Args A,
-                                                     const cpx<typename P::real>* __restrict__ tw_g,
-                                                     cpx<typename P::real>* __restrict__ spec, int remap) {
+__device__ __forceinline__ void zspec_body(const typename P::Args& A, const cpx<typename P::real>* __restrict__ tw_g,
+                                           cpx<typename P::real>* __restrict__ spec, int remap) {
   using T = typename P::real;
   constexpr int NF = P::NF;
   constexpr int RA = N / 4;
@@ -350,11 +403,28 @@ __global__ void __launch_bounds__(N / 4 * TX) k_zspec(const typename P::Args A,
   }
 }
 
+// batched: RVE blockIdx.z
+template <class P, int N, int TX>
+__global__ void __launch_bounds__(N / 4 * TX) k_zspec(const typename P::Args A,
+                                                     const cpx<typename P::real>* __restrict__ tw_g,
+                                                     cpx<typename P::real>* __restrict__ spec, int remap,
+                                                     const BatchEntry<P>* __restrict__ batch) {
+  if constexpr (Batchable<P>::value) {
+    if (batch) {
+      const BatchEntry<P>& e = batch[blockIdx.z];
+      if (e.stop && *e.stop != 0.0) return;
+      zspec_body<P, N, TX>(e.A, tw_g, e.spec, remap);
+      return;
+    }
+  }
+  zspec_body<P, N, TX>(A, tw_g, spec, remap);
+}
+
 template <class P, bool ANY>
-__global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xinv(const typename P::Args A, const AxisPlan pl,
-                                                 const cpx<typename P::real>* __restrict__ tw_g,
-                                                 const cpx<typename P::real>* __restrict__ spec,
-                                                 int rows_per_block, double* __restrict__ partials) {
+__device__ __forceinline__ void xinv_body(const typename P::Args& A, const AxisPlan& pl,
+                                          const cpx<typename P::real>* __restrict__ tw_g,
+                                          const cpx<typename P::real>* __restrict__ spec, int rows_per_block,
+                                          double* __restrict__ partials) {
   using T = typename P::real;
   constexpr int NF = P::NF;
   constexpr int NP = (NF + 1) / 2;
@@ -427,6 +497,24 @@ __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xinv(co
     if (threadIdx.x == 0)
       for (int q = 0; q < NR; ++q) partials[(long long)q * gridDim.x + blockIdx.x] = red[q];
   }
+}
+
+// batched: RVE blockIdx.y
+template <class P, bool ANY>
+__global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xinv(const typename P::Args A, const AxisPlan pl,
+                                                 const cpx<typename P::real>* __restrict__ tw_g,
+                                                 const cpx<typename P::real>* __restrict__ spec,
+                                                 int rows_per_block, double* __restrict__ partials,
+                                                 const BatchEntry<P>* __restrict__ batch) {
+  if constexpr (Batchable<P>::value) {
+    if (batch) {
+      const BatchEntry<P>& e = batch[blockIdx.y];
+      if (e.stop && *e.stop != 0.0) return;
+      xinv_body<P, ANY>(e.A, pl, tw_g, e.spec, rows_per_block, e.part1);
+      return;
+    }
+  }
+  xinv_body<P, ANY>(A, pl, tw_g, spec, rows_per_block, partials);
 }
 
 // ---- spectral stage shared by the pipes -------------------------------------

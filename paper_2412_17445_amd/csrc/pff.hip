@@ -11,15 +11,21 @@
 #include <array>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <map>
+#include <memory>
+#include <thread>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
+#include "batch.hpp"
 #include "krylov.hpp"
 #include "pipes.hpp"
 
@@ -101,6 +107,12 @@ bool make_plan(int n, AxisPlan& pl) {
   return true;
 }
 
+// A graph under construction: kernel nodes appended in launch order (see launch_k).
+struct GraphRec {
+  hipGraph_t g = nullptr;
+  hipGraphNode_t last = nullptr;
+};
+
 template <typename T> struct DevTables {
   cpx<T>* tw[3] = {nullptr, nullptr, nullptr};
   T* hs[3] = {nullptr, nullptr, nullptr};
@@ -170,6 +182,9 @@ struct pff_solver {
   int fused = 1;            // BiCGSTAB steps fused into the applies (env PFF_FUSED): 0 none,
                             // 1 inner products in the epilogues, 2 also the p / s updates in the prologues
   hipEvent_t ev_scal = nullptr;   // marks the scalar copy of a BiCGSTAB iteration
+  pff::KBatcher* kb = nullptr;    // request server: FP32 inner solves batched across solvers
+  GraphRec* rec = nullptr;        // always null: a solver's passes are launched directly
+  hipEvent_t kb_ready = nullptr, kb_done = nullptr;   // hand-over events of a batched solve
   // sampled pass timing per slot 6 * (5 * fp32 + variant) + kernel, variant = mode + 2 * pro
   std::vector<std::array<hipEvent_t, 6>> tim_pending, tim_free;
   std::vector<int> tim_group;
@@ -297,6 +312,37 @@ size_t lds_axis(int n, int nfb, int tx, size_t csz) { return (size_t(nfb) * n * 
 
 // Runs the FFT round trip of pipe P: forward passes with its prologue, the
 // spectral stage, inverse passes with its epilogue.
+// Kernel launches of the pass runner: queued on the context's stream, or,
+// when the context records a graph (the request server's batched chunks),
+// appended to that graph as kernel nodes in launch order.  The graph is
+// built node by node rather than by stream capture, so that other threads
+// issuing HIP calls meanwhile (the server's slots) cannot invalidate it.
+template <typename... KArgs, typename... Args>
+void launch_k(GraphRec* rec, void (*kern)(KArgs...), dim3 grid, dim3 block, size_t shmem, hipStream_t st,
+              Args&&... args) {
+  if (!rec) {
+    hipLaunchKernelGGL(kern, grid, block, shmem, st, std::forward<Args>(args)...);
+    LAUNCH_CHECK();
+    return;
+  }
+  std::tuple<std::decay_t<KArgs>...> vals(std::forward<Args>(args)...);
+  void* params[sizeof...(KArgs) > 0 ? sizeof...(KArgs) : 1];
+  std::apply([&](auto&... v) {
+    int k = 0;
+    ((params[k++] = static_cast<void*>(&v)), ...);
+  }, vals);
+  hipKernelNodeParams kp{};
+  kp.func = reinterpret_cast<void*>(kern);
+  kp.gridDim = grid;
+  kp.blockDim = block;
+  kp.sharedMemBytes = (unsigned int)shmem;
+  kp.kernelParams = params;
+  kp.extra = nullptr;
+  hipGraphNode_t node = nullptr;
+  HC(hipGraphAddKernelNode(&node, rec->g, rec->last ? &rec->last : nullptr, rec->last ? 1 : 0, &kp));
+  rec->last = node;
+}
+
 // Pipes of plane-strain problems never take the 3D z pass.
 template <class P> struct Only2D : std::false_type {};
 template <typename T> struct Only2D<TangentPipe<T, 2>> : std::true_type {};
@@ -308,35 +354,38 @@ template <typename T> struct Only2D<ProjectPipe<T, 2>> : std::true_type {};
 // for z lengths 32, 64 and 128; returns false where it does not apply.
 // FP32 tiles run 256 threads, FP64 tiles 128 (the same LDS bytes).
 template <class P, int N, class S>
-void launch_zspec_n(S* s, const typename P::Args& A, const cpx<typename P::real>* tw, cpx<typename P::real>* spec) {
+void launch_zspec_n(S* s, const typename P::Args& A, const cpx<typename P::real>* tw, cpx<typename P::real>* spec,
+                    const BatchEntry<P>* batch, int B) {
   using T = typename P::real;
   constexpr int TX = (sizeof(T) == 4 ? 256 : 128) / (N / 4);
   const size_t lds = (size_t(lds_padded((long long)P::NF * N * TX)) + N) * sizeof(cpx<T>);
   const int nkt = (s->g.nxm + TX - 1) / TX;
-  const dim3 gs(nkt + s->g.nyq, s->ny, 1);
-  k_zspec<P, N, TX><<<gs, N / 4 * TX, lds, s->stream>>>(A, tw, spec, s->xcd_remap);
-  LAUNCH_CHECK();
+  const dim3 gs(nkt + s->g.nyq, s->ny, B);
+  launch_k(s->rec, k_zspec<P, N, TX>, gs, dim3(N / 4 * TX), lds, s->stream, A, tw, spec, s->xcd_remap, batch);
 }
 
 template <class P, class S>
-bool launch_zspec(S* s, const typename P::Args& A, const cpx<typename P::real>* tw, cpx<typename P::real>* spec) {
+bool launch_zspec(S* s, const typename P::Args& A, const cpx<typename P::real>* tw, cpx<typename P::real>* spec,
+                  const BatchEntry<P>* batch, int B) {
   if constexpr (Only2D<P>::value) {
     return false;
   } else {
     if (!s->zspec) return false;
     switch (s->nz) {
-      case 32: launch_zspec_n<P, 32>(s, A, tw, spec); return true;
-      case 64: launch_zspec_n<P, 64>(s, A, tw, spec); return true;
-      case 128: launch_zspec_n<P, 128>(s, A, tw, spec); return true;
+      case 32: launch_zspec_n<P, 32>(s, A, tw, spec, batch, B); return true;
+      case 64: launch_zspec_n<P, 64>(s, A, tw, spec, batch, B); return true;
+      case 128: launch_zspec_n<P, 128>(s, A, tw, spec, batch, B); return true;
       default: return false;
     }
   }
 }
 
 // S: a solver, or any context with the same members (tables, spectra,
-// plans, launch knobs, stream).
+// plans, launch knobs, stream).  batch: B entries of a batched launch (one
+// RVE each, their own arguments, spectra and partials), or null.
 template <class P, bool ANY, class S>
-void run_passes(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev) {
+void run_passes(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev, const BatchEntry<P>* batch,
+                int B) {
   using T = typename P::real;
   constexpr int NF = P::NF;
   constexpr int NP = (NF + 1) / 2;
@@ -353,8 +402,8 @@ void run_passes(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev) {
   nblk_x = (int)((nrows + rb - 1) / rb);
   if ((size_t)nblk_x > s->part_len) throw Fail("partial buffer too small", PFF_ERR_STATE);
   if (ev) HC(hipEventRecord(ev[0], s->stream));
-  k_xfwd<P, ANY><<<nblk_x, nthr, ldsx, s->stream>>>(A, s->plan[0], tb.tw[0], spec, rb, s->part0);
-  LAUNCH_CHECK();
+  launch_k(s->rec, k_xfwd<P, ANY>, dim3(nblk_x, B), dim3(nthr), ldsx, s->stream, A, s->plan[0], tb.tw[0], spec, rb,
+           s->part0, batch);
   if (ev) HC(hipEventRecord(ev[1], s->stream));
   // the spectral pass holds all NF fields of a tile
   const int last = s->dim == 2 ? 1 : 2;
@@ -364,11 +413,10 @@ void run_passes(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev) {
   const size_t ldss = lds_axis(nl, NF, txs, csz);
   if (ldss > kLdsBudget || size_t(NF) * nl * txs > size_t(maxe_of(csz)) * sthr)
     throw Fail("axis too long for the LDS budget", PFF_ERR_ARG);
-  const dim3 gs((s->g.nxm + txs - 1) / txs + s->g.nyq, last == 1 ? s->nz : s->ny, 1);
+  const dim3 gs((s->g.nxm + txs - 1) / txs + s->g.nyq, last == 1 ? s->nz : s->ny, B);
   if (s->dim == 2) {
-    k_axis<P, -1, true, ANY><<<gs, sthr, ldss, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txs), NF,
-                                                            0);
-    LAUNCH_CHECK();
+    launch_k(s->rec, k_axis<P, -1, true, ANY>, gs, dim3(sthr), ldss, s->stream, A, s->plan[1], tb.tw[1], spec, 1,
+             log2i(txs), NF, 0, batch);
     if (ev) {
       HC(hipEventRecord(ev[2], s->stream));
       HC(hipEventRecord(ev[3], s->stream));
@@ -380,33 +428,31 @@ void run_passes(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev) {
     const int athr = s->axis_threads > 0 ? std::min(s->axis_threads, nthr) : (csz == 8 ? 256 : 512);
     const int txy = choose_tx(s->ny, 1, csz, s->g.nxm, athr, s->axis_tx);
     const size_t ldsy = lds_axis(s->ny, 1, txy, csz);
-    const dim3 gy((s->g.nxm + txy - 1) / txy + s->g.nyq, s->nz, NF);
-    k_axis<P, -1, false, ANY><<<gy, athr, ldsy, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txy), 1,
-                                                             0);
-    LAUNCH_CHECK();
+    const dim3 gy((s->g.nxm + txy - 1) / txy + s->g.nyq, s->nz, NF * B);
+    launch_k(s->rec, k_axis<P, -1, false, ANY>, gy, dim3(athr), ldsy, s->stream, A, s->plan[1], tb.tw[1], spec, 1,
+             log2i(txy), 1, 0, batch);
     if (ev) HC(hipEventRecord(ev[2], s->stream));
-    if (!launch_zspec<P>(s, A, tb.tw[2], spec)) {
-      k_axis<P, -1, true, ANY><<<gs, sthr, ldss, s->stream>>>(A, s->plan[2], tb.tw[2], spec, 2, log2i(txs), NF,
-                                                              s->xcd_remap);
-      LAUNCH_CHECK();
+    if (!launch_zspec<P>(s, A, tb.tw[2], spec, batch, B)) {
+      launch_k(s->rec, k_axis<P, -1, true, ANY>, gs, dim3(sthr), ldss, s->stream, A, s->plan[2], tb.tw[2], spec, 2,
+               log2i(txs), NF, s->xcd_remap, batch);
     }
     if (ev) HC(hipEventRecord(ev[3], s->stream));
-    k_axis<P, 1, false, ANY><<<gy, athr, ldsy, s->stream>>>(A, s->plan[1], tb.tw[1], spec, 1, log2i(txy), 1,
-                                                            0);
-    LAUNCH_CHECK();
+    launch_k(s->rec, k_axis<P, 1, false, ANY>, gy, dim3(athr), ldsy, s->stream, A, s->plan[1], tb.tw[1], spec, 1,
+             log2i(txy), 1, 0, batch);
     if (ev) HC(hipEventRecord(ev[4], s->stream));
   }
-  k_xinv<P, ANY><<<nblk_x, nthr, ldsx, s->stream>>>(A, s->plan[0], tb.tw[0], spec, rb, s->part1);
-  LAUNCH_CHECK();
+  launch_k(s->rec, k_xinv<P, ANY>, dim3(nblk_x, B), dim3(nthr), ldsx, s->stream, A, s->plan[0], tb.tw[0], spec, rb,
+           s->part1, batch);
   if (ev) HC(hipEventRecord(ev[5], s->stream));
 }
 
 // The kernels with the generic-radix FFT stage run only where a grid length
 // has a prime factor above 3.
 template <class P, class S>
-void run_pipeline(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev = nullptr) {
-  if (s->plan_any) run_passes<P, true>(s, A, nblk_x, ev);
-  else run_passes<P, false>(s, A, nblk_x, ev);
+void run_pipeline(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev = nullptr,
+                  const BatchEntry<P>* batch = nullptr, int B = 1) {
+  if (s->plan_any) run_passes<P, true>(s, A, nblk_x, ev, batch, B);
+  else run_passes<P, false>(s, A, nblk_x, ev, batch, B);
 }
 
 // ---- live kernel timing (sampled event pairs on the solver stream) -------------
@@ -1245,6 +1291,494 @@ struct Impl {
   }
 };
 
+// ---- batched FP32 inner solves (request server) --------------------------------
+
+}  // namespace
+
+namespace pff {
+
+// One FP32 BiCGSTAB solve handed to the engine: x = J^{-1} b at the solver's
+// tangent state, with the run control of Impl::bicgstab (best iterate,
+// true-residual check and restart at the end of every run).
+struct KJob {
+  pff_solver* s = nullptr;
+  const float* b = nullptr;
+  float* x = nullptr;
+  double rtol = 0.0;
+  int maxit = 0;
+  hipStream_t slot = nullptr;   // the solver's own stream while the engine holds it
+  int cycle = 0, total = 0, best = 0, conv = 0;
+  double bnorm = 0.0, true_res = 0.0;
+  long long applies = 0;
+  bool finished = false;        // set under the batcher's lock
+  bool failed = false;          // a device error ended the solve
+};
+
+// Solves in flight on one grid (a size class): they share launches.  Acts as
+// the pass context of run_pipeline (plans, launch knobs, its own twiddles).
+struct KClass {
+  int nx = 0, ny = 0, nz = 0, dim = 0;
+  GridDesc g{};
+  AxisPlan plan[3]{};
+  bool plan_any = false;
+  hipStream_t stream = nullptr;
+  int x_rows = 64, spec_threads = 512, spec_tx = 8, axis_threads = 0, axis_tx = 16, xcd_remap = 1, zspec = 1;
+  GraphRec* rec = nullptr;     // set while a chunk graph is being built
+  size_t part_len = 0;
+  double* part0 = nullptr;
+  double* part1 = nullptr;
+  DevTables<float> tf;
+  DevTables<double> td;
+  long long N = 0, M = 0;
+  int C = 0;
+  std::vector<KJob*> pending, active;
+  // batch arrays (capacity bmax): entries of the two applies, Krylov entries
+  void* d_ent1 = nullptr;
+  void* d_ent2 = nullptr;
+  KryEntry<float>* d_kry = nullptr;
+  double* d_flags = nullptr;
+  unsigned char* h_ent1 = nullptr;   // pinned staging
+  unsigned char* h_ent2 = nullptr;
+  KryEntry<float>* h_kry = nullptr;
+  double* h_flags = nullptr;
+  std::vector<void*> dev_allocs;
+  std::map<int, hipGraphExec_t> graphs;   // per batch size
+  std::thread th;                         // this class's engine thread
+  std::condition_variable cv;             // new solves for it
+  template <typename T> const DevTables<T>& tables() const;
+  template <typename T> cpx<T>* spec() const { return nullptr; }
+};
+template <> const DevTables<float>& KClass::tables<float>() const { return tf; }
+template <> const DevTables<double>& KClass::tables<double>() const { return td; }
+
+struct KBatcher {
+  int device = 0, bmax = 8, chunk = 4, graph = 1;
+  std::mutex m;
+  std::condition_variable cv_done;
+  std::vector<std::unique_ptr<KClass>> classes;
+  bool stop = false;
+  KBatcherStats st{};
+  std::string err;
+};
+
+}  // namespace pff
+
+namespace {
+
+size_t entry_bytes(int dim) {
+  return dim == 2 ? sizeof(BatchEntry<TangentPipe<float, 2>>) : sizeof(BatchEntry<TangentPipe<float, 3>>);
+}
+
+void* kclass_alloc(KClass& c, size_t bytes) {
+  void* p = nullptr;
+  HC(hipMalloc(&p, bytes));
+  c.dev_allocs.push_back(p);
+  return p;
+}
+
+void class_engine(KBatcher* kb, KClass* c);
+
+// Size class of solver s (created on first use, with its engine thread,
+// under the batcher's lock).
+KClass* kclass_of(KBatcher* kb, pff_solver* s) {
+  for (auto& c : kb->classes)
+    if (c->nx == s->nx && c->ny == s->ny && c->nz == s->nz) return c.get();
+  auto c = std::make_unique<KClass>();
+  c->nx = s->nx;
+  c->ny = s->ny;
+  c->nz = s->nz;
+  c->dim = s->dim;
+  c->g = s->g;
+  for (int a = 0; a < 3; ++a) c->plan[a] = s->plan[a];
+  c->plan_any = s->plan_any;
+  c->x_rows = s->x_rows;
+  c->spec_threads = s->spec_threads;
+  c->spec_tx = s->spec_tx;
+  c->axis_threads = s->axis_threads;
+  c->axis_tx = s->axis_tx;
+  c->xcd_remap = s->xcd_remap;
+  c->zspec = s->zspec;
+  c->part_len = s->part_len;
+  c->N = s->N;
+  c->M = s->M;
+  c->C = s->C;
+  HC(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+  const int ns[3] = {s->nx, s->ny, s->nz};
+  for (int a = 0; a < 3; ++a) {
+    c->tf.tw[a] = static_cast<cpx<float>*>(kclass_alloc(*c, ns[a] * sizeof(cpx<float>)));
+    HC(hipMemcpy(c->tf.tw[a], s->tf.tw[a], ns[a] * sizeof(cpx<float>), hipMemcpyDeviceToDevice));
+  }
+  const size_t eb = entry_bytes(c->dim) * kb->bmax;
+  c->d_ent1 = kclass_alloc(*c, eb);
+  c->d_ent2 = kclass_alloc(*c, eb);
+  c->d_kry = static_cast<KryEntry<float>*>(kclass_alloc(*c, sizeof(KryEntry<float>) * kb->bmax));
+  c->d_flags = static_cast<double*>(kclass_alloc(*c, 4 * sizeof(double) * kb->bmax));
+  HC(hipHostMalloc((void**)&c->h_ent1, eb, hipHostMallocDefault));
+  HC(hipHostMalloc((void**)&c->h_ent2, eb, hipHostMallocDefault));
+  HC(hipHostMalloc((void**)&c->h_kry, sizeof(KryEntry<float>) * kb->bmax, hipHostMallocDefault));
+  HC(hipHostMalloc((void**)&c->h_flags, 4 * sizeof(double) * kb->bmax, hipHostMallocDefault));
+  KClass* cp = c.get();
+  kb->classes.push_back(std::move(c));
+  cp->th = std::thread(class_engine, kb, cp);
+  return cp;
+}
+
+void kclass_free(KClass& c) {
+  for (auto& ge : c.graphs) (void)hipGraphExecDestroy(ge.second);
+  c.graphs.clear();
+  if (c.stream) (void)hipStreamSynchronize(c.stream);
+  for (void* p : c.dev_allocs) (void)hipFree(p);
+  c.dev_allocs.clear();
+  if (c.h_ent1) (void)hipHostFree(c.h_ent1);
+  if (c.h_ent2) (void)hipHostFree(c.h_ent2);
+  if (c.h_kry) (void)hipHostFree(c.h_kry);
+  if (c.h_flags) (void)hipHostFree(c.h_flags);
+  if (c.stream) (void)hipStreamDestroy(c.stream);
+  c.stream = nullptr;
+}
+
+// The pipe and Krylov entries of one solve (FP32 vectors of the solver).
+template <int DIM>
+void fill_entries(KClass& c, int b, KJob* j) {
+  using I = Impl<DIM, float>;
+  using Pipe = TangentPipe<float, DIM>;
+  pff_solver* s = j->s;
+  float *r = I::vec(s, I::R), *rhat = I::vec(s, I::RHAT), *p = I::vec(s, I::P), *v = I::vec(s, I::V),
+        *sv = I::vec(s, I::S), *t = I::vec(s, I::T);
+  double* ks = s->scal + SC_KS;
+  BatchEntry<Pipe> e1{};
+  I::fill_tangent_args(s, e1.A);
+  e1.A.mode = 1;
+  e1.A.pro = 0;
+  e1.A.mech = 0;
+  e1.A.lgc = nullptr;
+  e1.A.r = e1.A.w = nullptr;
+  e1.A.vout = nullptr;
+  e1.A.ks = ks;
+  e1.spec = s->spec<float>();
+  e1.part0 = s->part0;
+  e1.part1 = s->part1;
+  e1.stop = ks + KS_STOP;
+  BatchEntry<Pipe> e2 = e1;
+  e1.A.v = p;
+  e1.A.Jv = v;
+  e1.A.dv = rhat;
+  e2.A.mode = 2;
+  e2.A.v = sv;
+  e2.A.Jv = t;
+  e2.A.dv = sv;
+  std::memcpy(c.h_ent1 + b * sizeof(e1), &e1, sizeof(e1));
+  std::memcpy(c.h_ent2 + b * sizeof(e2), &e2, sizeof(e2));
+  KryEntry<float> k{};
+  for (int q = 0; q < 3; ++q) k.x[q] = I::vec(s, I::X0 + q);
+  k.r = r;
+  k.rhat = rhat;
+  k.p = p;
+  k.v = v;
+  k.s = sv;
+  k.t = t;
+  k.ks = ks;
+  k.part = s->part0;
+  k.part0 = s->part0;
+  k.part1 = s->part1;
+  k.wa = s->wa;
+  k.wE = s->wE;
+  c.h_kry[b] = k;
+}
+
+// One BiCGSTAB iteration of every solve of the batch (the kernel sequence of
+// Impl::bicgstab with fused applies, one grid dimension over the solves).
+// The vector reduction of k_bicg_xr_b and the apply epilogues share the
+// solver's partial buffers in stream order, as in the unbatched solve.
+template <int DIM>
+void batched_iteration(KClass& c, int B) {
+  using Pipe = TangentPipe<float, DIM>;
+  const long long M = c.M;
+  const int g1 = red_blocks(M);
+  const long long last = (long long)(c.C + 1) * c.N;
+  const typename Pipe::Args none{};
+  auto* e1 = static_cast<const BatchEntry<Pipe>*>(c.d_ent1);
+  auto* e2 = static_cast<const BatchEntry<Pipe>*>(c.d_ent2);
+  int nblk = 0;
+  const KryEntry<float>* kry = c.d_kry;
+  launch_k(c.rec, k_bicg_p_b<float>, dim3(g1, B), dim3(kBlock), 0, c.stream, kry, M);
+  run_pipeline<Pipe>(&c, none, nblk, nullptr, e1, B);
+  launch_k(c.rec, k_fin_fused_b<float>, dim3(B), dim3(kBlock), 0, c.stream, kry, nblk, 1, last);
+  launch_k(c.rec, k_bicg_s_b<float>, dim3(g1, B), dim3(kBlock), 0, c.stream, kry, M);
+  run_pipeline<Pipe>(&c, none, nblk, nullptr, e2, B);
+  launch_k(c.rec, k_fin_fused_b<float>, dim3(B), dim3(kBlock), 0, c.stream, kry, nblk, 2, last);
+  launch_k(c.rec, k_bicg_xr_b<float>, dim3(g1, B), dim3(kBlock), 0, c.stream, kry, M);
+  launch_k(c.rec, k_fin_rr_b<float>, dim3(B), dim3(kBlock), 0, c.stream, kry, g1, kDiverged);
+}
+
+template <int DIM>
+void launch_chunk(KBatcher* kb, KClass& c, int B) {
+  const size_t eb = entry_bytes(c.dim);
+  HC(hipMemcpyAsync(c.d_ent1, c.h_ent1, eb * B, hipMemcpyHostToDevice, c.stream));
+  HC(hipMemcpyAsync(c.d_ent2, c.h_ent2, eb * B, hipMemcpyHostToDevice, c.stream));
+  HC(hipMemcpyAsync(c.d_kry, c.h_kry, sizeof(KryEntry<float>) * B, hipMemcpyHostToDevice, c.stream));
+  if (kb->graph) {
+    auto it = c.graphs.find(B);
+    if (it == c.graphs.end()) {
+      GraphRec rec;
+      HC(hipGraphCreate(&rec.g, 0));
+      c.rec = &rec;
+      try {
+        for (int k = 0; k < kb->chunk; ++k) batched_iteration<DIM>(c, B);
+      } catch (...) {
+        c.rec = nullptr;
+        (void)hipGraphDestroy(rec.g);
+        throw;
+      }
+      c.rec = nullptr;
+      hipGraphExec_t ex = nullptr;
+      const hipError_t e = hipGraphInstantiate(&ex, rec.g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(rec.g);
+      HC(e);
+      it = c.graphs.emplace(B, ex).first;
+      kb->st.graphs++;
+    }
+    HC(hipGraphLaunch(it->second, c.stream));
+  } else {
+    for (int k = 0; k < kb->chunk; ++k) batched_iteration<DIM>(c, B);
+  }
+  k_gather_run<float><<<1, 64, 0, c.stream>>>(c.d_kry, B, c.d_flags);
+  LAUNCH_CHECK();
+  HC(hipMemcpyAsync(c.h_flags, c.d_flags, 4 * sizeof(double) * B, hipMemcpyDeviceToHost, c.stream));
+}
+
+// Start of a run of job j: shadow residual, rho, and the device run control.
+template <int DIM>
+void job_run_start(KJob* j, int cur, double resbest) {
+  using I = Impl<DIM, float>;
+  pff_solver* s = j->s;
+  const int g1 = red_blocks(s->M);
+  double* ks = s->scal + SC_KS;
+  k_bicg_shadow<float><<<g1, kBlock, 0, s->stream>>>(I::vec(s, I::R), I::vec(s, I::RHAT), ks, kShadowSeed, s->M,
+                                                    s->part0);
+  LAUNCH_CHECK();
+  I::reduce_ks(s, 1, 1);
+  k_ks_run_start<<<1, 64, 0, s->stream>>>(ks, double(j->total), double(cur), resbest, j->rtol, double(j->maxit));
+  LAUNCH_CHECK();
+}
+
+template <int DIM>
+void job_finish(KJob* j) {
+  using I = Impl<DIM, float>;
+  pff_solver* s = j->s;
+  k_copy<float><<<red_blocks(s->M), kBlock, 0, s->stream>>>(j->x, I::vec(s, I::X0 + j->best), s->M);
+  LAUNCH_CHECK();
+  HC(hipEventRecord(s->kb_done, s->stream));
+  s->kiters += j->total;
+  s->applies += j->applies;
+  s->stream = j->slot;
+}
+
+// Admission: x = 0, r = b, ||b||; returns false when the solve is finished.
+template <int DIM>
+bool job_admit(KClass& c, KJob* j) {
+  using I = Impl<DIM, float>;
+  pff_solver* s = j->s;
+  j->slot = s->stream;
+  s->stream = c.stream;
+  HC(hipStreamWaitEvent(c.stream, s->kb_ready, 0));
+  const int g1 = red_blocks(s->M);
+  k_bicg_init<float><<<g1, kBlock, 0, s->stream>>>(j->b, I::vec(s, I::X0), I::vec(s, I::R), I::vec(s, I::P),
+                                                  I::vec(s, I::V), s->M, s->part0);
+  LAUNCH_CHECK();
+  I::reduce_ks(s, 1, 0);
+  j->best = 0;
+  job_run_start<DIM>(j, 0, -1.0);     // ||b|| stays on the device until the run ends
+  return true;
+}
+
+// End of a run (the device stopped it): the true residual of the best
+// iterate decides between convergence, the end of the solve and a new run.
+template <int DIM>
+bool job_run_end(KJob* j, int total, int best) {
+  using I = Impl<DIM, float>;
+  pff_solver* s = j->s;
+  const int g1 = red_blocks(s->M);
+  j->applies += 2LL * (total - j->total);
+  j->total = total;
+  j->best = best;
+  I::apply(s, I::vec(s, I::X0 + best), I::vec(s, I::T));
+  s->applies--;                              // counted in j->applies
+  j->applies++;
+  k_true_resid<float><<<g1, kBlock, 0, s->stream>>>(I::vec(s, I::R), j->b, I::vec(s, I::T), I::vec(s, I::P),
+                                                   I::vec(s, I::V), s->M, s->part0);
+  LAUNCH_CHECK();
+  k_reduce<FinRestart><<<1, kBlock, 0, s->stream>>>(s->part0, g1, 1, FinRestart::Args{s->scal + SC_KS});
+  LAUNCH_CHECK();
+  sync_scal(s);
+  j->bnorm = s->hscal[SC_KS + KS_BNORM];
+  j->true_res = s->hscal[SC_KS + KS_TRUE];
+  if (j->true_res <= j->rtol * j->bnorm) j->conv = 1;
+  if (j->conv || j->total >= j->maxit || ++j->cycle >= kMaxCycles) {
+    job_finish<DIM>(j);
+    return false;
+  }
+  job_run_start<DIM>(j, best, j->true_res);
+  return true;
+}
+
+template <int DIM>
+void class_admit(KClass& c, std::vector<KJob*>& in, std::vector<KJob*>& done) {
+  for (KJob* j : in) {
+    if (job_admit<DIM>(c, j)) c.active.push_back(j);
+    else done.push_back(j);
+  }
+}
+
+template <int DIM>
+void class_collect(KClass& c, int B, std::vector<KJob*>& done) {
+  HC(hipStreamSynchronize(c.stream));
+  std::vector<KJob*> keep;
+  for (int b = 0; b < B; ++b) {
+    KJob* j = c.active[b];
+    const double* f = c.h_flags + 4 * b;
+    if (f[0] == 0.0) {
+      keep.push_back(j);
+      continue;
+    }
+    // the device stopped this run: the true residual of its best iterate
+    if (job_run_end<DIM>(j, int(f[2]), int(f[3]))) keep.push_back(j);
+    else done.push_back(j);
+  }
+  for (size_t b = B; b < c.active.size(); ++b) keep.push_back(c.active[b]);
+  c.active.swap(keep);
+}
+
+// Engine thread of one size class: admit the solves handed in, run a chunk
+// of batched iterations over (at most bmax of) the solves in flight, collect
+// the runs the device stopped, repeat.  Device errors end the solves in
+// flight with an error.
+void class_engine(KBatcher* kb, KClass* cp) {
+  KClass& c = *cp;
+  (void)hipSetDevice(kb->device);
+  std::unique_lock<std::mutex> lk(kb->m);
+  for (;;) {
+    c.cv.wait(lk, [&] { return kb->stop || !c.pending.empty() || !c.active.empty(); });
+    if (c.pending.empty() && c.active.empty()) break;   // stop with nothing in flight
+    std::vector<KJob*> in;
+    in.swap(c.pending);
+    lk.unlock();
+    std::vector<KJob*> done;
+    int B = 0;
+    try {
+      if (c.dim == 2) class_admit<2>(c, in, done);
+      else class_admit<3>(c, in, done);
+      B = (int)std::min<size_t>(c.active.size(), (size_t)kb->bmax);
+      if (B > 0) {
+        for (int b = 0; b < B; ++b) {
+          if (c.dim == 2) fill_entries<2>(c, b, c.active[b]);
+          else fill_entries<3>(c, b, c.active[b]);
+        }
+        if (c.dim == 2) launch_chunk<2>(kb, c, B);
+        else launch_chunk<3>(kb, c, B);
+        if (c.dim == 2) class_collect<2>(c, B, done);
+        else class_collect<3>(c, B, done);
+      }
+    } catch (const std::exception& e) {
+      lk.lock();
+      kb->err = e.what();
+      for (KJob* j : in) done.push_back(j);
+      for (KJob* j : c.active) done.push_back(j);
+      c.active.clear();
+      for (KJob* j : done) {
+        if (j->slot) j->s->stream = j->slot;
+        j->failed = true;
+        j->finished = true;
+      }
+      kb->cv_done.notify_all();
+      continue;
+    }
+    lk.lock();
+    if (B > 0) {
+      kb->st.chunks++;
+      kb->st.rve_chunks += B;
+      kb->st.max_batch = std::max(kb->st.max_batch, B);
+    }
+    for (KJob* j : done) {
+      j->finished = true;
+      kb->st.solves++;
+      kb->st.iterations += j->total;
+    }
+    if (!done.empty()) kb->cv_done.notify_all();
+  }
+}
+
+// Slot thread: hand the solve to the engine and wait for it.
+int kbatcher_solve(pff_solver* s, const float* b, float* x, double rtol, int maxit, int* iters, double* relres) {
+  KBatcher* kb = s->kb;
+  KJob j;
+  j.s = s;
+  j.b = b;
+  j.x = x;
+  j.rtol = rtol;
+  j.maxit = maxit;
+  HC(hipEventRecord(s->kb_ready, s->stream));
+  {
+    std::unique_lock<std::mutex> lk(kb->m);
+    if (kb->stop) throw Fail("request server is shutting down", PFF_ERR_STATE);
+    KClass* c = kclass_of(kb, s);
+    c->pending.push_back(&j);
+    c->cv.notify_one();
+    kb->cv_done.wait(lk, [&] { return j.finished; });
+    if (j.failed) throw Fail("batched Krylov engine: " + kb->err, PFF_ERR_DEVICE);
+  }
+  HC(hipStreamWaitEvent(s->stream, s->kb_done, 0));
+  if (iters) *iters = j.total;
+  if (relres) *relres = j.bnorm > 0.0 ? j.true_res / j.bnorm : 0.0;
+  return j.conv;
+}
+
+}  // namespace
+
+namespace pff {
+
+KBatcher* kbatcher_create(int device, int bmax, int chunk, int graph) {
+  auto* kb = new (std::nothrow) KBatcher();
+  if (!kb) return nullptr;
+  kb->device = device;
+  kb->bmax = std::max(1, std::min(bmax, 64));
+  kb->chunk = std::max(1, std::min(chunk, 64));
+  kb->graph = graph ? 1 : 0;
+  return kb;
+}
+
+void kbatcher_destroy(KBatcher* kb) {
+  if (!kb) return;
+  {
+    std::lock_guard<std::mutex> lk(kb->m);
+    kb->stop = true;
+    for (auto& c : kb->classes) c->cv.notify_all();
+  }
+  for (auto& c : kb->classes)
+    if (c->th.joinable()) c->th.join();
+  (void)hipSetDevice(kb->device);
+  for (auto& c : kb->classes) kclass_free(*c);
+  delete kb;
+}
+
+void kbatcher_stats(KBatcher* kb, KBatcherStats* out) {
+  std::lock_guard<std::mutex> lk(kb->m);
+  *out = kb->st;
+}
+
+void kbatcher_attach(pff_solver* s, KBatcher* kb) {
+  if (kb && (s->var_het || !s->mixed())) kb = nullptr;   // batched: FP32 inner solves, plain toughness term
+  if (kb && !s->kb_ready) {
+    HC(hipEventCreateWithFlags(&s->kb_ready, hipEventDisableTiming));
+    HC(hipEventCreateWithFlags(&s->kb_done, hipEventDisableTiming));
+  }
+  s->kb = kb;
+}
+
+}  // namespace pff
+
+namespace {
+
 // Newton linear solve J dq = -F into the FP64 vector SOL, to the FP64
 // relative residual rtol.  FP64 mode: one FP64 BiCGSTAB.  Mixed mode: FP64
 // iterative refinement around FP32 solves: BiCGSTAB on the FP32 tangent
@@ -1274,7 +1808,11 @@ void newton_linear_solve(pff_solver* s, int* kit, double* eta_out) {
   float* sol32 = I32::vec(s, I32::SOL);
   int k32 = 0, k64 = 0, kk = 0;
   double rr = 0.0, eta = 0.0, eta_prev = 1.0;
-  I32::bicgstab(s, rhs32, sol32, rtol_in, maxit32, &kk, &rr);
+  auto solve32 = [&]() {
+    if (s->kb) kbatcher_solve(s, rhs32, sol32, rtol_in, maxit32, &kk, &rr);
+    else I32::bicgstab(s, rhs32, sol32, rtol_in, maxit32, &kk, &rr);
+  };
+  solve32();
   k32 += kk;
   k_widen<<<nb, kBlock, 0, s->stream>>>(sol, sol32, M);
   LAUNCH_CHECK();
@@ -1306,7 +1844,7 @@ void newton_linear_solve(pff_solver* s, int* kit, double* eta_out) {
     const double rn = std::sqrt(rr2);
     k_narrow_scaled<<<nb, kBlock, 0, s->stream>>>(rhs32, defect, 1.0 / rn, M);
     LAUNCH_CHECK();
-    I32::bicgstab(s, rhs32, sol32, rtol_in, maxit32, &kk, &rr);
+    solve32();
     k32 += kk;
     k_axpy_widen<<<nb, kBlock, 0, s->stream>>>(sol, sol32, rn, M);
     LAUNCH_CHECK();
@@ -1480,6 +2018,9 @@ void destroy_buffers(pff_solver* s) {
   s->tim_group.clear();
   if (s->ev_scal) (void)hipEventDestroy(s->ev_scal);
   s->ev_scal = nullptr;
+  if (s->kb_ready) (void)hipEventDestroy(s->kb_ready);
+  if (s->kb_done) (void)hipEventDestroy(s->kb_done);
+  s->kb_ready = s->kb_done = nullptr;
   for (auto& pb : s->allocs) {
     if (s->allocator.alloc) s->allocator.free(pb.first, pb.second, s->allocator.ctx);
     else (void)hipFree(pb.first);
@@ -1507,6 +2048,7 @@ struct NoAllocCtx {
   hipStream_t stream = nullptr;
   // the launch configuration of a solver (pff_create's defaults)
   int x_rows = 64, spec_threads = 512, spec_tx = 8, axis_threads = 0, axis_tx = 16, xcd_remap = 1, zspec = 1;
+  GraphRec* rec = nullptr;             // launched directly
   size_t part_len = 0;                 // the projection has no reductions
   double* part0 = nullptr;
   double* part1 = nullptr;
@@ -1610,7 +2152,13 @@ extern "C" {
 
 int pff_abi_version(void) { return PFF_ABI_VERSION; }
 
-const char* pff_last_error(const pff_solver* s) { return s ? s->err.c_str() : "null handle"; }
+// text of the last failed pff_create on this thread (there is no handle then)
+thread_local std::string g_create_error;
+
+const char* pff_last_error(const pff_solver* s) {
+  if (s) return s->err.c_str();
+  return g_create_error.empty() ? "null handle" : g_create_error.c_str();
+}
 
 pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phases, const uint8_t* phase_id,
                       const uint8_t* crack_mask, const pff_params* params, const pff_allocator* allocator,
@@ -1794,10 +2342,12 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     return PFF_OK;
   });
   if (st != PFF_OK) {
+    g_create_error = "pff_create: " + s->err;
     destroy_buffers(s);
     delete s;
     return st;
   }
+  g_create_error.clear();
   *out = s;
   return PFF_OK;
 }

@@ -169,6 +169,9 @@ struct TangentPipe {
   }
 };
 
+// the FP32 tangent takes batched launches (the request server's inner solves)
+template <int DIM> struct Batchable<TangentPipe<float, DIM>> : std::true_type {};
+
 template <int DIM>
 struct ResidualPipe {
   using real = double;

@@ -11,14 +11,24 @@
 // first-fit over the queue in arrival order; a request that has been
 // overtaken kMaxSkips times blocks further overtaking until it fits.
 //
-// A solve depends only on its own inputs: all reductions are fixed-order and
-// every buffer is written before it is read, so a request gives the same
-// results alone and in a mix.
+// Batching: the FP32 Krylov solves of the mixed-precision requests (the bulk
+// of an increment) go to one engine thread (csrc/batch.hpp) that groups the
+// solves in flight by grid and advances each group by a fixed chunk of
+// BiCGSTAB iterations per launch sequence, replayed from a captured HIP
+// graph: every kernel of a chunk covers all solves of the group, and a solve
+// joins or leaves its group at chunk boundaries.  The rest of each
+// increment (residual, Newton update, FP64 refinement) runs on the slot's
+// stream.
+//
+// A solve depends only on its own inputs: all reductions are fixed-order per
+// RVE and every buffer is written before it is read, so a request gives the
+// same results alone and in a mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -28,6 +38,7 @@
 #include <thread>
 #include <vector>
 
+#include "batch.hpp"
 #include "pff.h"
 
 namespace {
@@ -62,6 +73,7 @@ struct Request {
 struct pff_server {
   int device = 0;
   pff_allocator allocator{nullptr, nullptr, nullptr};   // for every request's solver
+  pff::KBatcher* kb = nullptr;                           // batched FP32 inner solves (or null)
   size_t budget = 0;
   int nslots = 0;
   std::mutex m;
@@ -111,6 +123,15 @@ void run_request(pff_server* S, Request* r, hipStream_t st) {
     r->err = "pff_create failed";
     return;
   }
+  try {
+    pff::kbatcher_attach(s, S->kb);
+  } catch (const std::exception& e) {
+    pff_destroy(s);
+    std::lock_guard<std::mutex> lk(S->m);
+    r->status = PFF_ERR_DEVICE;
+    r->err = e.what();
+    return;
+  }
   double a0 = 0.0, E_s = 0.0;
   status = pff_bootstrap(s, &a0, &E_s);
   {
@@ -142,6 +163,8 @@ void run_request(pff_server* S, Request* r, hipStream_t st) {
   std::lock_guard<std::mutex> lk(S->m);
   r->err = err;
   r->status = status;
+  if (status != PFF_OK)
+    S->err = "request " + std::to_string(r->ticket) + " (status " + std::to_string(status) + "): " + err;
 }
 
 void worker(pff_server* S, int slot) {
@@ -207,6 +230,20 @@ pff_status pff_server_create(size_t hbm_budget_bytes, int max_slots, const pff_a
   S->budget = hbm_budget_bytes;
   S->nslots = max_slots;
   if (allocator && allocator->alloc) S->allocator = *allocator;
+  {
+    auto envi = [](const char* k, int d) {
+      const char* v = std::getenv(k);
+      return v ? std::atoi(v) : d;
+    };
+    if (envi("PFF_SERVER_BATCH", 1) != 0) {
+      S->kb = pff::kbatcher_create(S->device, envi("PFF_BATCH_MAX", 8), envi("PFF_BATCH_CHUNK", 4),
+                                   envi("PFF_BATCH_GRAPH", 1));
+      if (!S->kb) {
+        delete S;
+        return PFF_ERR_OOM;
+      }
+    }
+  }
   S->t0 = std::chrono::steady_clock::now();
   for (int k = 0; k < max_slots; ++k) S->workers.emplace_back(worker, S, k);
   *out = S;
@@ -328,6 +365,16 @@ pff_status pff_server_get_stats(pff_server* S, pff_server_stats* out) {
   out->bytes_in_use = S->in_use;
   out->peak_bytes = S->peak;
   out->clock = S->now();
+  if (S->kb) {
+    pff::KBatcherStats b;
+    pff::kbatcher_stats(S->kb, &b);
+    out->batch_chunks = b.chunks;
+    out->batch_solves = b.solves;
+    out->batch_iterations = b.iterations;
+    out->batch_graphs = b.graphs;
+    out->batch_max = b.max_batch;
+    out->batch_mean = b.chunks > 0 ? double(b.rve_chunks) / double(b.chunks) : 0.0;
+  }
   return PFF_OK;
 }
 
@@ -348,6 +395,7 @@ void pff_server_destroy(pff_server* S) {
   S->cv_work.notify_all();
   S->cv_done.notify_all();
   for (auto& t : S->workers) t.join();
+  pff::kbatcher_destroy(S->kb);
   delete S;
 }
 

@@ -176,7 +176,8 @@ class Solver:
                                  None if allocator is None else C.byref(allocator.struct),
                                  C.c_void_p(stream), C.byref(h))
         if st != L.PFF_OK:
-            raise PffError(st, "pff_create failed")
+            msg = self.lib.pff_last_error(None)
+            raise PffError(st, msg.decode() if msg else "pff_create failed")
         self.h = h
 
     @classmethod
@@ -425,6 +426,10 @@ class Server:
         if st != L.PFF_OK:
             raise PffError(st, "pff_server_results")
         return [_result_dict(arr[k]) for k in range(n.value)]
+
+    def last_error(self):
+        msg = self.lib.pff_server_last_error(self.h)
+        return msg.decode() if msg else ""
 
     def release(self, ticket):
         st = self.lib.pff_server_release(self.h, C.c_uint64(ticket))

@@ -150,5 +150,5 @@ def test_invalid_arguments_rejected_before_device_work():
     # null handle calls
     assert lib.pff_step(None, None) == L.PFF_ERR_ARG
     assert lib.pff_device_views(None, None, None, None) == L.PFF_ERR_ARG
-    assert lib.pff_last_error(None) == b"null handle"
+    assert lib.pff_last_error(None).startswith(b"pff_create")   # the last failed create on this thread
     lib.pff_destroy(None)

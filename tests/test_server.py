@@ -107,7 +107,7 @@ def test_request_gives_the_same_results_alone_and_in_a_mix():
     tickets += [mix.submit(n, **_kw(p, prec)) for p, prec, n in others[2:]]
     for tk in tickets + [tt]:
         assert mix.wait(tk, 300.0)
-        assert mix.info(tk)["status"] == L.PFF_OK, mix.info(tk)
+        assert mix.info(tk)["status"] == L.PFF_OK, (mix.info(tk), mix.last_error())
     _same(mix.results(tt), ref)
     st = mix.stats()
     assert st["completed"] == 5 and st["max_running"] >= 2 and st["bytes_in_use"] == 0
@@ -134,3 +134,38 @@ def test_admission_respects_the_memory_budget():
     with pytest.raises(PffError):
         srv.submit(1, **_kw(big, "mixed"))     # footprint above the whole budget
     srv.close()
+
+
+@pytest.mark.gpu
+def test_batched_inner_solves_equal_the_solver_alone():
+    """The server batches the FP32 inner solves of requests on the same grid
+    (one launch sequence per chunk of BiCGSTAB iterations for the whole
+    group, replayed from a captured graph).  Each request's increments are
+    the same bits as the same problem stepped alone by a solver outside the
+    server (host-driven BiCGSTAB on its own stream): the batched kernels do
+    each RVE's arithmetic in the same order, and the run control on the
+    device takes the host loop's decisions."""
+    from paper_2412_17445_amd import Server, Solver
+    reqs = [(_problem("gc16"), 3), (_problem("tiny16"), 3), (_problem("gc16_iso"), 2),
+            (_problem("pore24"), 2), (_problem("part24"), 1)]
+    srv = Server(64 << 30, len(reqs))
+    tickets = [srv.submit(n, **_kw(p, "mixed")) for p, n in reqs]
+    for tk in tickets:
+        assert srv.wait(tk, 300.0)
+        assert srv.info(tk)["status"] == L.PFF_OK, (srv.info(tk), srv.last_error())
+    st = srv.stats()
+    assert st["batch_solves"] > 0 and st["batch_graphs"] >= 1, st
+    assert st["batch_max"] >= 2, st                # solves of one grid shared chunks
+    served = [srv.results(tk) for tk in tickets]
+    srv.close()
+    for (p, n), res in zip(reqs, served):
+        s = Solver.from_problem(p, precision="mixed")
+        s.bootstrap()
+        ref = [s.step() for _ in range(n)]
+        s.close()
+        assert len(res) == n
+        for x, y in zip(res, ref):
+            assert x["converged"] and y["converged"]
+            assert (x["newton_iters"], x["krylov_iters"]) == (y["newton_iters"], y["krylov_iters"]), (p.name, x, y)
+            assert x["E"] == y["E"] and x["Gamma"] == y["Gamma"], (p.name, x["E"], y["E"])
+            assert x["sigma_M"] == y["sigma_M"]
