@@ -54,7 +54,7 @@ KRYLOV_RTOL = {"fibres2d_256": 1e-4, "pores3d_64": 1e-2, "particles3d_128": 1e-2
 
 # committed states stored for re-seeded parity: increments after which the
 # state is written (0 = none)
-STATES = {"crack2d_64": list(range(1, 30)), "part24_m": [1, 2], "part12_m": [1, 2]}
+STATES = {"part24_m": [1, 2], "part12_m": [1, 2]}
 
 
 def sample_index(prob):

@@ -18,13 +18,15 @@ on the residual, so a relaxed Newton (alpha = 0.9, linear convergence) no
 longer leaves either side a tolerance away from the root.
 
 Re-seeded parity: for the cases whose golden stores the oracle's committed
-states (the 30-increment path of the centred crack, whose mirror-symmetric
-root sits next to a nearly neutral "which tip grows" direction, and the 3D
-cells under mixed macroscopic conditions), the GPU also starts each
-increment from the oracle's committed state (pff_set_state) and is compared
-with the oracle's next increment, including the whole damage field.  Both
-sides then take the same increment from the same state, so drift along a
-nearly neutral direction cannot accumulate between them.
+states (the 3D cells under mixed macroscopic conditions, whose bordered
+system has a nearly neutral direction), the GPU also starts each increment
+from the oracle's committed state (pff_set_state) and is compared with the
+oracle's next increment, including the whole damage field.  Both sides then
+take the same increment from the same state, so drift along a nearly
+neutral direction cannot accumulate between them.  The 30-increment path of
+the centred crack (crack2d_64) is compared free-running: with the residual
+stop both sides stay on its mirror-symmetric root and agree to ~1e-14 over
+all 30 increments.
 
 The roots are compared as points of the physical solution set: the strain
 fluctuation is compatible (G eps~ = eps~); the last test checks
@@ -138,7 +140,7 @@ def test_mixed_increments_match_fp64_oracle(case, rtol):
     s.close()
 
 
-RESEEDED = ["crack2d_64", "part12_m", "part24_m"]
+RESEEDED = ["part12_m", "part24_m"]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
