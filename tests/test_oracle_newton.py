@@ -83,3 +83,25 @@ def test_path_invariants():
         assert np.abs(comp - s.eps_t).max() <= 1e-9 * np.abs(s.eps_t).max()
         assert s.phi.min() > -1e-3 and s.phi.max() <= 1.0 + 1e-12
         a_prev, H_prev = s.a, s.Hn.copy()
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.9])
+def test_residual_stop_pins_the_root_whatever_the_krylov_tolerance(alpha):
+    """With the parity-mode residual stop the increment is the root of the
+    discrete system to the residual tolerance: an inexact Newton (Krylov
+    tolerance 1e-3) lands on the same increments as the exact one (1e-10),
+    with the linear convergence of a relaxed Newton (alpha = 0.9) too.  The
+    full-size oracle runs use such inexact steps."""
+    prob = tiny(n=16, crack=(6, 10))
+    prob.alpha = alpha
+    ex = Solver(prob, rtol=1e-10, resid_tol=1e-11)
+    inx = Solver(prob, rtol=1e-3, resid_tol=1e-11)
+    ex.bootstrap()
+    inx.bootstrap()
+    for _ in range(2):
+        a, b = ex.step(), inx.step()
+        assert a["converged"] and b["converged"]
+        assert max(b["resid"]) <= 1e-11
+        assert abs(a["E"] - b["E"]) <= 1e-10 * abs(a["E"])
+        assert np.abs(ex.phi - inx.phi).max() <= 1e-10
+        assert np.abs(ex.eps_t - inx.eps_t).max() <= 1e-10 * np.abs(ex.eps_t).max()
