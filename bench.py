@@ -408,8 +408,14 @@ def serve_stream(args):
             "throughput_mvoxel_applies_per_s": round(applies_vox / makespan / 1e6, 1),
             "slots": args.serve_slots, "max_running": st["max_running"],
             "peak_bytes": st["peak_bytes"], "budget_bytes": st["budget"],
+            "batched_inner_solves": {"chunks": st["batch_chunks"], "solves": st["batch_solves"],
+                                     "iterations": st["batch_iterations"], "graphs": st["batch_graphs"],
+                                     "max_batch": st["batch_max"], "mean_batch": round(st["batch_mean"], 3),
+                                     "enabled": os.environ.get("PFF_SERVER_BATCH", "1") != "0"},
             "stream": f"synth.stream seeds 0..{len(reqs) - 1}, Poisson {args.serve_rate}/s, "
-                      f"increments scaled by {args.serve_inc_scale}"}
+                      f"increments scaled by {args.serve_inc_scale}",
+            "kind": ("the full 256-request served stream" if len(reqs) >= 256
+                     else "a reduced served stream (smoke run of the serving path)")}
 
 
 def apply_mode(prob, args):

@@ -10,7 +10,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpff.so")
+# the in-tree build; PFF_LIB_PATH points at another build of the same ABI
+# (side-by-side timing of two builds)
+LIB_PATH = os.environ.get("PFF_LIB_PATH") or os.path.join(HERE, "libpff.so")
 
 PFF_OK, PFF_NOT_CONVERGED, PFF_QUEUED = 0, 1, 2
 PFF_ERR_ARG, PFF_ERR_OOM, PFF_ERR_DEVICE, PFF_ERR_STATE = -1, -2, -3, -4

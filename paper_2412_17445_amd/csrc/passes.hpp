@@ -52,12 +52,24 @@ template <class P> struct BatchEntry {
   const double* stop;
 };
 
-template <class P, bool ANY>
-__device__ __forceinline__ void xfwd_body(const typename P::Args& A, const AxisPlan& pl,
-                                          const cpx<typename P::real>* __restrict__ tw_g,
-                                          cpx<typename P::real>* __restrict__ spec, int rows_per_block,
-                                          double* __restrict__ partials) {
+// rows_per_block rows of x per block (blockIdx.x).  BATCHED: one RVE of the
+// batch per blockIdx.y, its arguments, spectra and partials from its entry
+// (a separate instantiation: the unbatched kernel is the plain code).
+template <class P, bool ANY, bool BATCHED = false>
+__global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xfwd(const typename P::Args A_in, const AxisPlan pl,
+                                                 const cpx<typename P::real>* __restrict__ tw_g,
+                                                 cpx<typename P::real>* __restrict__ spec_in,
+                                                 int rows_per_block, double* __restrict__ partials_in,
+                                                 const BatchEntry<P>* __restrict__ batch) {
   using T = typename P::real;
+  const BatchEntry<P>* e = nullptr;
+  if constexpr (BATCHED) {
+    e = &batch[blockIdx.y];
+    if (e->stop && *e->stop != 0.0) return;
+  }
+  const typename P::Args& A = BATCHED ? e->A : A_in;
+  cpx<T>* __restrict__ spec = BATCHED ? e->spec : spec_in;
+  double* __restrict__ partials = BATCHED ? e->part0 : partials_in;
   constexpr int NF = P::NF;
   constexpr int NP = (NF + 1) / 2;
   constexpr int NR = P::NRED_PRO;
@@ -122,24 +134,6 @@ __device__ __forceinline__ void xfwd_body(const typename P::Args& A, const AxisP
   }
 }
 
-// rows_per_block rows of x per block (blockIdx.x); batched: RVE blockIdx.y
-template <class P, bool ANY>
-__global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xfwd(const typename P::Args A, const AxisPlan pl,
-                                                 const cpx<typename P::real>* __restrict__ tw_g,
-                                                 cpx<typename P::real>* __restrict__ spec,
-                                                 int rows_per_block, double* __restrict__ partials,
-                                                 const BatchEntry<P>* __restrict__ batch) {
-  if constexpr (Batchable<P>::value) {
-    if (batch) {
-      const BatchEntry<P>& e = batch[blockIdx.y];
-      if (e.stop && *e.stop != 0.0) return;
-      xfwd_body<P, ANY>(e.A, pl, tw_g, e.spec, rows_per_block, e.part0);
-      return;
-    }
-  }
-  xfwd_body<P, ANY>(A, pl, tw_g, spec, rows_per_block, partials);
-}
-
 constexpr int kXcds = 8;   // MI355X: workgroups are dispatched round-robin over 8 XCDs
 
 // Complex FFT along y (axis 1) or z (axis 2) for one tile and a group of NFB
@@ -155,7 +149,7 @@ constexpr int kXcds = 8;   // MI355X: workgroups are dispatched round-robin over
 // given to workgroups on the same XCD, so that two tiles sharing 128-byte
 // lines meet in that XCD's L2.
 template <class P, int S, bool SPECTRAL, bool ANY>
-__device__ __forceinline__ void axis_body(const typename P::Args& A, const AxisPlan& pl,
+__device__ __forceinline__ void axis_body(const typename P::Args A, const AxisPlan pl,
                                           const cpx<typename P::real>* __restrict__ tw_g,
                                           cpx<typename P::real>* __restrict__ spec, int axis, int ltx, int NFB,
                                           int remap, int fg) {
@@ -270,29 +264,37 @@ __device__ __forceinline__ void axis_body(const typename P::Args& A, const AxisP
 // Each element crosses the LDS twice per direction instead of once per
 // radix stage plus the staging copies.  Tiles as in k_axis (axis 2): TX
 // consecutive kx columns of the main block at one y, or TX consecutive y of
-// the Nyquist plane; RA * TX threads.
-// field groups of NFB fields on blockIdx.z; batched: blockIdx.z = RVE * NG +
-// group, NG = ceil(NF / NFB)
+// the Nyquist plane; RA * TX threads.  The tile is padded by one element
+// every 32.  (A second padding for the inverse exchange, eight every 32,
+// removes the 4-way bank conflicts of the stage-B' writes at N = 128, but
+// the larger tile made the pass slower, 39.7 against 38.7 us.)
+template <class P, int N, int TX> struct ZspecLds {
+  static constexpr long long E = (long long)P::NF * N * TX;
+  static constexpr long long ELEMS = E + (E >> 5) + 1;   // the padded tile (lds_padded), then N twiddles
+};
+// field groups of NFB fields on blockIdx.z
 template <class P, int S, bool SPECTRAL, bool ANY>
 __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_axis(const typename P::Args A, const AxisPlan pl,
                                                  const cpx<typename P::real>* __restrict__ tw_g,
                                                  cpx<typename P::real>* __restrict__ spec, int axis,
-                                                 int ltx, int NFB, int remap,
-                                                 const BatchEntry<P>* __restrict__ batch) {
-  if constexpr (Batchable<P>::value) {
-    if (batch) {
-      const int ng = (P::NF + NFB - 1) / NFB;
-      const BatchEntry<P>& e = batch[blockIdx.z / ng];
-      if (e.stop && *e.stop != 0.0) return;
-      axis_body<P, S, SPECTRAL, ANY>(e.A, pl, tw_g, e.spec, axis, ltx, NFB, remap, blockIdx.z % ng);
-      return;
-    }
-  }
+                                                 int ltx, int NFB, int remap) {
   axis_body<P, S, SPECTRAL, ANY>(A, pl, tw_g, spec, axis, ltx, NFB, remap, blockIdx.z);
 }
 
+// batched launch: blockIdx.z = RVE * NG + group, NG = ceil(NF / NFB)
+template <class P, int S, bool SPECTRAL, bool ANY>
+__global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_axis_b(const BatchEntry<P>* __restrict__ batch,
+                                                   const AxisPlan pl,
+                                                   const cpx<typename P::real>* __restrict__ tw_g, int axis,
+                                                   int ltx, int NFB, int remap) {
+  const int ng = (P::NF + NFB - 1) / NFB;
+  const BatchEntry<P>& e = batch[blockIdx.z / ng];
+  if (e.stop && *e.stop != 0.0) return;
+  axis_body<P, S, SPECTRAL, ANY>(e.A, pl, tw_g, e.spec, axis, ltx, NFB, remap, blockIdx.z % ng);
+}
+
 template <class P, int N, int TX>
-__device__ __forceinline__ void zspec_body(const typename P::Args& A, const cpx<typename P::real>* __restrict__ tw_g,
+__device__ __forceinline__ void zspec_body(const typename P::Args A, const cpx<typename P::real>* __restrict__ tw_g,
                                            cpx<typename P::real>* __restrict__ spec, int remap) {
   using T = typename P::real;
   constexpr int NF = P::NF;
@@ -335,7 +337,7 @@ __device__ __forceinline__ void zspec_body(const typename P::Args& A, const cpx<
     ts = 1;
   }
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* tw = buf + lds_padded((long long)NF * N * TX);
+  cpx<T>* tw = buf + ZspecLds<P, N, TX>::ELEMS;
   for (int t = threadIdx.x; t < N; t += NT) tw[t] = tw_g[t];
   auto L = [](int f, int pos, int t) { return lpad((f * N + pos) * TX + t); };
   // forward stage A
@@ -403,29 +405,38 @@ __device__ __forceinline__ void zspec_body(const typename P::Args& A, const cpx<
   }
 }
 
-// batched: RVE blockIdx.z
 template <class P, int N, int TX>
 __global__ void __launch_bounds__(N / 4 * TX) k_zspec(const typename P::Args A,
                                                      const cpx<typename P::real>* __restrict__ tw_g,
-                                                     cpx<typename P::real>* __restrict__ spec, int remap,
-                                                     const BatchEntry<P>* __restrict__ batch) {
-  if constexpr (Batchable<P>::value) {
-    if (batch) {
-      const BatchEntry<P>& e = batch[blockIdx.z];
-      if (e.stop && *e.stop != 0.0) return;
-      zspec_body<P, N, TX>(e.A, tw_g, e.spec, remap);
-      return;
-    }
-  }
+                                                     cpx<typename P::real>* __restrict__ spec, int remap) {
   zspec_body<P, N, TX>(A, tw_g, spec, remap);
 }
 
-template <class P, bool ANY>
-__device__ __forceinline__ void xinv_body(const typename P::Args& A, const AxisPlan& pl,
-                                          const cpx<typename P::real>* __restrict__ tw_g,
-                                          const cpx<typename P::real>* __restrict__ spec, int rows_per_block,
-                                          double* __restrict__ partials) {
+// batched launch: RVE blockIdx.z
+template <class P, int N, int TX>
+__global__ void __launch_bounds__(N / 4 * TX) k_zspec_b(const BatchEntry<P>* __restrict__ batch,
+                                                       const cpx<typename P::real>* __restrict__ tw_g, int remap) {
+  const BatchEntry<P>& e = batch[blockIdx.z];
+  if (e.stop && *e.stop != 0.0) return;
+  zspec_body<P, N, TX>(e.A, tw_g, e.spec, remap);
+}
+
+// BATCHED: one RVE of the batch per blockIdx.y (as k_xfwd)
+template <class P, bool ANY, bool BATCHED = false>
+__global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xinv(const typename P::Args A_in, const AxisPlan pl,
+                                                 const cpx<typename P::real>* __restrict__ tw_g,
+                                                 const cpx<typename P::real>* __restrict__ spec_in,
+                                                 int rows_per_block, double* __restrict__ partials_in,
+                                                 const BatchEntry<P>* __restrict__ batch) {
   using T = typename P::real;
+  const BatchEntry<P>* e = nullptr;
+  if constexpr (BATCHED) {
+    e = &batch[blockIdx.y];
+    if (e->stop && *e->stop != 0.0) return;
+  }
+  const typename P::Args& A = BATCHED ? e->A : A_in;
+  const cpx<T>* __restrict__ spec = BATCHED ? e->spec : spec_in;
+  double* __restrict__ partials = BATCHED ? e->part1 : partials_in;
   constexpr int NF = P::NF;
   constexpr int NP = (NF + 1) / 2;
   constexpr int NR = P::NRED_EPI;
@@ -497,24 +508,6 @@ __device__ __forceinline__ void xinv_body(const typename P::Args& A, const AxisP
     if (threadIdx.x == 0)
       for (int q = 0; q < NR; ++q) partials[(long long)q * gridDim.x + blockIdx.x] = red[q];
   }
-}
-
-// batched: RVE blockIdx.y
-template <class P, bool ANY>
-__global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xinv(const typename P::Args A, const AxisPlan pl,
-                                                 const cpx<typename P::real>* __restrict__ tw_g,
-                                                 const cpx<typename P::real>* __restrict__ spec,
-                                                 int rows_per_block, double* __restrict__ partials,
-                                                 const BatchEntry<P>* __restrict__ batch) {
-  if constexpr (Batchable<P>::value) {
-    if (batch) {
-      const BatchEntry<P>& e = batch[blockIdx.y];
-      if (e.stop && *e.stop != 0.0) return;
-      xinv_body<P, ANY>(e.A, pl, tw_g, e.spec, rows_per_block, e.part1);
-      return;
-    }
-  }
-  xinv_body<P, ANY>(A, pl, tw_g, spec, rows_per_block, partials);
 }
 
 // ---- spectral stage shared by the pipes -------------------------------------

@@ -343,6 +343,15 @@ void launch_k(GraphRec* rec, void (*kern)(KArgs...), dim3 grid, dim3 block, size
   rec->last = node;
 }
 
+// The batched strided-axis kernel of pipe P, or null where P takes no
+// batched launches (it is then never instantiated).
+template <class P, int S, bool SPECTRAL, bool ANY>
+auto k_axis_b_of() {
+  using Fn = void (*)(const BatchEntry<P>*, AxisPlan, const cpx<typename P::real>*, int, int, int, int);
+  if constexpr (Batchable<P>::value) return static_cast<Fn>(k_axis_b<P, S, SPECTRAL, ANY>);
+  else return static_cast<Fn>(nullptr);
+}
+
 // Pipes of plane-strain problems never take the 3D z pass.
 template <class P> struct Only2D : std::false_type {};
 template <typename T> struct Only2D<TangentPipe<T, 2>> : std::true_type {};
@@ -353,15 +362,35 @@ template <typename T> struct Only2D<ProjectPipe<T, 2>> : std::true_type {};
 // The z pass with register-resident first and last radix stages (k_zspec),
 // for z lengths 32, 64 and 128; returns false where it does not apply.
 // FP32 tiles run 256 threads, FP64 tiles 128 (the same LDS bytes).
+// LDS bytes one workgroup may allocate on the current device (queried once).
+size_t lds_per_block_limit() {
+  static const size_t lim = [] {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+      return size_t(64) << 10;
+    return size_t(v);
+  }();
+  return lim;
+}
+
 template <class P, int N, class S>
-void launch_zspec_n(S* s, const typename P::Args& A, const cpx<typename P::real>* tw, cpx<typename P::real>* spec,
+bool launch_zspec_n(S* s, const typename P::Args& A, const cpx<typename P::real>* tw, cpx<typename P::real>* spec,
                     const BatchEntry<P>* batch, int B) {
   using T = typename P::real;
   constexpr int TX = (sizeof(T) == 4 ? 256 : 128) / (N / 4);
-  const size_t lds = (size_t(lds_padded((long long)P::NF * N * TX)) + N) * sizeof(cpx<T>);
+  const size_t lds = (size_t(ZspecLds<P, N, TX>::ELEMS) + N) * sizeof(cpx<T>);
+  if (lds > lds_per_block_limit()) return false;
   const int nkt = (s->g.nxm + TX - 1) / TX;
   const dim3 gs(nkt + s->g.nyq, s->ny, B);
-  launch_k(s->rec, k_zspec<P, N, TX>, gs, dim3(N / 4 * TX), lds, s->stream, A, tw, spec, s->xcd_remap, batch);
+  if constexpr (Batchable<P>::value) {
+    if (batch) {
+      launch_k(s->rec, k_zspec_b<P, N, TX>, gs, dim3(N / 4 * TX), lds, s->stream, batch, tw, s->xcd_remap);
+      return true;
+    }
+  }
+  launch_k(s->rec, k_zspec<P, N, TX>, gs, dim3(N / 4 * TX), lds, s->stream, A, tw, spec, s->xcd_remap);
+  return true;
 }
 
 template <class P, class S>
@@ -372,9 +401,9 @@ bool launch_zspec(S* s, const typename P::Args& A, const cpx<typename P::real>* 
   } else {
     if (!s->zspec) return false;
     switch (s->nz) {
-      case 32: launch_zspec_n<P, 32>(s, A, tw, spec, batch, B); return true;
-      case 64: launch_zspec_n<P, 64>(s, A, tw, spec, batch, B); return true;
-      case 128: launch_zspec_n<P, 128>(s, A, tw, spec, batch, B); return true;
+      case 32: return launch_zspec_n<P, 32>(s, A, tw, spec, batch, B);
+      case 64: return launch_zspec_n<P, 64>(s, A, tw, spec, batch, B);
+      case 128: return launch_zspec_n<P, 128>(s, A, tw, spec, batch, B);
       default: return false;
     }
   }
@@ -402,8 +431,28 @@ void run_passes(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev, co
   nblk_x = (int)((nrows + rb - 1) / rb);
   if ((size_t)nblk_x > s->part_len) throw Fail("partial buffer too small", PFF_ERR_STATE);
   if (ev) HC(hipEventRecord(ev[0], s->stream));
-  launch_k(s->rec, k_xfwd<P, ANY>, dim3(nblk_x, B), dim3(nthr), ldsx, s->stream, A, s->plan[0], tb.tw[0], spec, rb,
-           s->part0, batch);
+  // batched launches (the request server's FP32 tangent) take the *_b kernels
+  constexpr bool BAT = Batchable<P>::value;
+  auto axis_launch = [&](auto kern_u, auto kern_b, dim3 grid, int thr, size_t lds, int axis, int ltx, int nfb,
+                         int remap) {
+    if constexpr (BAT) {
+      if (batch) {
+        launch_k(s->rec, kern_b, grid, dim3(thr), lds, s->stream, batch, s->plan[axis], tb.tw[axis], axis, ltx,
+                 nfb, remap);
+        return;
+      }
+    }
+    launch_k(s->rec, kern_u, grid, dim3(thr), lds, s->stream, A, s->plan[axis], tb.tw[axis], spec, axis, ltx, nfb,
+             remap);
+  };
+  if constexpr (BAT) {
+    if (batch)
+      launch_k(s->rec, k_xfwd<P, ANY, true>, dim3(nblk_x, B), dim3(nthr), ldsx, s->stream, A, s->plan[0], tb.tw[0],
+               spec, rb, s->part0, batch);
+  }
+  if (!BAT || !batch)
+    launch_k(s->rec, k_xfwd<P, ANY, false>, dim3(nblk_x), dim3(nthr), ldsx, s->stream, A, s->plan[0], tb.tw[0], spec,
+             rb, s->part0, static_cast<const BatchEntry<P>*>(nullptr));
   if (ev) HC(hipEventRecord(ev[1], s->stream));
   // the spectral pass holds all NF fields of a tile
   const int last = s->dim == 2 ? 1 : 2;
@@ -415,8 +464,7 @@ void run_passes(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev, co
     throw Fail("axis too long for the LDS budget", PFF_ERR_ARG);
   const dim3 gs((s->g.nxm + txs - 1) / txs + s->g.nyq, last == 1 ? s->nz : s->ny, B);
   if (s->dim == 2) {
-    launch_k(s->rec, k_axis<P, -1, true, ANY>, gs, dim3(sthr), ldss, s->stream, A, s->plan[1], tb.tw[1], spec, 1,
-             log2i(txs), NF, 0, batch);
+    axis_launch(k_axis<P, -1, true, ANY>, k_axis_b_of<P, -1, true, ANY>(), gs, sthr, ldss, 1, log2i(txs), NF, 0);
     if (ev) {
       HC(hipEventRecord(ev[2], s->stream));
       HC(hipEventRecord(ev[3], s->stream));
@@ -429,20 +477,24 @@ void run_passes(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev, co
     const int txy = choose_tx(s->ny, 1, csz, s->g.nxm, athr, s->axis_tx);
     const size_t ldsy = lds_axis(s->ny, 1, txy, csz);
     const dim3 gy((s->g.nxm + txy - 1) / txy + s->g.nyq, s->nz, NF * B);
-    launch_k(s->rec, k_axis<P, -1, false, ANY>, gy, dim3(athr), ldsy, s->stream, A, s->plan[1], tb.tw[1], spec, 1,
-             log2i(txy), 1, 0, batch);
+    axis_launch(k_axis<P, -1, false, ANY>, k_axis_b_of<P, -1, false, ANY>(), gy, athr, ldsy, 1, log2i(txy), 1, 0);
     if (ev) HC(hipEventRecord(ev[2], s->stream));
     if (!launch_zspec<P>(s, A, tb.tw[2], spec, batch, B)) {
-      launch_k(s->rec, k_axis<P, -1, true, ANY>, gs, dim3(sthr), ldss, s->stream, A, s->plan[2], tb.tw[2], spec, 2,
-               log2i(txs), NF, s->xcd_remap, batch);
+      axis_launch(k_axis<P, -1, true, ANY>, k_axis_b_of<P, -1, true, ANY>(), gs, sthr, ldss, 2, log2i(txs), NF,
+                  s->xcd_remap);
     }
     if (ev) HC(hipEventRecord(ev[3], s->stream));
-    launch_k(s->rec, k_axis<P, 1, false, ANY>, gy, dim3(athr), ldsy, s->stream, A, s->plan[1], tb.tw[1], spec, 1,
-             log2i(txy), 1, 0, batch);
+    axis_launch(k_axis<P, 1, false, ANY>, k_axis_b_of<P, 1, false, ANY>(), gy, athr, ldsy, 1, log2i(txy), 1, 0);
     if (ev) HC(hipEventRecord(ev[4], s->stream));
   }
-  launch_k(s->rec, k_xinv<P, ANY>, dim3(nblk_x, B), dim3(nthr), ldsx, s->stream, A, s->plan[0], tb.tw[0], spec, rb,
-           s->part1, batch);
+  if constexpr (BAT) {
+    if (batch)
+      launch_k(s->rec, k_xinv<P, ANY, true>, dim3(nblk_x, B), dim3(nthr), ldsx, s->stream, A, s->plan[0], tb.tw[0],
+               spec, rb, s->part1, batch);
+  }
+  if (!BAT || !batch)
+    launch_k(s->rec, k_xinv<P, ANY, false>, dim3(nblk_x), dim3(nthr), ldsx, s->stream, A, s->plan[0], tb.tw[0], spec,
+             rb, s->part1, static_cast<const BatchEntry<P>*>(nullptr));
   if (ev) HC(hipEventRecord(ev[5], s->stream));
 }
 
