@@ -381,14 +381,20 @@ def serve_stream(args):
         if dt > 0:
             time.sleep(dt)
         tickets.append(srv.submit(n, **problem_kwargs(prob)))
-    infos, applies_vox, incs, failed = [], 0, 0, 0
+    infos, applies_vox, incs, failed, alg_bytes = [], 0, 0, 0, 0
     for k, tk in enumerate(tickets):
         srv.wait(tk)
         info = srv.info(tk)
         res = srv.results(tk)
         infos.append(info)
         prob = reqs[k][0]
-        applies_vox += sum(r["applies"] for r in res) * prob.nvox
+        n_all = sum(r["applies"] for r in res)
+        n64 = sum(r["applies_fp64"] for r in res)
+        applies_vox += n_all * prob.nvox
+        # algorithmic bytes of every apply: the working-precision applies at
+        # their width, the FP64 ones (refinement defects, fallbacks) at 8 bytes
+        alg_bytes += ((n_all - n64) * alg_bytes_per_voxel(prob, prob.precision)
+                      + n64 * alg_bytes_per_voxel(prob, "fp64")) * prob.nvox
         incs += len(res)
         failed += info["status"] != 0
         log(f"request {k}: {prob.notes}, {len(res)} increments, status {info['status']}, "
@@ -406,6 +412,11 @@ def serve_stream(args):
             "makespan_s": round(makespan, 3),
             "throughput_requests_per_s": round(len(reqs) / makespan, 3),
             "throughput_mvoxel_applies_per_s": round(applies_vox / makespan / 1e6, 1),
+            "roofline": {"bound": "hbm", "achieved": round(alg_bytes / makespan / 1e9, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(alg_bytes / makespan / 1e9 / HBM_PEAK_GBS, 4),
+                         "what": "algorithmic bytes of every tangent apply of the stream (22 words "
+                                 "per voxel-apply in 2D, 37 in 3D, plus the phase byte) over the makespan"},
             "slots": args.serve_slots, "max_running": st["max_running"],
             "peak_bytes": st["peak_bytes"], "budget_bytes": st["budget"],
             "batched_inner_solves": {"chunks": st["batch_chunks"], "solves": st["batch_solves"],

@@ -421,6 +421,99 @@ __global__ void __launch_bounds__(N / 4 * TX) k_zspec_b(const BatchEntry<P>* __r
   zspec_body<P, N, TX>(e.A, tw_g, e.spec, remap);
 }
 
+// The y passes of a 3D round trip for lengths N = 32, 64, 128 with the first
+// and the last radix stage in registers, N = RA * 4 (decimation in time):
+//   stage A (radix RA over the rows j + 4 r, j < 4): loaded straight from the
+//           spectra, written to LDS as Y_j[m];
+//   stage B (radix 4 over j, twiddles w^(j m)): read from LDS and stored
+//           straight to the spectra at rows m + RA q (natural order).
+// Each element crosses the LDS once instead of once per radix stage plus the
+// staging copies.  S = -1 forward, +1 inverse (conjugate twiddles, no
+// scaling: the x-inverse pass scales).  Tiles as in k_axis (axis 1): TX
+// consecutive kx columns of the main block at one z, or TX consecutive z of
+// the Nyquist plane; one field per block (blockIdx.z); 4 * TX threads, each
+// holding one radix-RA transform in stage A.
+template <class T, int N, int TX> struct YregLds {
+  static constexpr int E = N * TX;
+  static constexpr int ELEMS = E + (E >> 5) + 1;   // the padded tile, then N twiddles
+};
+
+template <class T, int N, int TX, int S>
+__device__ __forceinline__ void yreg_body(const GridDesc& g, const cpx<T>* __restrict__ tw_g,
+                                          cpx<T>* __restrict__ spec, int field, int bx, int by) {
+  constexpr int RA = N / 4;
+  constexpr int NT = 4 * TX;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nkt = (g.nxm + TX - 1) / TX;
+  long long off0;
+  int js, ts, tc;
+  if (bx < nkt) {
+    const int kx0 = bx * TX;
+    tc = min(TX, g.nxm - kx0);
+    off0 = (long long)by * g.ny * g.nxm + kx0;
+    js = g.nxm;
+    ts = 1;
+  } else {
+    const int q0 = by * TX;
+    if (q0 >= g.nz) return;
+    tc = min(TX, g.nz - q0);
+    off0 = g.Nm + (long long)q0 * g.ny;
+    js = 1;
+    ts = g.ny;
+  }
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw = buf + YregLds<T, N, TX>::ELEMS;
+  for (int t = threadIdx.x; t < N; t += NT) tw[t] = tw_g[t];
+  cpx<T>* base = spec + (long long)field * g.Nh + off0;
+  {
+    const int t = threadIdx.x % TX, j = threadIdx.x / TX;
+    const cpx<T>* src = base + (long long)t * ts;
+    cpx<T> v[RA];
+#pragma unroll
+    for (int r = 0; r < RA; ++r) v[r] = t < tc ? src[(long long)(j + 4 * r) * js] : cpx<T>{T(0), T(0)};
+    dft_pow2<T, S, RA>(v);
+#pragma unroll
+    for (int m = 0; m < RA; ++m) buf[lpad((j * RA + m) * TX + t)] = v[m];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < RA / 4; ++it) {
+    const int item = it * NT + threadIdx.x;
+    const int t = item % TX, m = item / TX;
+    cpx<T> v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = buf[lpad((j * RA + m) * TX + t)];
+#pragma unroll
+    for (int j = 1; j < 4; ++j) {
+      cpx<T> w = tw[j * m];
+      if constexpr (S > 0) w.y = -w.y;
+      v[j] = cmul(v[j], w);
+    }
+    dft4<T, S>(v);
+    if (t < tc) {
+      cpx<T>* dst = base + (long long)t * ts;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dst[(long long)(m + RA * q) * js] = v[q];
+    }
+  }
+}
+
+template <class P, int N, int TX, int S>
+__global__ void __launch_bounds__(4 * TX) k_yreg(const typename P::Args A,
+                                                 const cpx<typename P::real>* __restrict__ tw_g,
+                                                 cpx<typename P::real>* __restrict__ spec) {
+  yreg_body<typename P::real, N, TX, S>(A.g, tw_g, spec, blockIdx.z, blockIdx.x, blockIdx.y);
+}
+
+// batched launch: blockIdx.z = RVE * NF + field
+template <class P, int N, int TX, int S>
+__global__ void __launch_bounds__(4 * TX) k_yreg_b(const BatchEntry<P>* __restrict__ batch,
+                                                   const cpx<typename P::real>* __restrict__ tw_g) {
+  const BatchEntry<P>& e = batch[blockIdx.z / P::NF];
+  if (e.stop && *e.stop != 0.0) return;
+  yreg_body<typename P::real, N, TX, S>(e.A.g, tw_g, e.spec, blockIdx.z % P::NF, blockIdx.x, blockIdx.y);
+}
+
 // BATCHED: one RVE of the batch per blockIdx.y (as k_xfwd)
 template <class P, bool ANY, bool BATCHED = false>
 __global__ void __launch_bounds__(FftThreads<typename P::real>::value) k_xinv(const typename P::Args A_in, const AxisPlan pl,

@@ -179,6 +179,8 @@ struct pff_solver {
   double inner32 = 0.0;     // mixed: FP32 inner-solve tolerance (env PFF_INNER32)
   int xcd_remap = 1;        // z pass: consecutive tiles on one XCD (env PFF_XCD_REMAP)
   int zspec = 1;            // z pass with register-resident end stages for nz = 32, 64, 128 (env PFF_ZSPEC)
+  int yreg = 1;             // FP32 y passes with register-resident end stages (env PFF_YREG: 0 off,
+                            // 1 / 2 / 3 tiles of 16 / 32 / 64 columns)
   int fused = 1;            // BiCGSTAB steps fused into the applies (env PFF_FUSED): 0 none,
                             // 1 inner products in the epilogues, 2 also the p / s updates in the prologues
   hipEvent_t ev_scal = nullptr;   // marks the scalar copy of a BiCGSTAB iteration
@@ -374,11 +376,10 @@ size_t lds_per_block_limit() {
   return lim;
 }
 
-template <class P, int N, class S>
-bool launch_zspec_n(S* s, const typename P::Args& A, const cpx<typename P::real>* tw, cpx<typename P::real>* spec,
-                    const BatchEntry<P>* batch, int B) {
+template <class P, int N, int TX, class S>
+bool launch_zspec_tx(S* s, const typename P::Args& A, const cpx<typename P::real>* tw, cpx<typename P::real>* spec,
+                     const BatchEntry<P>* batch, int B) {
   using T = typename P::real;
-  constexpr int TX = (sizeof(T) == 4 ? 256 : 128) / (N / 4);
   const size_t lds = (size_t(ZspecLds<P, N, TX>::ELEMS) + N) * sizeof(cpx<T>);
   if (lds > lds_per_block_limit()) return false;
   const int nkt = (s->g.nxm + TX - 1) / TX;
@@ -393,6 +394,17 @@ bool launch_zspec_n(S* s, const typename P::Args& A, const cpx<typename P::real>
   return true;
 }
 
+// Tile width: TX columns of N / 4 threads each, 256 threads per FP32 tile and
+// 128 per FP64 tile.  (At 128^3 FP32, half-width tiles gave the same apply
+// time, 177.8 against 178.0 us, and double-width tiles 182.0 us.)
+template <class P, int N, class S>
+bool launch_zspec_n(S* s, const typename P::Args& A, const cpx<typename P::real>* tw, cpx<typename P::real>* spec,
+                    const BatchEntry<P>* batch, int B) {
+  using T = typename P::real;
+  constexpr int TX = (sizeof(T) == 4 ? 256 : 128) / (N / 4);
+  return launch_zspec_tx<P, N, TX>(s, A, tw, spec, batch, B);
+}
+
 template <class P, class S>
 bool launch_zspec(S* s, const typename P::Args& A, const cpx<typename P::real>* tw, cpx<typename P::real>* spec,
                   const BatchEntry<P>* batch, int B) {
@@ -404,6 +416,51 @@ bool launch_zspec(S* s, const typename P::Args& A, const cpx<typename P::real>* 
       case 32: return launch_zspec_n<P, 32>(s, A, tw, spec, batch, B);
       case 64: return launch_zspec_n<P, 64>(s, A, tw, spec, batch, B);
       case 128: return launch_zspec_n<P, 128>(s, A, tw, spec, batch, B);
+      default: return false;
+    }
+  }
+}
+
+// The y passes of a 3D FP32 tangent apply with register-resident end stages
+// (k_yreg) for y lengths 32, 64, 128: tile width 16, 32 or 64 columns
+// (context member yreg = 1, 2, 3; 0 keeps k_axis).  Returns false where it
+// does not apply.  At 128^3 the FP32 apply takes 171.6 us with 16-column
+// tiles, 174.8 with 32, 187.4 with 64, and 177.2 with k_axis.
+template <class P, int N, int TX, int SG, class C>
+bool launch_yreg_tx(C* s, const typename P::Args& A, const cpx<typename P::real>* tw, cpx<typename P::real>* spec,
+                    const BatchEntry<P>* batch, int B) {
+  using T = typename P::real;
+  const size_t lds = (size_t(YregLds<T, N, TX>::ELEMS) + N) * sizeof(cpx<T>);
+  if (lds > lds_per_block_limit()) return false;
+  const int nkt = (s->g.nxm + TX - 1) / TX;
+  const dim3 gy(nkt + s->g.nyq, s->nz, P::NF * B);
+  if (batch) launch_k(s->rec, k_yreg_b<P, N, TX, SG>, gy, dim3(4 * TX), lds, s->stream, batch, tw);
+  else launch_k(s->rec, k_yreg<P, N, TX, SG>, gy, dim3(4 * TX), lds, s->stream, A, tw, spec);
+  return true;
+}
+
+template <class P, int N, int SG, class C>
+bool launch_yreg_n(C* s, const typename P::Args& A, const cpx<typename P::real>* tw, cpx<typename P::real>* spec,
+                   const BatchEntry<P>* batch, int B) {
+  switch (s->yreg) {
+    case 1: return launch_yreg_tx<P, N, 16, SG>(s, A, tw, spec, batch, B);
+    case 2: return launch_yreg_tx<P, N, 32, SG>(s, A, tw, spec, batch, B);
+    case 3: return launch_yreg_tx<P, N, 64, SG>(s, A, tw, spec, batch, B);
+    default: return false;
+  }
+}
+
+template <class P, int SG, class C>
+bool launch_yreg(C* s, const typename P::Args& A, const cpx<typename P::real>* tw, cpx<typename P::real>* spec,
+                 const BatchEntry<P>* batch, int B) {
+  if constexpr (!Batchable<P>::value || P::NF != 7) {
+    return false;
+  } else {
+    if (s->dim != 3 || !s->yreg) return false;
+    switch (s->ny) {
+      case 32: return launch_yreg_n<P, 32, SG>(s, A, tw, spec, batch, B);
+      case 64: return launch_yreg_n<P, 64, SG>(s, A, tw, spec, batch, B);
+      case 128: return launch_yreg_n<P, 128, SG>(s, A, tw, spec, batch, B);
       default: return false;
     }
   }
@@ -477,14 +534,16 @@ void run_passes(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev, co
     const int txy = choose_tx(s->ny, 1, csz, s->g.nxm, athr, s->axis_tx);
     const size_t ldsy = lds_axis(s->ny, 1, txy, csz);
     const dim3 gy((s->g.nxm + txy - 1) / txy + s->g.nyq, s->nz, NF * B);
-    axis_launch(k_axis<P, -1, false, ANY>, k_axis_b_of<P, -1, false, ANY>(), gy, athr, ldsy, 1, log2i(txy), 1, 0);
+    if (!launch_yreg<P, -1>(s, A, tb.tw[1], spec, batch, B))
+      axis_launch(k_axis<P, -1, false, ANY>, k_axis_b_of<P, -1, false, ANY>(), gy, athr, ldsy, 1, log2i(txy), 1, 0);
     if (ev) HC(hipEventRecord(ev[2], s->stream));
     if (!launch_zspec<P>(s, A, tb.tw[2], spec, batch, B)) {
       axis_launch(k_axis<P, -1, true, ANY>, k_axis_b_of<P, -1, true, ANY>(), gs, sthr, ldss, 2, log2i(txs), NF,
                   s->xcd_remap);
     }
     if (ev) HC(hipEventRecord(ev[3], s->stream));
-    axis_launch(k_axis<P, 1, false, ANY>, k_axis_b_of<P, 1, false, ANY>(), gy, athr, ldsy, 1, log2i(txy), 1, 0);
+    if (!launch_yreg<P, 1>(s, A, tb.tw[1], spec, batch, B))
+      axis_launch(k_axis<P, 1, false, ANY>, k_axis_b_of<P, 1, false, ANY>(), gy, athr, ldsy, 1, log2i(txy), 1, 0);
     if (ev) HC(hipEventRecord(ev[4], s->stream));
   }
   if constexpr (BAT) {
@@ -1374,7 +1433,7 @@ struct KClass {
   AxisPlan plan[3]{};
   bool plan_any = false;
   hipStream_t stream = nullptr;
-  int x_rows = 64, spec_threads = 512, spec_tx = 8, axis_threads = 0, axis_tx = 16, xcd_remap = 1, zspec = 1;
+  int x_rows = 64, spec_threads = 512, spec_tx = 8, axis_threads = 0, axis_tx = 16, xcd_remap = 1, zspec = 1, yreg = 0;
   GraphRec* rec = nullptr;     // set while a chunk graph is being built
   size_t part_len = 0;
   double* part0 = nullptr;
@@ -1450,6 +1509,7 @@ KClass* kclass_of(KBatcher* kb, pff_solver* s) {
   c->axis_tx = s->axis_tx;
   c->xcd_remap = s->xcd_remap;
   c->zspec = s->zspec;
+  c->yreg = s->yreg;
   c->part_len = s->part_len;
   c->N = s->N;
   c->M = s->M;
@@ -2099,7 +2159,7 @@ struct NoAllocCtx {
   bool plan_any = false;
   hipStream_t stream = nullptr;
   // the launch configuration of a solver (pff_create's defaults)
-  int x_rows = 64, spec_threads = 512, spec_tx = 8, axis_threads = 0, axis_tx = 16, xcd_remap = 1, zspec = 1;
+  int x_rows = 64, spec_threads = 512, spec_tx = 8, axis_threads = 0, axis_tx = 16, xcd_remap = 1, zspec = 1, yreg = 0;
   GraphRec* rec = nullptr;             // launched directly
   size_t part_len = 0;                 // the projection has no reductions
   double* part0 = nullptr;
@@ -2334,6 +2394,7 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     s->x_rows = envi("PFF_X_ROWS", 64);
     s->xcd_remap = envi("PFF_XCD_REMAP", 1) != 0 ? 1 : 0;
     s->zspec = envi("PFF_ZSPEC", 1) != 0 ? 1 : 0;
+    s->yreg = std::min(3, std::max(0, envi("PFF_YREG", 1)));
     s->fused = std::min(2, std::max(0, envi("PFF_FUSED", 1)));
     if (s->var_het) s->fused = std::min(s->fused, 1);   // the variational term needs the input before the pass
     {

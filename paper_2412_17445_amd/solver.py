@@ -127,7 +127,10 @@ class TorchAllocator:
 
         def _free(ptr, nbytes, ctx):
             self.live.pop(ptr, None)
-            self._torch.cuda.caching_allocator_delete(ptr)
+            cuda = getattr(self._torch, "cuda", None)
+            if cuda is None:                    # interpreter shutdown: the process returns the memory
+                return
+            cuda.caching_allocator_delete(ptr)
 
         self._alloc = L.ALLOC_FN(_alloc)
         self._free = L.FREE_FN(_free)

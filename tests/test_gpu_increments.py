@@ -140,6 +140,24 @@ def test_mixed_increments_match_fp64_oracle(case, rtol):
     s.close()
 
 
+@pytest.mark.parametrize("case,precision", [("part24_iso", "fp64"), ("gc16", "fp64"), ("part24", "mixed")])
+def test_fused_vector_updates_match_oracle(case, precision, monkeypatch):
+    """PFF_FUSED=2 forms the BiCGSTAB p and s updates inside the apply
+    prologues.  It applies to the FP32 solves only: an FP64 solve keeps the
+    separate p update and its projection onto compatible strains (without
+    which the 24^3 isotropic case's FP64 solve picks up a near-null
+    direction), so every case still matches the oracle."""
+    monkeypatch.setenv("PFF_FUSED", "2")
+    g = golden(case)
+    prob = problem_config(case)
+    s = gpu(prob, g, precision=precision, krylov_rtol=1e-10 if precision == "fp64" else 1e-5)
+    s.bootstrap()
+    for ref in g["increments"]:
+        out = s.step()
+        check(case, s, out, ref, TOL_FP64 if precision == "fp64" else TOL_MIXED, precision + " fused=2")
+    s.close()
+
+
 RESEEDED = ["part12_m", "part24_m"]
 
 
