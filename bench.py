@@ -298,7 +298,8 @@ def odd_grid_leg(args):
     s.bootstrap()
     w = s.step()
     log(f"{args.odd_workload} warm-up increment: converged={w['converged']} {w['seconds']:.2f}s")
-    s.timing(args.timing_every)
+    tim_warm = s.timing_read()
+    s.timing(-args.timing_every)
     a0, _ = s.counters()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -524,6 +525,9 @@ def main():
     s = Solver.from_problem(prob)
     s.bootstrap()
     log("bootstrap done")
+    # per-pass events on the warm-up applies (the pass breakdown); the timed
+    # region samples the whole apply only (two events, less perturbation)
+    s.timing(args.timing_every)
     warm = []
     for i in range(args.warmup):
         out = s.step()
@@ -532,7 +536,8 @@ def main():
             f"newton={out['newton_iters']} krylov={out['krylov_iters']} {out['seconds']:.2f}s")
         if not out["converged"]:
             raise RuntimeError(f"warm-up increment did not converge: {out}")
-    s.timing(args.timing_every)
+    tim_warm = s.timing_read()
+    s.timing(-args.timing_every)
     a0, _ = s.counters()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -552,23 +557,27 @@ def main():
     applies = a1 - a0
     value = applies * N / elapsed / 1e6
 
-    tim = s.timing_read()
+    tim_all = s.timing_read()
+    # the timed region's whole-apply samples
+    tim = {k: (n - tim_warm.get(k, (0, 0.0))[0], ms - tim_warm.get(k, (0, 0.0))[1])
+           for k, (n, ms) in tim_all.items()}
     prec_main = "mixed" if prob.precision == "mixed" else "fp64"
     main_groups = range(5, 10) if prec_main == "mixed" else range(0, 5)
     # whole apply (its five pass kernels and the finisher) over the sampled
     # applies of the working precision, every fused variant
-    whole = [tim[6 * gp + 5] for gp in main_groups if 6 * gp + 5 in tim]
+    whole = [tim[6 * gp + 5] for gp in main_groups if tim.get(6 * gp + 5, (0, 0))[0] > 0]
     apply_n, apply_ms = sum(v[0] for v in whole), sum(v[1] for v in whole)
     apply_s = apply_ms * 1e-3 / apply_n
     bvox = alg_bytes_per_voxel(prob, prob.precision)
     achieved = bvox * N / apply_s / 1e9
-    # per pass kernel: its own algorithmic bytes and time (secondary figures)
+    # per pass kernel: its own algorithmic bytes and time (secondary figures,
+    # from the per-pass events of the warm-up increments)
     passes = {}
     for gp in main_groups:
         for k in range(5):
-            if 6 * gp + k not in tim:
+            if 6 * gp + k not in tim_warm:
                 continue
-            n, ms = tim[6 * gp + k]
+            n, ms = tim_warm[6 * gp + k]
             b = kernel_bytes(prob.shape, prec_main, gp % 5)[k]
             if b <= 0:
                 continue
@@ -586,9 +595,13 @@ def main():
                           + ("FP32" if prec_main == "mixed" else "FP64"),
                 "alg_bytes_per_voxel_apply": bvox, "voxels_per_launch": N,
                 "alg_bytes_per_launch": bvox * N, "avg_launch_us": round(apply_s * 1e6, 2),
-                "timed_launches": apply_n, "passes": pass_out}
+                "timed_launches": apply_n,
+                "timing": "HIP events around every sampled apply (two per apply) on the solver stream over "
+                          "the timed region; passes: per-pass events over the warm-up increments",
+                "traffic_over_alg": None if traffic is None else round(traffic / (bvox * N), 3),
+                "passes": pass_out}
     by_mode = {"fp32": [0] * 5, "fp64": [0] * 5}
-    for sl, (n, _) in tim.items():
+    for sl, (n, _) in tim_warm.items():
         if sl % 6 == 5:
             by_mode["fp32" if sl // 6 >= 5 else "fp64"][(sl // 6) % 5] += n
     line = {

@@ -334,7 +334,9 @@ pff_status pff_krylov_solve(pff_solver* s, const void* b_dev, void* x_dev, doubl
 
 /* Kernel timing (measurement support).  With every > 0, each every-th
  * tangent apply brackets its FFT pass kernels with HIP events on the solver
- * stream; every = 0 disables.  pff_timing_read(slot) returns the number of
+ * stream; with every < 0, each |every|-th apply carries only the two events
+ * around the whole apply (slot k = 5; the per-pass slots do not advance), which
+ * perturbs the timed apply less; every = 0 disables.  pff_timing_read(slot) returns the number of
  * timed launches and their summed duration in milliseconds for
  * slot = 6 * (5 * prec + variant) + k, with prec 1 for FP32 applies and 0
  * for FP64 ones; variant 0 a plain apply, 1 (3) the apply whose epilogue

@@ -174,6 +174,7 @@ struct pff_solver {
   bool trace = false;       // PFF_TRACE=1: per-Newton-iteration log on stderr
   bool ktrace = false;      // PFF_TRACE=2: the first BiCGSTAB scalars of every solve
   int tim_every = 0;        // sampled kernel timing of the tangent apply
+  bool tim_whole = false;   // sampled applies carry the whole-apply events only
   // launch tuning (env PFF_AXIS_THREADS, PFF_SPEC_THREADS, PFF_AXIS_TX, PFF_SPEC_TX, PFF_X_ROWS)
   int axis_threads = 0, spec_threads = 0, axis_tx = 64, spec_tx = 64, x_rows = 64;
   double inner32 = 0.0;     // mixed: FP32 inner-solve tolerance (env PFF_INNER32)
@@ -487,7 +488,7 @@ void run_passes(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev, co
   const long long nrows = (long long)s->ny * s->nz;
   nblk_x = (int)((nrows + rb - 1) / rb);
   if ((size_t)nblk_x > s->part_len) throw Fail("partial buffer too small", PFF_ERR_STATE);
-  if (ev) HC(hipEventRecord(ev[0], s->stream));
+  if (ev && ev[0]) HC(hipEventRecord(ev[0], s->stream));
   // batched launches (the request server's FP32 tangent) take the *_b kernels
   constexpr bool BAT = Batchable<P>::value;
   auto axis_launch = [&](auto kern_u, auto kern_b, dim3 grid, int thr, size_t lds, int axis, int ltx, int nfb,
@@ -510,7 +511,7 @@ void run_passes(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev, co
   if (!BAT || !batch)
     launch_k(s->rec, k_xfwd<P, ANY, false>, dim3(nblk_x), dim3(nthr), ldsx, s->stream, A, s->plan[0], tb.tw[0], spec,
              rb, s->part0, static_cast<const BatchEntry<P>*>(nullptr));
-  if (ev) HC(hipEventRecord(ev[1], s->stream));
+  if (ev && ev[1]) HC(hipEventRecord(ev[1], s->stream));
   // the spectral pass holds all NF fields of a tile
   const int last = s->dim == 2 ? 1 : 2;
   const int nl = s->dim == 2 ? s->ny : s->nz;
@@ -523,9 +524,8 @@ void run_passes(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev, co
   if (s->dim == 2) {
     axis_launch(k_axis<P, -1, true, ANY>, k_axis_b_of<P, -1, true, ANY>(), gs, sthr, ldss, 1, log2i(txs), NF, 0);
     if (ev) {
-      HC(hipEventRecord(ev[2], s->stream));
-      HC(hipEventRecord(ev[3], s->stream));
-      HC(hipEventRecord(ev[4], s->stream));
+      for (int k = 2; k <= 4; ++k)
+        if (ev[k]) HC(hipEventRecord(ev[k], s->stream));
     }
   } else {
     // forward / inverse y passes: one field per block, wide tiles
@@ -536,15 +536,15 @@ void run_passes(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev, co
     const dim3 gy((s->g.nxm + txy - 1) / txy + s->g.nyq, s->nz, NF * B);
     if (!launch_yreg<P, -1>(s, A, tb.tw[1], spec, batch, B))
       axis_launch(k_axis<P, -1, false, ANY>, k_axis_b_of<P, -1, false, ANY>(), gy, athr, ldsy, 1, log2i(txy), 1, 0);
-    if (ev) HC(hipEventRecord(ev[2], s->stream));
+    if (ev && ev[2]) HC(hipEventRecord(ev[2], s->stream));
     if (!launch_zspec<P>(s, A, tb.tw[2], spec, batch, B)) {
       axis_launch(k_axis<P, -1, true, ANY>, k_axis_b_of<P, -1, true, ANY>(), gs, sthr, ldss, 2, log2i(txs), NF,
                   s->xcd_remap);
     }
-    if (ev) HC(hipEventRecord(ev[3], s->stream));
+    if (ev && ev[3]) HC(hipEventRecord(ev[3], s->stream));
     if (!launch_yreg<P, 1>(s, A, tb.tw[1], spec, batch, B))
       axis_launch(k_axis<P, 1, false, ANY>, k_axis_b_of<P, 1, false, ANY>(), gy, athr, ldsy, 1, log2i(txy), 1, 0);
-    if (ev) HC(hipEventRecord(ev[4], s->stream));
+    if (ev && ev[4]) HC(hipEventRecord(ev[4], s->stream));
   }
   if constexpr (BAT) {
     if (batch)
@@ -554,7 +554,7 @@ void run_passes(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev, co
   if (!BAT || !batch)
     launch_k(s->rec, k_xinv<P, ANY, false>, dim3(nblk_x), dim3(nthr), ldsx, s->stream, A, s->plan[0], tb.tw[0], spec,
              rb, s->part1, static_cast<const BatchEntry<P>*>(nullptr));
-  if (ev) HC(hipEventRecord(ev[5], s->stream));
+  if (ev && ev[5]) HC(hipEventRecord(ev[5], s->stream));
 }
 
 // The kernels with the generic-radix FFT stage run only where a grid length
@@ -2086,12 +2086,20 @@ void upload_tables(pff_solver* s, DevTables<T>& t) {
 
 hipEvent_t* timing_acquire(pff_solver* s, int group) {
   if (s->tim_pending.size() >= 512) timing_harvest(s);
-  std::array<hipEvent_t, 6> ev;
+  std::array<hipEvent_t, 6> ev{};
   if (!s->tim_free.empty()) {
     ev = s->tim_free.back();
     s->tim_free.pop_back();
-  } else {
-    for (auto& e : ev) HC(hipEventCreate(&e));
+  }
+  // whole-apply sampling: only the events before the first and after the
+  // last pass (slots 0 and 5); per-pass sampling: all six
+  for (int k = 0; k < 6; ++k) {
+    const bool want = !s->tim_whole || k == 0 || k == 5;
+    if (want && !ev[k]) HC(hipEventCreate(&ev[k]));
+    if (!want && ev[k]) {
+      (void)hipEventDestroy(ev[k]);
+      ev[k] = nullptr;
+    }
   }
   s->tim_group.push_back(group);
   s->tim_pending.push_back(ev);
@@ -2104,14 +2112,16 @@ void timing_harvest(pff_solver* s) {
   for (size_t e = 0; e < s->tim_pending.size(); ++e) {
     auto& ev = s->tim_pending[e];
     const int base = 6 * s->tim_group[e];
-    float ms[5];
-    for (int k = 0; k < 5; ++k) HC(hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]));
+    if (ev[1]) {
+      float ms[5];
+      for (int k = 0; k < 5; ++k) HC(hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]));
+      for (int k = 0; k < 5; ++k) {
+        s->tim_ms[base + k] += ms[k];
+        s->tim_n[base + k] += 1;
+      }
+    }
     float all = 0.f;
     HC(hipEventElapsedTime(&all, ev[0], ev[5]));
-    for (int k = 0; k < 5; ++k) {
-      s->tim_ms[base + k] += ms[k];
-      s->tim_n[base + k] += 1;
-    }
     s->tim_ms[base + 5] += all;
     s->tim_n[base + 5] += 1;
     s->tim_free.push_back(ev);
@@ -2122,9 +2132,11 @@ void timing_harvest(pff_solver* s) {
 
 void destroy_buffers(pff_solver* s) {
   for (auto& ev : s->tim_pending)
-    for (auto e : ev) (void)hipEventDestroy(e);
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
   for (auto& ev : s->tim_free)
-    for (auto e : ev) (void)hipEventDestroy(e);
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
   s->tim_pending.clear();
   s->tim_free.clear();
   s->tim_group.clear();
@@ -2937,10 +2949,10 @@ pff_status pff_krylov_solve(pff_solver* s, const void* b_dev, void* x_dev, doubl
 
 pff_status pff_timing(pff_solver* s, int every) {
   return guarded(s, [&]() -> pff_status {
-    if (every < 0) throw Fail("pff_timing: every must be >= 0", PFF_ERR_ARG);
     HC(hipStreamSynchronize(s->stream));
     timing_harvest(s);
-    s->tim_every = every;
+    s->tim_every = every < 0 ? -every : every;
+    s->tim_whole = every < 0;
     return PFF_OK;
   });
 }

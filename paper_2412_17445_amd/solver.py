@@ -317,7 +317,8 @@ class Solver:
         return x, it.value, rr.value, st == L.PFF_OK
 
     def timing(self, every):
-        """Sample every `every`-th tangent apply's pass kernels with HIP events."""
+        """Sample every `every`-th tangent apply's pass kernels with HIP events
+        (every < 0: every |every|-th apply, the whole apply only)."""
         self._check(self.lib.pff_timing(self.h, int(every)), "pff_timing")
 
     def timing_read(self):
