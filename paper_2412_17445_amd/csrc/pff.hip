@@ -397,7 +397,11 @@ bool launch_zspec_tx(S* s, const typename P::Args& A, const cpx<typename P::real
 
 // Tile width: TX columns of N / 4 threads each, 256 threads per FP32 tile and
 // 128 per FP64 tile.  (At 128^3 FP32, half-width tiles gave the same apply
-// time, 177.8 against 178.0 us, and double-width tiles 182.0 us.)
+// time, 177.8 against 178.0 us, and double-width tiles 182.0 us.  The 16
+// Nyquist tiles of that grid make the 1025th..1040th tile, a tail after two
+// full rounds of two blocks per CU worth about 8 us of the apply; folding the
+// Nyquist pencils into the main tiles as a ninth column cost more, +3.5 us,
+// and as an extra half-wavefront +13 us, its two code paths taking 249 VGPRs.)
 template <class P, int N, class S>
 bool launch_zspec_n(S* s, const typename P::Args& A, const cpx<typename P::real>* tw, cpx<typename P::real>* spec,
                     const BatchEntry<P>* batch, int B) {
