@@ -383,23 +383,32 @@ def serve_stream(args):
             time.sleep(dt)
         tickets.append(srv.submit(n, **problem_kwargs(prob)))
     infos, applies_vox, incs, failed, alg_bytes = [], 0, 0, 0, 0
-    for k, tk in enumerate(tickets):
-        srv.wait(tk)
-        info = srv.info(tk)
-        res = srv.results(tk)
-        infos.append(info)
-        prob = reqs[k][0]
-        n_all = sum(r["applies"] for r in res)
-        n64 = sum(r["applies_fp64"] for r in res)
-        applies_vox += n_all * prob.nvox
-        # algorithmic bytes of every apply: the working-precision applies at
-        # their width, the FP64 ones (refinement defects, fallbacks) at 8 bytes
-        alg_bytes += ((n_all - n64) * alg_bytes_per_voxel(prob, prob.precision)
-                      + n64 * alg_bytes_per_voxel(prob, "fp64")) * prob.nvox
-        incs += len(res)
-        failed += info["status"] != 0
-        log(f"request {k}: {prob.notes}, {len(res)} increments, status {info['status']}, "
-            f"latency {info['t_done'] - info['t_submit']:.2f}s")
+    # requests are collected in the order they finish, each logged as it completes
+    pending = list(range(len(tickets)))
+    while pending:
+        finished = [k for k in pending if srv.wait(tickets[k], 0.0)]
+        if not finished:
+            srv.wait(tickets[pending[0]], 0.2)
+            continue
+        for k in finished:
+            tk = tickets[k]
+            info = srv.info(tk)
+            res = srv.results(tk)
+            infos.append(info)
+            prob = reqs[k][0]
+            n_all = sum(r["applies"] for r in res)
+            n64 = sum(r["applies_fp64"] for r in res)
+            applies_vox += n_all * prob.nvox
+            # algorithmic bytes of every apply: the working-precision applies at
+            # their width, the FP64 ones (refinement defects, fallbacks) at 8 bytes
+            alg_bytes += ((n_all - n64) * alg_bytes_per_voxel(prob, prob.precision)
+                          + n64 * alg_bytes_per_voxel(prob, "fp64")) * prob.nvox
+            incs += len(res)
+            failed += info["status"] != 0
+            log(f"request {k}: {prob.notes}, {len(res)} increments, status {info['status']}, "
+                f"latency {info['t_done'] - info['t_submit']:.2f}s")
+        done = set(finished)
+        pending = [k for k in pending if k not in done]
     makespan = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
