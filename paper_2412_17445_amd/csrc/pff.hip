@@ -180,6 +180,7 @@ struct pff_solver {
   double inner32 = 0.0;     // mixed: FP32 inner-solve tolerance (env PFF_INNER32)
   int xcd_remap = 1;        // z pass: consecutive tiles on one XCD (env PFF_XCD_REMAP)
   int zspec = 1;            // z pass with register-resident end stages for nz = 32, 64, 128 (env PFF_ZSPEC)
+  int fit_shapes = 1;       // launch shapes sized to the grid's block count (env PFF_FIT_SHAPES)
   int yreg = 1;             // FP32 y passes with register-resident end stages (env PFF_YREG: 0 off,
                             // 1 / 2 / 3 tiles of 16 / 32 / 64 columns)
   int fused = 1;            // BiCGSTAB steps fused into the applies (env PFF_FUSED): 0 none,
@@ -489,7 +490,8 @@ void run_passes(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev, co
   // 512 blocks where the grid has the rows (small grids are latency-bound:
   // 256^2 FP64 apply 35.8 -> 31.1 us, 64^2 28.2 -> 23.2 us with one row per block)
   const int rb = choose_rb(s->nx, NP, csz,
-                           std::min(s->x_rows, std::max(1, (int)(((long long)s->ny * s->nz) / 512))));
+                           s->fit_shapes ? std::min(s->x_rows, std::max(1, (int)(((long long)s->ny * s->nz) / 512)))
+                                         : s->x_rows);
   const size_t ldsx = lds_x(rb, NP, s->nx, csz, nred);
   if (ldsx > kLdsBudget || size_t(rb) * NP * s->nx > size_t(maxe_of(csz)) * fft_threads(csz))
     throw Fail("grid too large for the LDS budget of the x pass", PFF_ERR_ARG);
@@ -527,7 +529,8 @@ void run_passes(S* s, const typename P::Args& A, int& nblk_x, hipEvent_t* ev, co
   // 2D: one column per spectral tile where fewer than 256 tiles would remain
   // (the whole pass is a few dozen blocks otherwise)
   const int txs = choose_tx(nl, NF, csz, s->g.nxm, sthr,
-                            s->dim == 2 ? std::min(s->spec_tx, std::max(1, s->g.nxm / 256)) : s->spec_tx);
+                            s->dim == 2 && s->fit_shapes ? std::min(s->spec_tx, std::max(1, s->g.nxm / 256))
+                                                         : s->spec_tx);
   const size_t ldss = lds_axis(nl, NF, txs, csz);
   if (ldss > kLdsBudget || size_t(NF) * nl * txs > size_t(maxe_of(csz)) * sthr)
     throw Fail("axis too long for the LDS budget", PFF_ERR_ARG);
@@ -1444,7 +1447,7 @@ struct KClass {
   AxisPlan plan[3]{};
   bool plan_any = false;
   hipStream_t stream = nullptr;
-  int x_rows = 64, spec_threads = 512, spec_tx = 8, axis_threads = 0, axis_tx = 16, xcd_remap = 1, zspec = 1, yreg = 0;
+  int x_rows = 64, spec_threads = 512, spec_tx = 8, axis_threads = 0, axis_tx = 16, xcd_remap = 1, zspec = 1, yreg = 0, fit_shapes = 1;
   GraphRec* rec = nullptr;     // set while a chunk graph is being built
   size_t part_len = 0;
   double* part0 = nullptr;
@@ -1520,6 +1523,7 @@ KClass* kclass_of(KBatcher* kb, pff_solver* s) {
   c->axis_tx = s->axis_tx;
   c->xcd_remap = s->xcd_remap;
   c->zspec = s->zspec;
+  c->fit_shapes = s->fit_shapes;
   c->yreg = s->yreg;
   c->part_len = s->part_len;
   c->N = s->N;
@@ -1889,6 +1893,8 @@ void kbatcher_stats(KBatcher* kb, KBatcherStats* out) {
   *out = kb->st;
 }
 
+void serving_shapes(pff_solver* s) { s->fit_shapes = 0; }
+
 void kbatcher_attach(pff_solver* s, KBatcher* kb) {
   if (kb && (s->var_het || !s->mixed())) kb = nullptr;   // batched: FP32 inner solves, plain toughness term
   if (kb && !s->kb_ready) {
@@ -2182,7 +2188,7 @@ struct NoAllocCtx {
   bool plan_any = false;
   hipStream_t stream = nullptr;
   // the launch configuration of a solver (pff_create's defaults)
-  int x_rows = 64, spec_threads = 512, spec_tx = 8, axis_threads = 0, axis_tx = 16, xcd_remap = 1, zspec = 1, yreg = 0;
+  int x_rows = 64, spec_threads = 512, spec_tx = 8, axis_threads = 0, axis_tx = 16, xcd_remap = 1, zspec = 1, yreg = 0, fit_shapes = 1;
   GraphRec* rec = nullptr;             // launched directly
   size_t part_len = 0;                 // the projection has no reductions
   double* part0 = nullptr;
@@ -2418,6 +2424,7 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     s->xcd_remap = envi("PFF_XCD_REMAP", 1) != 0 ? 1 : 0;
     s->zspec = envi("PFF_ZSPEC", 1) != 0 ? 1 : 0;
     s->yreg = std::min(3, std::max(0, envi("PFF_YREG", 1)));
+    s->fit_shapes = envi("PFF_FIT_SHAPES", 1) != 0 ? 1 : 0;
     s->fused = std::min(2, std::max(0, envi("PFF_FUSED", 1)));
     if (s->var_het) s->fused = std::min(s->fused, 1);   // the variational term needs the input before the pass
     {

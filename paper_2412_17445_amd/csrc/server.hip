@@ -124,6 +124,7 @@ void run_request(pff_server* S, Request* r, hipStream_t st) {
     return;
   }
   try {
+    pff::serving_shapes(s);
     pff::kbatcher_attach(s, S->kb);
   } catch (const std::exception& e) {
     pff_destroy(s);

@@ -137,7 +137,7 @@ def test_admission_respects_the_memory_budget():
 
 
 @pytest.mark.gpu
-def test_batched_inner_solves_equal_the_solver_alone():
+def test_batched_inner_solves_equal_the_solver_alone(monkeypatch):
     """The server batches the FP32 inner solves of requests on the same grid
     (one launch sequence per chunk of BiCGSTAB iterations for the whole
     group, replayed from a captured graph).  Each request's increments are
@@ -158,6 +158,10 @@ def test_batched_inner_solves_equal_the_solver_alone():
     assert st["batch_max"] >= 2, st                # solves of one grid shared chunks
     served = [srv.results(tk) for tk in tickets]
     srv.close()
+    # the server's solvers keep the fixed launch shapes (the per-block
+    # partial sums, and so the rounding of the inner products, follow the
+    # launch shape): the solver alone takes the same
+    monkeypatch.setenv("PFF_FIT_SHAPES", "0")
     for (p, n), res in zip(reqs, served):
         s = Solver.from_problem(p, precision="mixed")
         s.bootstrap()
