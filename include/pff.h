@@ -177,6 +177,25 @@ typedef struct {
 
 int pff_abi_version(void);
 
+/* Environment read by pff_create (tuning and measurement; the defaults are
+ * the measured best on MI355X; none changes the equations solved or the
+ * tolerances the results are held to, only launch shapes, fusion and the
+ * path of the iterations):
+ *   PFF_TRACE=1|2         per-Newton-iteration log (2: also the first BiCGSTAB scalars)
+ *   PFF_FUSED=0|1|2       BiCGSTAB steps fused into the applies: 1 (default) the
+ *                         inner products in the epilogues, 2 also the FP32 p / s
+ *                         updates in the prologues (FP64 solves keep 1)
+ *   PFF_INNER32=r         mixed precision: FP32 inner-solve tolerance (default 5e-2)
+ *   PFF_ZSPEC=0|1         z pass with register-resident end stages (lengths 32/64/128)
+ *   PFF_YREG=0|1|2|3      FP32 3D y passes with register-resident end stages,
+ *                         tiles of 16 / 32 / 64 columns (0: LDS Stockham pass)
+ *   PFF_FIT_SHAPES=0|1    launch shapes sized to the grid (solvers of a request
+ *                         server keep the fixed shapes)
+ *   PFF_X_ROWS, PFF_SPEC_TX, PFF_SPEC_THREADS, PFF_AXIS_TX, PFF_AXIS_THREADS,
+ *   PFF_XCD_REMAP         launch knobs of the FFT passes
+ * and by pff_server_create: PFF_SERVER_BATCH, PFF_BATCH_CHUNK, PFF_BATCH_MAX,
+ * PFF_BATCH_GRAPH (see the request server below). */
+
 /* Create a solver.  phase_id: N bytes (host) with values < n_phases;
  * crack_mask: N bytes (host, 1 = initial crack, phi = 1 there) or NULL;
  * allocator: device memory hook (copied; NULL = hipMalloc), every device
