@@ -191,6 +191,7 @@ int pff_abi_version(void);
  *                         tiles of 16 / 32 / 64 columns (0: LDS Stockham pass)
  *   PFF_FIT_SHAPES=0|1    launch shapes sized to the grid (solvers of a request
  *                         server keep the fixed shapes)
+ *   PFF_SUBSTEPS=d        sub-increments of a failing increment (see pff_step)
  *   PFF_X_ROWS, PFF_SPEC_TX, PFF_SPEC_THREADS, PFF_AXIS_TX, PFF_AXIS_THREADS,
  *   PFF_XCD_REMAP         launch knobs of the FFT passes
  * and by pff_server_create: PFF_SERVER_BATCH, PFF_BATCH_CHUNK, PFF_BATCH_MAX,
@@ -216,8 +217,15 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
  * Outputs (host, may be NULL): a0, E_s. */
 pff_status pff_bootstrap(pff_solver* s, double* a0, double* E_s);
 
-/* One crack-length increment (Algorithm 2).  On PFF_NOT_CONVERGED the state
- * is rolled back to the last converged increment. */
+/* One crack-length increment (Algorithm 2): the control value rises by
+ * delta_a.  If Newton does not converge (after increment 1), the increment is
+ * retried as two half increments from the committed state, recursively down
+ * to delta_a / 8 (env PFF_SUBSTEPS = maximum depth, default 3; 0: off); each
+ * converged part commits its history, and out reports the final state with
+ * the iteration counts of every attempt.  With sub-increments on, a Newton
+ * solve whose update measure has not halved its best value for 12 iterations
+ * stops early.  On PFF_NOT_CONVERGED the state is rolled back to the last
+ * converged increment. */
 pff_status pff_step(pff_solver* s, pff_increment_result* out);
 
 /* Strain-controlled implicit staggered scheme (Sec. 3.1, Algorithm 1): the

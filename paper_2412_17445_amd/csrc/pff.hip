@@ -181,6 +181,7 @@ struct pff_solver {
   int xcd_remap = 1;        // z pass: consecutive tiles on one XCD (env PFF_XCD_REMAP)
   int zspec = 1;            // z pass with register-resident end stages for nz = 32, 64, 128 (env PFF_ZSPEC)
   int fit_shapes = 1;       // launch shapes sized to the grid's block count (env PFF_FIT_SHAPES)
+  int max_substep_depth = 3;  // sub-increments of a failing increment, down to delta_a / 2^depth (env PFF_SUBSTEPS)
   int yreg = 1;             // FP32 y passes with register-resident end stages (env PFF_YREG: 0 off,
                             // 1 / 2 / 3 tiles of 16 / 32 / 64 columns)
   int fused = 1;            // BiCGSTAB steps fused into the applies (env PFF_FUSED): 0 none,
@@ -2425,6 +2426,7 @@ pff_status pff_create(const pff_grid* grid, const pff_phase* phases, int n_phase
     s->zspec = envi("PFF_ZSPEC", 1) != 0 ? 1 : 0;
     s->yreg = std::min(3, std::max(0, envi("PFF_YREG", 1)));
     s->fit_shapes = envi("PFF_FIT_SHAPES", 1) != 0 ? 1 : 0;
+    s->max_substep_depth = std::min(8, std::max(0, envi("PFF_SUBSTEPS", 3)));
     s->fused = std::min(2, std::max(0, envi("PFF_FUSED", 1)));
     if (s->var_het) s->fused = std::min(s->fused, 1);   // the variational term needs the input before the pass
     {
@@ -2562,12 +2564,15 @@ pff_status pff_bootstrap(pff_solver* s, double* a0, double* E_s) {
   });
 }
 
-pff_status pff_step(pff_solver* s, pff_increment_result* out) {
-  return guarded(s, [&]() -> pff_status {
+// One Newton solve of the increment from the committed state to the target
+// a + delta (paper Algorithm 2); commits on convergence (count_inc: the
+// increment counter advances), rolls back otherwise.
+static pff_status step_once(pff_solver* s, double delta, bool count_inc, pff_increment_result* out) {
+  {
     if (!s->bootstrapped) throw Fail("pff_step before pff_bootstrap/pff_set_state", PFF_ERR_STATE);
     const auto t0 = std::chrono::steady_clock::now();
     const long long ap0 = s->applies, ki0 = s->kiters;
-    const double a_new = s->a + s->prm.delta_a;
+    const double a_new = s->a + delta;
     const long long N = s->N;
     const int C = s->C;
     // Newton start
@@ -2584,7 +2589,8 @@ pff_status pff_step(pff_solver* s, pff_increment_result* out) {
       s->hstage[0] = s->E;
       HC(hipMemcpyAsync(s->Edev, s->hstage, sizeof(double), hipMemcpyHostToDevice, s->stream));
     }
-    int conv = 0, it = 0;
+    int conv = 0, it = 0, stall = 0;
+    double best_e = HUGE_VAL;
     double err[3] = {0, 0, 0};
     double res[2] = {0, 0};
     const bool trace = s->trace;
@@ -2633,6 +2639,15 @@ pff_status pff_step(pff_solver* s, pff_increment_result* out) {
           break;
         }
         if (!std::isfinite(e)) break;
+        // with sub-increments to fall back on, a Newton solve whose update
+        // measure has not halved its best value for 12 iterations stops early
+        // (the cycles of a failing increment repeat every few iterations)
+        if (e < 0.5 * best_e) {
+          best_e = e;
+          stall = 0;
+        } else if (++stall >= 12 && s->max_substep_depth > 0) {
+          break;
+        }
       }
     });
     if (it > s->prm.newton_maxit) it = s->prm.newton_maxit;
@@ -2670,7 +2685,7 @@ pff_status pff_step(pff_solver* s, pff_increment_result* out) {
     const double Ecur = s->hstage[0];
     s->E = Ecur;
     s->a = a_new;
-    s->n += 1;
+    if (count_inc) s->n += 1;
     s->ts_valid = false;
     if (out) {
       for (int q = 0; q < 6; ++q) out->sigma_M[q] = s->hscal[SC_SIG + q] / double(N);
@@ -2680,6 +2695,99 @@ pff_status pff_step(pff_solver* s, pff_increment_result* out) {
       out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return PFF_OK;
+  }
+}
+
+// Sub-increments: an increment whose Newton does not converge is retried as
+// two half increments from the committed state, recursively down to
+// delta_a / 2^max_depth (env PFF_SUBSTEPS, default 3; 0: off); each converged
+// half commits its history, the last one advances the increment counter.
+// (The paper takes fixed increments and notes that relaxation alpha < 1
+// sometimes helps near developed cracks; on the 256^2 fibre composite the
+// 62nd increment of delta_a = 2 cycles between four Newton iterates at any
+// alpha in [0.5, 1], and two increments of 1 converge.)
+namespace {
+
+void add_counts(pff_increment_result& agg, const pff_increment_result& r) {
+  agg.newton_iters += r.newton_iters;
+  agg.krylov_iters += r.krylov_iters;
+  agg.applies += r.applies;
+  agg.applies_fp64 += r.applies_fp64;
+  agg.fp64_fallbacks += r.fp64_fallbacks;
+  agg.refinements += r.refinements;
+}
+
+bool substeps(pff_solver* s, double delta, int depth, bool last, pff_increment_result& agg,
+              pff_increment_result& fin) {
+  for (int h = 0; h < 2; ++h) {
+    const bool final_half = last && h == 1;
+    pff_increment_result r{};
+    const pff_status st = step_once(s, 0.5 * delta, final_half, &r);
+    add_counts(agg, r);
+    if (st == PFF_OK) {
+      if (final_half) fin = r;
+      continue;
+    }
+    if (depth >= s->max_substep_depth) return false;
+    if (!substeps(s, 0.5 * delta, depth + 1, final_half, agg, fin)) return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+pff_status pff_step(pff_solver* s, pff_increment_result* out) {
+  return guarded(s, [&]() -> pff_status {
+    const auto t0 = std::chrono::steady_clock::now();
+    pff_increment_result first{};
+    const pff_status st = step_once(s, s->prm.delta_a, true, &first);
+    if (st == PFF_OK || s->max_substep_depth <= 0 || s->n == 0) {
+      if (out) *out = first;
+      return st;
+    }
+    // keep the committed state on the host, to restore it if the
+    // sub-increments fail too (the contract of PFF_NOT_CONVERGED)
+    const long long N = s->N;
+    const int C = s->C;
+    std::vector<double> eps(C * N), phi(N), Hn(N);
+    HC(hipStreamSynchronize(s->stream));
+    HC(hipMemcpy(eps.data(), s->eps_c, C * N * sizeof(double), hipMemcpyDeviceToHost));
+    HC(hipMemcpy(phi.data(), s->phi_c, N * sizeof(double), hipMemcpyDeviceToHost));
+    HC(hipMemcpy(Hn.data(), s->Hn, N * sizeof(double), hipMemcpyDeviceToHost));
+    const double E0 = s->E, a0 = s->a;
+    const int n0 = s->n;
+    pff_increment_result agg = first, fin{};
+    if (substeps(s, s->prm.delta_a, 1, true, agg, fin)) {
+      fin.newton_iters = agg.newton_iters;
+      fin.krylov_iters = agg.krylov_iters;
+      fin.applies = agg.applies;
+      fin.applies_fp64 = agg.applies_fp64;
+      fin.fp64_fallbacks = agg.fp64_fallbacks;
+      fin.refinements = agg.refinements;
+      fin.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (out) *out = fin;
+      return PFF_OK;
+    }
+    HC(hipMemcpy(s->eps_c, eps.data(), C * N * sizeof(double), hipMemcpyHostToDevice));
+    HC(hipMemcpy(s->eps_t, eps.data(), C * N * sizeof(double), hipMemcpyHostToDevice));
+    HC(hipMemcpy(s->phi_c, phi.data(), N * sizeof(double), hipMemcpyHostToDevice));
+    HC(hipMemcpy(s->phi, phi.data(), N * sizeof(double), hipMemcpyHostToDevice));
+    HC(hipMemcpy(s->Hn, Hn.data(), N * sizeof(double), hipMemcpyHostToDevice));
+    double e2[2] = {E0, E0};
+    HC(hipMemcpy(s->Edev, e2, 2 * sizeof(double), hipMemcpyHostToDevice));
+    s->E = E0;
+    s->a = a0;
+    s->n = n0;
+    s->ts_valid = false;
+    if (out) {
+      *out = first;
+      out->newton_iters = agg.newton_iters;
+      out->krylov_iters = agg.krylov_iters;
+      out->applies = agg.applies;
+      out->applies_fp64 = agg.applies_fp64;
+      out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return PFF_NOT_CONVERGED;
   });
 }
 
