@@ -439,6 +439,54 @@ def serve_stream(args):
                      else "a reduced served stream (smoke run of the serving path)")}
 
 
+def fullrun_mode(prob, args):
+    """The mixed-precision and the plain FP64 GPU solver over the workload's
+    whole configured path (bootstrap and every increment): time per run and
+    the largest relative difference per quantity over the increments."""
+    import copy
+
+    import numpy as np
+    import torch
+
+    from paper_2412_17445_amd import Solver
+
+    n = prob.n_increments
+    runs = {}
+    for prec in ("mixed", "fp64"):
+        p = copy.copy(prob)
+        p.precision = prec
+        s = Solver.from_problem(p)
+        s.bootstrap()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rows = []
+        for k in range(n):
+            o = s.step()
+            if not o["converged"]:
+                log(f"{prec}: increment {k + 1} did not converge")
+                break
+            _, phi, _, _, _ = s.get_state()
+            rows.append((o["E"], o["Gamma"], np.array(o["sigma_M"]), float(np.linalg.norm(phi)),
+                         o["newton_iters"], o["krylov_iters"]))
+            if (k + 1) % 10 == 0:
+                log(f"{prec}: increment {k + 1}, {time.perf_counter() - t0:.1f}s")
+        torch.cuda.synchronize()
+        runs[prec] = (rows, time.perf_counter() - t0)
+        s.close()
+    (m, tm), (f, tf) = runs["mixed"], runs["fp64"]
+    worst = {"E": 0.0, "Gamma": 0.0, "sigma_M": 0.0, "phi_norm": 0.0}
+    for a, b in zip(m, f):
+        worst["E"] = max(worst["E"], abs(a[0] - b[0]) / abs(b[0]))
+        worst["Gamma"] = max(worst["Gamma"], abs(a[1] - b[1]) / abs(b[1]))
+        worst["sigma_M"] = max(worst["sigma_M"], float(np.abs(a[2] - b[2]).max() / np.abs(b[2]).max()))
+        worst["phi_norm"] = max(worst["phi_norm"], abs(a[3] - b[3]) / b[3])
+    print(json.dumps({"mode": "fullrun", "workload": prob.name, "increments_configured": n,
+                      "increments_mixed": len(m), "increments_fp64": len(f),
+                      "seconds_mixed": round(tm, 2), "seconds_fp64": round(tf, 2),
+                      "newton_mixed": sum(r[4] for r in m), "newton_fp64": sum(r[4] for r in f),
+                      "max_rel_diff": {k: float("%.3e" % v) for k, v in worst.items()}}), flush=True)
+
+
 def apply_mode(prob, args):
     """Tangent applies on a frozen synthetic state (for counter runs)."""
     import numpy as np
@@ -474,10 +522,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-every", type=int, default=7,
                     help="sample every n-th apply (odd: the fused applies alternate modes)")
-    ap.add_argument("--mode", default="solve", choices=["solve", "apply", "copy", "serve"],
+    ap.add_argument("--mode", default="solve", choices=["solve", "apply", "copy", "serve", "fullrun"],
                     help="solve: timed increments (default); apply: tangent applies on a frozen "
                          "state (profiling counters); copy: plain device copy of 256 MiB "
-                         "(counter calibration)")
+                         "(counter calibration); serve: the served request stream; fullrun: the "
+                         "mixed and the plain FP64 solver over the workload's whole path")
     ap.add_argument("--applies", type=int, default=20)
     ap.add_argument("--no-compare", action="store_true",
                     help="mixed workloads: skip the plain-FP64 solve of the same increments")
@@ -529,6 +578,9 @@ def main():
         prob.precision = args.precision
     if args.mode == "apply":
         apply_mode(prob, args)
+        return
+    if args.mode == "fullrun":
+        fullrun_mode(prob, args)
         return
     log(f"workload {args.workload} {prob.shape[::-1]} {prob.precision}")
     s = Solver.from_problem(prob)
