@@ -203,3 +203,19 @@ def test_standard_projection_of_real_field_with_nyquist_content_is_real():
     # modes whose non-zero indices are all Nyquist indices have xi = 0 and
     # are projected to 0, like the DC mode
     assert zero[0, 0, 4] and zero[2, 3, 4] and not zero[0, 1, 4]
+
+
+def test_fft_bits_do_not_depend_on_the_thread_count(monkeypatch):
+    """The library FFT splits independent lines over its threads, so the
+    oracle's transforms and projection give the same bits for any
+    FFT_WORKERS (the full-size goldens are written with several threads,
+    the small ones with one)."""
+    rng = np.random.default_rng(7)
+    a = rng.standard_normal((3, 3, 6, 10, 12)) + 1j * rng.standard_normal((3, 3, 6, 10, 12))
+    A = rng.standard_normal((3, 3, 6, 10, 12))
+    A = A + A.transpose(1, 0, 2, 3, 4)
+    monkeypatch.setattr(fo, "FFT_WORKERS", 1)
+    f1, i1, g1 = fo.fftn(a), fo.ifftn(a), fo.G_tensor(A)
+    monkeypatch.setattr(fo, "FFT_WORKERS", 4)
+    f4, i4, g4 = fo.fftn(a), fo.ifftn(a), fo.G_tensor(A)
+    assert np.array_equal(f1, f4) and np.array_equal(i1, i4) and np.array_equal(g1, g4)
