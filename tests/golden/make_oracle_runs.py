@@ -34,8 +34,13 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
+from oracle import fourier  # noqa: E402
 from oracle.newton import Solver  # noqa: E402
 from synth import problem_config  # noqa: E402
+
+# FFT threads of the oracle (the transforms of independent lines are split
+# over the threads; the result does not depend on their number)
+fourier.FFT_WORKERS = int(os.environ.get("ORACLE_FFT_WORKERS", "1"))
 
 RESID_TOL = 1e-11
 N_RANDOM_SAMPLES = 40      # damage sampled at seeded voxels ...
@@ -46,7 +51,7 @@ CASES = {"tiny16": 4, "gc16": 4, "fib64": 4, "pore24": 3, "part24": 3, "crack2d_
          "crack2d_39": 4, "pore35": 1, "gc16_d": 4, "gc16_v": 4, "tiny16_v": 4,
          "gc16_m": 4, "tiny16_m": 4, "part12": 3, "part12_m": 3, "part24_m": 3,
          # full-size workloads (inexact Newton, see KRYLOV_RTOL)
-         "fibres2d_256": 5, "pores3d_64": 3, "particles3d_128": 1}
+         "fibres2d_256": 20, "pores3d_64": 3, "particles3d_128": 1}
 
 # Krylov tolerance of the oracle's Newton steps where it differs from the
 # problem's own (1e-10): loose inner solves for the full-size workloads
