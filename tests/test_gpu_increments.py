@@ -121,7 +121,7 @@ def test_fp64_increments_match_oracle(case):
     s.close()
 
 
-MIXED_CASES = [("tiny16", 1e-10), ("crack2d_64", 1e-6), ("gc16", 1e-6), ("fib64", 1e-6), ("pore24", 1e-6), ("part24", 1e-5),
+MIXED_CASES = [("tiny16", 1e-10), ("tiny16_v", 1e-10), ("tiny16_m", 1e-10), ("crack2d_64", 1e-6), ("gc16", 1e-6), ("fib64", 1e-6), ("pore24", 1e-6), ("part24", 1e-5),
                ("gc16_iso", 1e-6), ("part24_iso", 1e-5), ("gc16_std", 1e-6), ("gc16_w", 1e-6),
                ("crack2d_39", 1e-6), ("pore35", 1e-6), ("gc16_d", 1e-6), ("gc16_v", 1e-6),
                ("gc16_m", 1e-6), ("part12", 1e-5), ("part12_m", 1e-5), ("part24_m", 1e-5),
